@@ -1,0 +1,268 @@
+/*
+ * sel.h -- C ABI of libsel, exact selectivity by a COUNT scan (gfx950).
+ *
+ * The method (Shin 2018, "Novel Selectivity Estimation Strategy for Modern
+ * DBMS", Ch.3 sec.3.1 "Selectivity Computation") replaces a cardinality
+ * estimate of a pushed-down selection sigma(R) by the exact answer of
+ * SELECT COUNT(*) FROM R WHERE <R's predicates>, run on the in-memory GPU
+ * executor while the query is still being optimised.  If the count is at
+ * most a limit (Algorithm 1, function Execute: the count is compared with
+ * maxSize and an exception aborts the push-down when it is larger), sigma(R)
+ * is materialised at once while R's columns are resident (Ch.3 sec.3.3
+ * "Materialization").  This header exposes exactly that path:
+ *
+ *   sel_count               exact COUNT(*) of rows whose predicate is TRUE
+ *   sel_pushdown_rowids     count, limit check, then ascending row ids
+ *   sel_pushdown_keybitmap  count + dimension-key bitmap (push-down on a
+ *                           non-probe relation, Ch.3 sec.3.3 / Algorithm 1)
+ *   sel_star_count          exact fact-table count of a star semi-join over
+ *                           such key bitmaps
+ *
+ * Conventions
+ *  - Every function returns sel_status; nothing throws across the ABI.
+ *    Negative = error (nothing was computed or written unless stated),
+ *    positive = a non-error outcome (SEL_OVER_LIMIT, SEL_E_CAPACITY), for
+ *    which *out_count is still valid.
+ *  - Column data, validity bitmaps and every output buffer named d_* are
+ *    DEVICE pointers owned by the caller (BORROWED: the caller keeps them
+ *    alive while a table / program / call uses them).  Pointers named h_* or
+ *    out_* without the d_ prefix are host pointers.
+ *  - Column data must be 16-byte aligned; validity bitmaps 4-byte aligned.
+ *  - Synchronous calls return after results are on the host.  *_async
+ *    calls only enqueue work on the context's stream.
+ *  - A context is used by one host thread at a time.
+ *  - Rows are numbered 0..nrows-1; nrows < 2^32 (row ids are uint32).
+ *
+ * Truth values follow SQL three-valued (Kleene) logic: a comparison on a
+ * NULL value is UNKNOWN, AND = min and OR = max over FALSE < UNKNOWN < TRUE,
+ * NOT swaps TRUE and FALSE, and WHERE keeps only TRUE rows.
+ */
+#ifndef SEL_H
+#define SEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sel_status {
+  SEL_OK = 0,
+  SEL_OVER_LIMIT = 1,  /* count > max_rows: nothing materialised (Algorithm 1:
+                          Execute throws, EvaluateAndPushDown reverts) */
+  SEL_E_CAPACITY = 2,  /* count > caller's output capacity: nothing written */
+  SEL_E_INVALID = -1,  /* bad handle, argument or program; found before any
+                          device work was enqueued */
+  SEL_E_TYPE = -2,     /* operation not valid for the column's type */
+  SEL_E_NOMEM = -3,    /* device or host allocation failed */
+  SEL_E_DEVICE = -4,   /* HIP runtime error; sel_last_error() has its text */
+  SEL_E_BUSY = -5,     /* admission refused (server memory budget) */
+  SEL_E_RANGE = -6     /* a qualifying key fell outside the key-bitmap range */
+} sel_status;
+
+/* Column element types.  Values are signed and compared after sign extension
+ * to int64.  TEXT columns are dictionary codes (int32 in [0, dict_card)),
+ * DECIMAL(p,2) columns are int64 scaled by 100 and DATE columns are int32
+ * day numbers: the thesis' TPC-H predicates on INTEGER, TEXT, DECIMAL(15,2)
+ * and DATE attributes (Ch.5 sec.5.2) all become integer tests. */
+typedef enum sel_type { SEL_I8 = 1, SEL_I16 = 2, SEL_I32 = 3, SEL_I64 = 4 } sel_type;
+
+typedef struct sel_column {
+  int32_t type;            /* sel_type */
+  uint32_t dict_card;      /* > 0: dictionary-coded, codes in [0, dict_card) */
+  const void* data;        /* device, nrows elements, 16-byte aligned, BORROWED */
+  const uint32_t* valid;   /* device, ceil(nrows/32) words; bit (i%32) of word
+                              i/32 is 1 iff row i is not NULL.  NULL pointer =
+                              the column has no NULLs.  BORROWED. */
+} sel_column;
+
+/* Predicate program: postfix (reverse Polish) code.  Leaves push one truth
+ * value, NOT / IS_UNKNOWN pop one and push one, AND / OR pop two and push
+ * one; the program must leave exactly one value.  These are the selection
+ * predicates of the count query of Ch.3 sec.3.1 (conjunctions of =, <, >,
+ * BETWEEN and OR-groups) plus IN-lists, pre-resolved LIKE (a set of
+ * dictionary codes) and NULL tests. */
+typedef enum sel_op {
+  SEL_OP_EQ = 1,          /* col = a                                         */
+  SEL_OP_NE = 2,          /* col <> a                                        */
+  SEL_OP_LT = 3,          /* col < a                                         */
+  SEL_OP_LE = 4,          /* col <= a                                        */
+  SEL_OP_GT = 5,          /* col > a                                         */
+  SEL_OP_GE = 6,          /* col >= a                                        */
+  SEL_OP_BETWEEN = 7,     /* a <= col <= b (a > b: FALSE for non-NULL rows)  */
+  SEL_OP_IN = 8,          /* col IN (list): aux = pool byte offset (8-aligned)
+                             of b int64 values, b >= 1, any order, duplicates
+                             allowed                                         */
+  SEL_OP_CODESET = 9,     /* 0 <= col < b and bit col of the set: aux = pool
+                             byte offset (4-aligned) of ceil(b/32) uint32
+                             words, bit c = word c/32 bit c%32; b <= 2^24.
+                             A LIKE pattern on a dictionary column resolved
+                             to the codes it matches.                        */
+  SEL_OP_IS_NULL = 10,    /* never UNKNOWN                                   */
+  SEL_OP_IS_NOT_NULL = 11,/* never UNKNOWN                                   */
+  SEL_OP_AND = 16,
+  SEL_OP_OR = 17,
+  SEL_OP_NOT = 18,
+  SEL_OP_IS_UNKNOWN = 19, /* (p) IS UNKNOWN: TRUE iff p is UNKNOWN           */
+  SEL_OP_TRUE = 20,
+  SEL_OP_FALSE = 21
+} sel_op;
+
+typedef struct sel_instr {   /* 24 bytes */
+  uint16_t op;               /* sel_op */
+  uint16_t col;              /* column index for leaves, else 0 */
+  uint32_t aux;              /* pool byte offset for IN / CODESET */
+  int64_t a;
+  int64_t b;
+} sel_instr;
+
+#define SEL_MAX_INSTRS 64         /* postfix length                       */
+#define SEL_MAX_DEPTH 8           /* evaluation stack after operand reordering */
+#define SEL_MAX_POOL_BYTES 65536  /* constant pool                         */
+#define SEL_MAX_COLUMNS 64
+
+typedef struct sel_ctx sel_ctx;
+typedef struct sel_table sel_table;
+typedef struct sel_program sel_program;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * (for instance torch.cuda.current_stream().cuda_stream) on which every call
+ * enqueues its work; NULL makes the context create its own stream.
+ * Errors: SEL_E_INVALID (bad device / out NULL), SEL_E_DEVICE, SEL_E_NOMEM. */
+sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out);
+void sel_ctx_destroy(sel_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the next
+ * call on the same context.  ctx may be NULL (errors of sel_ctx_create). */
+const char* sel_last_error(const sel_ctx* ctx);
+
+/* Number of compute units of the context's device (for launch sizing). */
+uint32_t sel_ctx_num_cus(const sel_ctx* ctx);
+
+/* ---- tables ----------------------------------------------------------- */
+
+/* Describe a resident columnar table of `nrows` rows and `ncols` columns.
+ * The descriptor array is copied; the device buffers it names are borrowed.
+ * Errors: SEL_E_INVALID (nrows >= 2^32, ncols 0 or > SEL_MAX_COLUMNS,
+ * unknown type, NULL data with nrows > 0, misaligned data). */
+sel_status sel_table_create(sel_ctx* ctx, uint64_t nrows, uint32_t ncols,
+                            const sel_column* cols, sel_table** out);
+void sel_table_destroy(sel_table* t);  /* never frees borrowed buffers */
+uint64_t sel_table_nrows(const sel_table* t);
+
+/* ---- predicate programs ------------------------------------------------ */
+
+/* Validate postfix `code[0..n)` against `table` and compile it to the device
+ * form: comparisons become closed integer ranges clamped to the column type,
+ * IN-lists are sorted and deduplicated and dense ones become bitmaps,
+ * operands of AND/OR may be reordered to bound the stack depth (Kleene AND
+ * and OR are commutative, so the truth value of every row is unchanged).
+ * `pool` (host, `pool_bytes` bytes) holds IN values and code bitmaps; it is
+ * copied.  The program owns a device copy and is bound to `table`.
+ * Errors: SEL_E_INVALID (unknown op, column index out of range, stack
+ * underflow / overflow, final depth != 1, pool offset out of bounds or
+ * misaligned, n == 0 or n > SEL_MAX_INSTRS, IN with b < 1),
+ * SEL_E_TYPE (CODESET on a column that is not dictionary-coded),
+ * SEL_E_NOMEM / SEL_E_DEVICE. */
+sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table,
+                               const sel_instr* code, uint32_t n,
+                               const void* pool, uint32_t pool_bytes,
+                               sel_program** out);
+void sel_program_destroy(sel_program* p);
+
+/* ---- the count query (Ch.3 sec.3.1) ------------------------------------ */
+
+/* Exact number of rows of `table` for which `prog` is TRUE.
+ * Errors: SEL_E_INVALID (NULL handle, program bound to another table),
+ * SEL_E_DEVICE. */
+sel_status sel_count(sel_ctx* ctx, const sel_table* table,
+                     const sel_program* prog, uint64_t* out_count);
+
+/* Same count, enqueued only: the result is written to *d_count (device,
+ * 8 bytes) when the context's stream reaches it. */
+sel_status sel_count_async(sel_ctx* ctx, const sel_table* table,
+                           const sel_program* prog, uint64_t* d_count);
+
+/* ---- push-down with materialisation (Algorithm 1, Ch.3 sec.3.3) --------- */
+
+/* floor(nrows * ratio) for ratio in [0, 1]: Algorithm 1's maxSize for the
+ * PUSH_DOWN_MAX_SELECTIVITY ratio.  For an integer count c, c > nrows*ratio
+ * iff c > floor(nrows*ratio).  ratio outside [0,1] is clamped. */
+uint64_t sel_max_rows(uint64_t nrows, double ratio);
+
+/* Count the qualifying rows; if count > max_rows return SEL_OVER_LIMIT and
+ * write nothing (the thesis throws and reverts the push-down).  If count >
+ * cap return SEL_E_CAPACITY and write nothing.  Otherwise write the count
+ * qualifying row ids in ascending order to d_out[0..count) (device, caller
+ * owned) and return SEL_OK.  *out_count is set for every status >= 0.
+ * max_rows = UINT64_MAX disables the limit. */
+sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table,
+                               const sel_program* prog, uint64_t max_rows,
+                               uint32_t* d_out, uint64_t cap,
+                               uint64_t* out_count);
+
+/* Push the selection down on a dimension relation: zero d_bitmap[0 ..
+ * ceil(nbits/32)) and set bit (key - key_min) for every row whose predicate
+ * is TRUE, where key is column `key_col` (an int32 or int64 column without
+ * NULLs).  *out_count = number of qualifying rows.  A qualifying key outside
+ * [key_min, key_min + nbits) gives SEL_E_RANGE (bitmap contents then
+ * unspecified).  prog may be NULL (every row qualifies).  Keys are expected
+ * unique (a primary key); duplicates set the same bit. */
+sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim,
+                                  uint32_t key_col, int64_t key_min,
+                                  const sel_program* prog, uint32_t* d_bitmap,
+                                  uint64_t nbits, uint64_t* out_count);
+
+/* Exact star semi-join count: the number of fact rows i such that for every
+ * d < nfk, 0 <= fk_d[i] < nbits[d] and bit fk_d[i] of d_bitmaps[d] is set,
+ * and (fact_pred == NULL or fact_pred is TRUE on row i).  fk columns are
+ * int32 or int64 columns of `fact`; a NULL foreign key never matches.  With
+ * unique dimension keys this equals the cardinality of the FK-PK star join
+ * of the fact table with the pushed-down dimensions.  nfk in 1..8.
+ * d_bitmaps is a host array of nfk device pointers; nbits a host array. */
+sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact,
+                          const sel_program* fact_pred, uint32_t nfk,
+                          const uint32_t* fk_cols,
+                          const uint32_t* const* d_bitmaps,
+                          const uint64_t* nbits, uint64_t* out_count);
+
+/* ---- launch configuration and timing ------------------------------------ */
+
+typedef struct sel_launch {
+  uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  uint32_t grid;         /* workgroups; 0 = library default                   */
+} sel_launch;
+
+/* Override (or with NULL, restore) the launch shape used by the scan kernels
+ * of this context.  Errors: SEL_E_INVALID for an unsupported block size. */
+sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch);
+
+/* Kernel timing: when enabled, the library brackets each scan-kernel launch
+ * with HIP events on the context's stream and accumulates the elapsed time
+ * per kernel kind.  Reading the totals synchronises the stream. */
+typedef enum sel_kernel_kind {
+  SEL_K_COUNT = 0,       /* fused evaluate + count                      */
+  SEL_K_MASK = 1,        /* evaluate + count + result mask + tile counts */
+  SEL_K_SCAN = 2,        /* exclusive scan of tile counts               */
+  SEL_K_COMPACT = 3,     /* mask -> ascending row ids                   */
+  SEL_K_KEYBITMAP = 4,   /* dimension key bitmap build                  */
+  SEL_K_STAR = 5,        /* star semi-join probe count                  */
+  SEL_K_BATCH = 6,       /* persistent batched count                    */
+  SEL_K_NKINDS = 7
+} sel_kernel_kind;
+
+typedef struct sel_timing {
+  double ms[SEL_K_NKINDS];         /* summed kernel time                  */
+  uint64_t launches[SEL_K_NKINDS]; /* number of timed launches            */
+} sel_timing;
+
+sel_status sel_ctx_enable_timing(sel_ctx* ctx, int enable);
+sel_status sel_ctx_read_timing(sel_ctx* ctx, sel_timing* out, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEL_H */
