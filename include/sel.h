@@ -173,6 +173,26 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table,
                                sel_program** out);
 void sel_program_destroy(sel_program* p);
 
+/* Validate and lower a program for a table described by `cols` without any
+ * device work (usable on a machine without a GPU; column data pointers may
+ * be NULL -- only type, dict_card and whether `valid` is NULL matter).  On
+ * success `text` receives a listing of the lowered program, one device
+ * instruction per line; on failure `err` receives the reason.  Either buffer
+ * may be NULL.  Returns the status sel_program_compile would return. */
+sel_status sel_program_check(uint64_t nrows, uint32_t ncols, const sel_column* cols,
+                             const sel_instr* code, uint32_t n, const void* pool,
+                             uint32_t pool_bytes, char* text, size_t text_len, char* err,
+                             size_t err_len);
+
+/* Listing of a compiled program (as sel_program_check prints it); owned by
+ * the program. */
+const char* sel_program_listing(const sel_program* p);
+
+/* Bytes per row the scan of this program reads from device memory: the
+ * element size of every column whose values it tests plus 1/8 for every
+ * column whose validity bitmap it reads (the algorithmic traffic). */
+double sel_program_bytes_per_row(const sel_program* p);
+
 /* ---- the count query (Ch.3 sec.3.1) ------------------------------------ */
 
 /* Exact number of rows of `table` for which `prog` is TRUE.
@@ -188,9 +208,10 @@ sel_status sel_count_async(sel_ctx* ctx, const sel_table* table,
 
 /* ---- push-down with materialisation (Algorithm 1, Ch.3 sec.3.3) --------- */
 
-/* floor(nrows * ratio) for ratio in [0, 1]: Algorithm 1's maxSize for the
- * PUSH_DOWN_MAX_SELECTIVITY ratio.  For an integer count c, c > nrows*ratio
- * iff c > floor(nrows*ratio).  ratio outside [0,1] is clamped. */
+/* floor(nrows * ratio), the product taken in double precision, for ratio in
+ * [0, 1]: Algorithm 1's maxSize = R.size * PUSH_DOWN_MAX_SELECTIVITY.  For an
+ * integer count c, c > nrows*ratio iff c > floor(nrows*ratio).  ratio
+ * outside [0,1] (or NaN) is clamped: <= 0 gives 0, >= 1 gives nrows. */
 uint64_t sel_max_rows(uint64_t nrows, double ratio);
 
 /* Count the qualifying rows; if count > max_rows return SEL_OVER_LIMIT and

@@ -1,0 +1,716 @@
+// api.cpp -- the C ABI of libsel (include/sel.h): contexts, tables,
+// programs, the count query and the push-down calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sel.h"
+#include "sel_device.h"
+#include "sel_internal.h"
+
+using namespace sel;
+
+namespace {
+thread_local std::string g_create_error;
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+}  // namespace
+
+struct sel_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint32_t num_cus = 0;
+  std::string err;
+
+  DevSlot* slot = nullptr;                 // device
+  unsigned long long* dout = nullptr;      // device, 2 values
+  unsigned long long* hout = nullptr;      // pinned host, 2 values
+  DevInstr* hstage = nullptr;              // pinned host staging for dstar
+  DevInstr* dstar = nullptr;               // device, star-count program (128)
+  DevInstr* dtrue = nullptr;               // device, the program TRUE
+  void* scratch = nullptr;                 // device, grow-only
+  size_t scratch_bytes = 0;
+
+  sel_launch launch{256, 0};
+  bool launch_fixed = false;
+  int occ[3] = {0, 0, 0};                  // blocks per CU per scan mode at 256 threads
+
+  bool timing = false;
+  std::vector<EventPair> free_events;
+  std::vector<std::pair<int, EventPair>> pending;
+  double ms[SEL_K_NKINDS] = {};
+  uint64_t launches[SEL_K_NKINDS] = {};
+};
+
+struct sel_table {
+  sel_ctx* ctx;
+  uint64_t nrows;
+  std::vector<sel_column> cols;
+};
+
+struct sel_program {
+  sel_ctx* ctx;
+  const sel_table* table;
+  void* dev = nullptr;              // one allocation: code then blob
+  DevInstr* dcode = nullptr;
+  std::vector<DevInstr> host_code;  // with device pointers (for star programs)
+  uint32_t nins = 0;
+  int depth = 0;
+  double bytes_per_row = 0.0;
+  std::string text;
+};
+
+namespace {
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) (void)hipSetDevice(dev);
+    dev_ = dev;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1, dev_ = 0;
+};
+
+sel_status set_err(sel_ctx* ctx, sel_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  else g_create_error = msg;
+  return st;
+}
+
+sel_status hip_err(sel_ctx* ctx, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return set_err(ctx, e == hipErrorOutOfMemory ? SEL_E_NOMEM : SEL_E_DEVICE, m);
+}
+
+#define HIP_TRY(ctx, call, where)                      \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_err(ctx, e_, where); \
+  } while (0)
+
+uint32_t dev_type(int32_t t) {
+  switch (t) {
+    case SEL_I8: return T_I8;
+    case SEL_I16: return T_I16;
+    case SEL_I32: return T_I32;
+    case SEL_I64: return T_I64;
+    default: return 0;
+  }
+}
+
+uint32_t type_bytes(uint32_t dt) {
+  switch (dt) {
+    case T_I8: return 1;
+    case T_I16: return 2;
+    case T_I32: return 4;
+    default: return 8;
+  }
+}
+
+sel_status ensure_scratch(sel_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->scratch_bytes) return SEL_OK;
+  if (ctx->scratch) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_bytes = 0;
+  }
+  size_t want = std::max(bytes, size_t(1) << 20);
+  HIP_TRY(ctx, hipMalloc(&ctx->scratch, want), "hipMalloc(scratch)");
+  ctx->scratch_bytes = want;
+  return SEL_OK;
+}
+
+EventPair take_events(sel_ctx* ctx) {
+  if (!ctx->free_events.empty()) {
+    EventPair p = ctx->free_events.back();
+    ctx->free_events.pop_back();
+    return p;
+  }
+  EventPair p{};
+  (void)hipEventCreate(&p.a);
+  (void)hipEventCreate(&p.b);
+  return p;
+}
+
+// Brackets one kernel launch with events when timing is on.
+struct TimedLaunch {
+  sel_ctx* ctx;
+  int kind;
+  EventPair ev{};
+  bool on;
+  TimedLaunch(sel_ctx* c, int k) : ctx(c), kind(k), on(c->timing) {
+    if (on) {
+      ev = take_events(ctx);
+      (void)hipEventRecord(ev.a, ctx->stream);
+    }
+  }
+  void done() {
+    if (on) {
+      (void)hipEventRecord(ev.b, ctx->stream);
+      ctx->pending.push_back({kind, ev});
+      on = false;
+    }
+  }
+};
+
+uint64_t ntiles_of(uint64_t nrows) { return (nrows + kTileRows - 1) / kTileRows; }
+
+// Launch shape of a scan over ntiles wave tiles.
+void scan_shape(sel_ctx* ctx, int mode, uint64_t ntiles, uint32_t& grid, uint32_t& block) {
+  block = ctx->launch.block;
+  const uint32_t wpb = block / kWave;
+  uint64_t need = (ntiles + wpb - 1) / wpb;
+  if (need == 0) need = 1;
+  uint64_t g;
+  if (ctx->launch.grid) {
+    g = ctx->launch.grid;
+  } else {
+    int occ = 0;
+    if (block == 256) {
+      occ = ctx->occ[mode];
+    } else if (sel_scan_occupancy(mode, block, &occ) != 0) {
+      occ = 1;
+    }
+    if (occ < 1) occ = 1;
+    g = (uint64_t)occ * ctx->num_cus;
+  }
+  grid = (uint32_t)std::min<uint64_t>(need, std::max<uint64_t>(g, 1));
+}
+
+bool check_prog(sel_ctx* ctx, const sel_table* t, const sel_program* p) {
+  if (!ctx || !t || !p) {
+    set_err(ctx, SEL_E_INVALID, "NULL handle");
+    return false;
+  }
+  if (p->table != t) {
+    set_err(ctx, SEL_E_INVALID, "program is bound to another table");
+    return false;
+  }
+  return true;
+}
+
+sel_status run_scan(sel_ctx* ctx, int mode, ScanArgs& a, int kind) {
+  uint32_t grid, block;
+  scan_shape(ctx, mode, a.ntiles, grid, block);
+  a.slot = ctx->slot;
+  TimedLaunch tl(ctx, kind);
+  int e = sel_launch_scan(mode, a, grid, block, ctx->stream);
+  tl.done();
+  if (e != 0) return hip_err(ctx, (hipError_t)e, "scan kernel launch");
+  return SEL_OK;
+}
+
+sel_status read_out(sel_ctx* ctx, uint64_t* v0, uint64_t* v1) {
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->hout, ctx->dout, 2 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, ctx->stream), "hipMemcpyAsync(count)");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  if (v0) *v0 = ctx->hout[0];
+  if (v1) *v1 = ctx->hout[1];
+  return SEL_OK;
+}
+
+std::vector<ColInfo> col_infos(const sel_column* cols, uint32_t ncols) {
+  std::vector<ColInfo> v(ncols);
+  for (uint32_t k = 0; k < ncols; ++k) {
+    v[k].type = dev_type(cols[k].type);
+    v[k].dict_card = cols[k].dict_card;
+    v[k].nullable = cols[k].valid != nullptr;
+    v[k].data = cols[k].data;
+    v[k].valid = cols[k].valid;
+  }
+  return v;
+}
+
+sel_status check_columns(sel_ctx* ctx, uint64_t nrows, uint32_t ncols, const sel_column* cols) {
+  if (nrows >= (1ull << 32)) return set_err(ctx, SEL_E_INVALID, "nrows must be < 2^32");
+  if (ncols == 0 || ncols > SEL_MAX_COLUMNS || cols == nullptr)
+    return set_err(ctx, SEL_E_INVALID, "ncols must be 1..64 with a descriptor array");
+  for (uint32_t k = 0; k < ncols; ++k) {
+    if (dev_type(cols[k].type) == 0)
+      return set_err(ctx, SEL_E_INVALID, "column " + std::to_string(k) + ": unknown type");
+    if (nrows > 0 && cols[k].data == nullptr)
+      return set_err(ctx, SEL_E_INVALID, "column " + std::to_string(k) + ": NULL data");
+    if (((uintptr_t)cols[k].data) % 16 != 0)
+      return set_err(ctx, SEL_E_INVALID, "column " + std::to_string(k) + ": data not 16-byte aligned");
+    if (((uintptr_t)cols[k].valid) % 4 != 0)
+      return set_err(ctx, SEL_E_INVALID, "column " + std::to_string(k) + ": validity not 4-byte aligned");
+  }
+  return SEL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ---------------------------------------------------------------- context --
+
+sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
+  if (!out) return set_err(nullptr, SEL_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return set_err(nullptr, SEL_E_DEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return set_err(nullptr, SEL_E_INVALID, "device index out of range");
+  sel_ctx* ctx = new (std::nothrow) sel_ctx();
+  if (!ctx) return set_err(nullptr, SEL_E_NOMEM, "host allocation failed");
+  ctx->device = device;
+  DeviceGuard g(device);
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
+    delete ctx;
+    return hip_err(nullptr, e, "hipGetDeviceProperties");
+  }
+  ctx->num_cus = (uint32_t)prop.multiProcessorCount;
+  if (hip_stream) {
+    ctx->stream = (hipStream_t)hip_stream;
+  } else {
+    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
+      delete ctx;
+      return hip_err(nullptr, e, "hipStreamCreate");
+    }
+    ctx->own_stream = true;
+  }
+  void* dmem = nullptr;
+  const size_t dbytes = 256 + 129 * sizeof(DevInstr);
+  if ((e = hipMalloc(&dmem, dbytes)) != hipSuccess || (e = hipMemset(dmem, 0, dbytes)) != hipSuccess) {
+    if (dmem) (void)hipFree(dmem);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return hip_err(nullptr, e, "hipMalloc(ctx)");
+  }
+  ctx->slot = (DevSlot*)dmem;
+  ctx->dout = (unsigned long long*)((char*)dmem + 128);
+  ctx->dstar = (DevInstr*)((char*)dmem + 256);
+  ctx->dtrue = ctx->dstar + 128;
+  if ((e = hipHostMalloc((void**)&ctx->hout, 64 + 128 * sizeof(DevInstr), hipHostMallocDefault)) != hipSuccess) {
+    (void)hipFree(dmem);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return hip_err(nullptr, e, "hipHostMalloc");
+  }
+  ctx->hstage = (DevInstr*)((char*)ctx->hout + 64);
+  {
+    DevInstr t{};
+    t.op = D_TRUE;
+    if ((e = hipMemcpy(ctx->dtrue, &t, sizeof t, hipMemcpyHostToDevice)) != hipSuccess) {
+      (void)hipHostFree(ctx->hout);
+      (void)hipFree(dmem);
+      if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+      delete ctx;
+      return hip_err(nullptr, e, "hipMemcpy(ctx)");
+    }
+  }
+  for (int m = 0; m < 3; ++m)
+    if (sel_scan_occupancy(m, 256, &ctx->occ[m]) != 0 || ctx->occ[m] < 1) ctx->occ[m] = 1;
+  *out = ctx;
+  return SEL_OK;
+}
+
+void sel_ctx_destroy(sel_ctx* ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& p : ctx->pending) ctx->free_events.push_back(p.second);
+  for (auto& p : ctx->free_events) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->slot) (void)hipFree(ctx->slot);
+  if (ctx->hout) (void)hipHostFree(ctx->hout);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+const char* sel_last_error(const sel_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+uint32_t sel_ctx_num_cus(const sel_ctx* ctx) { return ctx ? ctx->num_cus : 0; }
+
+sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch) {
+  if (!ctx) return SEL_E_INVALID;
+  if (!launch) {
+    ctx->launch = sel_launch{256, 0};
+    ctx->launch_fixed = false;
+    return SEL_OK;
+  }
+  if (launch->block != 64 && launch->block != 128 && launch->block != 256)
+    return set_err(ctx, SEL_E_INVALID, "block must be 64, 128 or 256");
+  ctx->launch = *launch;
+  ctx->launch_fixed = true;
+  return SEL_OK;
+}
+
+sel_status sel_ctx_enable_timing(sel_ctx* ctx, int enable) {
+  if (!ctx) return SEL_E_INVALID;
+  ctx->timing = enable != 0;
+  return SEL_OK;
+}
+
+sel_status sel_ctx_read_timing(sel_ctx* ctx, sel_timing* out, int reset) {
+  if (!ctx || !out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  DeviceGuard g(ctx->device);
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.second.a, p.second.b) == hipSuccess) {
+      ctx->ms[p.first] += ms;
+      ctx->launches[p.first] += 1;
+    }
+    ctx->free_events.push_back(p.second);
+  }
+  ctx->pending.clear();
+  for (int k = 0; k < SEL_K_NKINDS; ++k) {
+    out->ms[k] = ctx->ms[k];
+    out->launches[k] = ctx->launches[k];
+    if (reset) {
+      ctx->ms[k] = 0.0;
+      ctx->launches[k] = 0;
+    }
+  }
+  return SEL_OK;
+}
+
+// ----------------------------------------------------------------- tables --
+
+sel_status sel_table_create(sel_ctx* ctx, uint64_t nrows, uint32_t ncols, const sel_column* cols,
+                            sel_table** out) {
+  if (!ctx || !out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  *out = nullptr;
+  sel_status st = check_columns(ctx, nrows, ncols, cols);
+  if (st != SEL_OK) return st;
+  sel_table* t = new (std::nothrow) sel_table();
+  if (!t) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
+  t->ctx = ctx;
+  t->nrows = nrows;
+  t->cols.assign(cols, cols + ncols);
+  *out = t;
+  return SEL_OK;
+}
+
+void sel_table_destroy(sel_table* t) { delete t; }
+
+uint64_t sel_table_nrows(const sel_table* t) { return t ? t->nrows : 0; }
+
+// --------------------------------------------------------------- programs --
+
+sel_status sel_program_check(uint64_t nrows, uint32_t ncols, const sel_column* cols,
+                             const sel_instr* code, uint32_t n, const void* pool,
+                             uint32_t pool_bytes, char* text, size_t text_len, char* err,
+                             size_t err_len) {
+  std::string e;
+  sel_status st = SEL_OK;
+  std::string tmp_err;
+  if (nrows >= (1ull << 32) || ncols == 0 || ncols > SEL_MAX_COLUMNS || cols == nullptr) {
+    st = SEL_E_INVALID;
+    e = "invalid table description";
+  } else {
+    for (uint32_t k = 0; k < ncols; ++k)
+      if (dev_type(cols[k].type) == 0) {
+        st = SEL_E_INVALID;
+        e = "column " + std::to_string(k) + ": unknown type";
+      }
+  }
+  Lowered L;
+  if (st == SEL_OK) {
+    std::vector<ColInfo> ci = col_infos(cols, ncols);
+    st = (sel_status)lower_program(ci.data(), ncols, code, n, (const uint8_t*)pool, pool_bytes, L, e);
+  }
+  if (err && err_len) std::snprintf(err, err_len, "%s", e.c_str());
+  if (text && text_len) std::snprintf(text, text_len, "%s", st == SEL_OK ? L.text.c_str() : "");
+  return st;
+}
+
+sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_instr* code,
+                               uint32_t n, const void* pool, uint32_t pool_bytes,
+                               sel_program** out) {
+  if (!ctx || !table || !out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  *out = nullptr;
+  std::vector<ColInfo> ci = col_infos(table->cols.data(), (uint32_t)table->cols.size());
+  Lowered L;
+  std::string e;
+  int st = lower_program(ci.data(), (uint32_t)ci.size(), code, n, (const uint8_t*)pool, pool_bytes, L, e);
+  if (st != SEL_OK) return set_err(ctx, (sel_status)st, e);
+  DeviceGuard g(ctx->device);
+  sel_program* p = new (std::nothrow) sel_program();
+  if (!p) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->table = table;
+  p->nins = (uint32_t)L.code.size();
+  p->depth = L.depth;
+  p->text = L.text;
+  const size_t code_bytes = L.code.size() * sizeof(DevInstr);
+  const size_t total = code_bytes + L.blob.size();
+  hipError_t he = hipMalloc(&p->dev, total);
+  if (he != hipSuccess) {
+    delete p;
+    return hip_err(ctx, he, "hipMalloc(program)");
+  }
+  p->dcode = (DevInstr*)p->dev;
+  const uintptr_t blob_base = (uintptr_t)p->dev + code_bytes;
+  for (size_t k = 0; k < L.code.size(); ++k)
+    if (L.aux_is_offset[k]) L.code[k].aux = (const void*)(blob_base + (uintptr_t)L.code[k].aux);
+  std::vector<uint8_t> host(total);
+  std::memcpy(host.data(), L.code.data(), code_bytes);
+  if (!L.blob.empty()) std::memcpy(host.data() + code_bytes, L.blob.data(), L.blob.size());
+  he = hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice);
+  if (he != hipSuccess) {
+    (void)hipFree(p->dev);
+    delete p;
+    return hip_err(ctx, he, "hipMemcpy(program)");
+  }
+  p->host_code = L.code;
+  double bpr = 0.0;
+  for (uint32_t c : L.columns) bpr += type_bytes(ci[c].type);
+  bpr += (double)L.valid_columns.size() / 8.0;
+  p->bytes_per_row = bpr;
+  *out = p;
+  return SEL_OK;
+}
+
+void sel_program_destroy(sel_program* p) {
+  if (!p) return;
+  if (p->dev) {
+    DeviceGuard g(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    (void)hipFree(p->dev);
+  }
+  delete p;
+}
+
+const char* sel_program_listing(const sel_program* p) { return p ? p->text.c_str() : ""; }
+
+double sel_program_bytes_per_row(const sel_program* p) { return p ? p->bytes_per_row : 0.0; }
+
+// ------------------------------------------------------------------ count --
+
+sel_status sel_count_async(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                           uint64_t* d_count) {
+  if (!check_prog(ctx, table, prog)) return SEL_E_INVALID;
+  if (!d_count) return set_err(ctx, SEL_E_INVALID, "d_count is NULL");
+  DeviceGuard g(ctx->device);
+  ScanArgs a{};
+  a.prog = prog->dcode;
+  a.nins = prog->nins;
+  a.nrows = table->nrows;
+  a.ntiles = ntiles_of(table->nrows);
+  a.out = (unsigned long long*)d_count;
+  return run_scan(ctx, M_COUNT, a, SEL_K_COUNT);
+}
+
+sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                     uint64_t* out_count) {
+  if (!out_count) return set_err(ctx, SEL_E_INVALID, "out_count is NULL");
+  if (!check_prog(ctx, table, prog)) return SEL_E_INVALID;
+  DeviceGuard g(ctx->device);
+  ScanArgs a{};
+  a.prog = prog->dcode;
+  a.nins = prog->nins;
+  a.nrows = table->nrows;
+  a.ntiles = ntiles_of(table->nrows);
+  a.out = ctx->dout;
+  sel_status st = run_scan(ctx, M_COUNT, a, SEL_K_COUNT);
+  if (st != SEL_OK) return st;
+  return read_out(ctx, out_count, nullptr);
+}
+
+// -------------------------------------------------------------- push-down --
+
+uint64_t sel_max_rows(uint64_t nrows, double ratio) {
+  if (!(ratio > 0.0)) return 0;   // also NaN
+  if (ratio >= 1.0) return nrows;
+  // maxSize = R.size * PUSH_DOWN_MAX_SELECTIVITY evaluated in double, as
+  // Algorithm 1 states it; for an integer count c, c > maxSize iff
+  // c > floor(maxSize)
+  const double v = (double)nrows * ratio;
+  uint64_t f = (uint64_t)std::floor(v);
+  return f > nrows ? nrows : f;
+}
+
+sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                               uint64_t max_rows, uint32_t* d_out, uint64_t cap,
+                               uint64_t* out_count) {
+  if (!out_count) return set_err(ctx, SEL_E_INVALID, "out_count is NULL");
+  if (!check_prog(ctx, table, prog)) return SEL_E_INVALID;
+  if (!d_out && cap > 0) return set_err(ctx, SEL_E_INVALID, "d_out is NULL with cap > 0");
+  DeviceGuard g(ctx->device);
+  const uint64_t ntiles = ntiles_of(table->nrows);
+  const size_t mask_bytes = (size_t)ntiles * kWave * 4;
+  const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
+  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 256);
+  if (st != SEL_OK) return st;
+  uint32_t* mask = (uint32_t*)ctx->scratch;
+  uint32_t* counts = (uint32_t*)((char*)ctx->scratch + mask_bytes);
+  uint32_t* offsets = (uint32_t*)((char*)ctx->scratch + mask_bytes + counts_bytes);
+  ScanArgs a{};
+  a.prog = prog->dcode;
+  a.nins = prog->nins;
+  a.nrows = table->nrows;
+  a.ntiles = ntiles;
+  a.out = ctx->dout;
+  a.mask = mask;
+  a.tile_counts = counts;
+  st = run_scan(ctx, M_MASK, a, SEL_K_MASK);
+  if (st != SEL_OK) return st;
+  uint64_t count = 0;
+  st = read_out(ctx, &count, nullptr);
+  if (st != SEL_OK) return st;
+  *out_count = count;
+  if (count > max_rows) return SEL_OVER_LIMIT;   // Algorithm 1: throw, revert
+  if (count > cap) return SEL_E_CAPACITY;
+  if (count == 0) return SEL_OK;
+  {
+    TimedLaunch tl(ctx, SEL_K_SCAN);
+    int e = sel_launch_scan_tiles(counts, offsets, ntiles, ctx->stream);
+    tl.done();
+    if (e) return hip_err(ctx, (hipError_t)e, "tile scan launch");
+  }
+  CompactArgs c{};
+  c.mask = mask;
+  c.offsets = offsets;
+  c.ntiles = ntiles;
+  c.out = d_out;
+  c.cap = cap;
+  uint32_t grid, block;
+  scan_shape(ctx, M_MASK, ntiles, grid, block);
+  {
+    TimedLaunch tl(ctx, SEL_K_COMPACT);
+    int e = sel_launch_compact(c, grid, block, ctx->stream);
+    tl.done();
+    if (e) return hip_err(ctx, (hipError_t)e, "compaction launch");
+  }
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  return SEL_OK;
+}
+
+sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t key_col,
+                                  int64_t key_min, const sel_program* prog, uint32_t* d_bitmap,
+                                  uint64_t nbits, uint64_t* out_count) {
+  if (!ctx || !dim || !out_count) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  if (prog && prog->table != dim) return set_err(ctx, SEL_E_INVALID, "program is bound to another table");
+  if (key_col >= dim->cols.size()) return set_err(ctx, SEL_E_INVALID, "key column out of range");
+  const sel_column& kc = dim->cols[key_col];
+  if (kc.type != SEL_I32 && kc.type != SEL_I64)
+    return set_err(ctx, SEL_E_TYPE, "key column must be int32 or int64");
+  if (kc.valid) return set_err(ctx, SEL_E_INVALID, "key column must not have NULLs");
+  if (nbits == 0 || nbits > (1ull << 32)) return set_err(ctx, SEL_E_INVALID, "nbits must be 1..2^32");
+  if (!d_bitmap) return set_err(ctx, SEL_E_INVALID, "d_bitmap is NULL");
+  DeviceGuard g(ctx->device);
+  int e = sel_launch_fill(d_bitmap, (nbits + 31) / 32, 0u, ctx->stream);
+  if (e) return hip_err(ctx, (hipError_t)e, "bitmap clear");
+  ScanArgs a{};
+  if (prog) {
+    a.prog = prog->dcode;
+    a.nins = prog->nins;
+  } else {
+    a.prog = ctx->dtrue;
+    a.nins = 1;
+  }
+  a.nrows = dim->nrows;
+  a.ntiles = ntiles_of(dim->nrows);
+  a.out = ctx->dout;
+  a.key_data = kc.data;
+  a.key_type = dev_type(kc.type);
+  a.key_min = key_min;
+  a.nbits = nbits;
+  a.bitmap = d_bitmap;
+  sel_status st = run_scan(ctx, M_KEYBITMAP, a, SEL_K_KEYBITMAP);
+  if (st != SEL_OK) return st;
+  uint64_t count = 0, oor = 0;
+  st = read_out(ctx, &count, &oor);
+  if (st != SEL_OK) return st;
+  *out_count = count;
+  if (oor) return set_err(ctx, SEL_E_RANGE, std::to_string(oor) + " qualifying keys outside the bitmap range");
+  return SEL_OK;
+}
+
+sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
+                          uint32_t nfk, const uint32_t* fk_cols, const uint32_t* const* d_bitmaps,
+                          const uint64_t* nbits, uint64_t* out_count) {
+  if (!ctx || !fact || !out_count || !fk_cols || !d_bitmaps || !nbits)
+    return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  if (nfk < 1 || nfk > 8) return set_err(ctx, SEL_E_INVALID, "nfk must be 1..8");
+  if (fact_pred && fact_pred->table != fact)
+    return set_err(ctx, SEL_E_INVALID, "program is bound to another table");
+  if (fact_pred && fact_pred->depth + 1 > SEL_MAX_DEPTH)
+    return set_err(ctx, SEL_E_INVALID, "fact predicate too deep to combine");
+  std::vector<uint32_t> order(nfk);
+  for (uint32_t d = 0; d < nfk; ++d) {
+    order[d] = d;
+    if (fk_cols[d] >= fact->cols.size()) return set_err(ctx, SEL_E_INVALID, "fk column out of range");
+    const sel_column& c = fact->cols[fk_cols[d]];
+    if (c.type != SEL_I32 && c.type != SEL_I64)
+      return set_err(ctx, SEL_E_TYPE, "foreign keys must be int32 or int64");
+    if (!d_bitmaps[d]) return set_err(ctx, SEL_E_INVALID, "NULL bitmap");
+    if (nbits[d] > (1ull << 32)) return set_err(ctx, SEL_E_INVALID, "nbits must be <= 2^32");
+  }
+  // probe the smallest bitmaps first; each later probe only looks up rows
+  // that every earlier probe left TRUE or UNKNOWN
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return nbits[x] < nbits[y]; });
+  std::vector<DevInstr> code;
+  for (uint32_t k = 0; k < nfk; ++k) {
+    const uint32_t d = order[k];
+    const sel_column& c = fact->cols[fk_cols[d]];
+    DevInstr I{};
+    if (nbits[d] == 0) {
+      I.op = c.valid ? D_NN_FALSE : D_FALSE;
+      I.valid = c.valid;
+      I.type = dev_type(c.type);
+    } else {
+      I.op = D_BITMAP;
+      I.type = dev_type(c.type);
+      I.data = c.data;
+      I.valid = c.valid;
+      I.lo = 0;
+      I.span = nbits[d];
+      I.aux = d_bitmaps[d];
+      I.flags = k > 0 ? F_GUARD_AND : 0u;
+    }
+    code.push_back(I);
+    if (k > 0) {
+      DevInstr A{};
+      A.op = D_AND;
+      code.push_back(A);
+    }
+  }
+  if (fact_pred) {
+    for (const DevInstr& I : fact_pred->host_code) code.push_back(I);
+    DevInstr A{};
+    A.op = D_AND;
+    code.push_back(A);
+  }
+  if (code.size() > 128) return set_err(ctx, SEL_E_INVALID, "combined program too long");
+  DeviceGuard g(ctx->device);
+  // the staging buffer is free: every earlier call on this context synchronised
+  std::memcpy(ctx->hstage, code.data(), code.size() * sizeof(DevInstr));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->dstar, ctx->hstage, code.size() * sizeof(DevInstr),
+                              hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync(star program)");
+  ScanArgs a{};
+  a.prog = ctx->dstar;
+  a.nins = (uint32_t)code.size();
+  a.nrows = fact->nrows;
+  a.ntiles = ntiles_of(fact->nrows);
+  a.out = ctx->dout;
+  sel_status st = run_scan(ctx, M_COUNT, a, SEL_K_STAR);
+  if (st != SEL_OK) return st;
+  return read_out(ctx, out_count, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,492 @@
+// kernels.hip -- gfx950 kernels of the exact-selectivity path.
+//
+//  k_scan<M_COUNT>      fused predicate evaluation + COUNT(*)   (Ch.3 sec.3.1)
+//  k_scan<M_MASK>       same, also writing the per-row result mask and the
+//                       per-tile TRUE counts that materialisation needs
+//                       (Algorithm 1: count first, then materialise)
+//  k_scan<M_KEYBITMAP>  same, setting bit (key - key_min) for every TRUE
+//                       row of a pushed-down dimension (Ch.3 sec.3.3)
+//  k_scan_tiles         exclusive scan of the per-tile counts
+//  k_compact            mask -> ascending row ids (LDS-free wave prefix by
+//                       ballot + mbcnt)
+//
+// Evaluation is bit-sliced: each lane owns 32 rows of a 2048-row wave tile
+// (sel_device.h) and every truth value of SQL's three-valued logic is a pair
+// of 32-bit words (t, f): bit set in t = TRUE, in f = FALSE, in neither =
+// UNKNOWN.  Kleene AND is (t1 & t2, f1 | f2), OR is (t1 | t2, f1 & f2), NOT
+// swaps the words.  The postfix program is wave-uniform, so its dispatch is
+// scalar; only the leaf tests touch per-row data.
+#include <hip/hip_runtime.h>
+
+#include "sel_device.h"
+
+using namespace sel;
+
+typedef int32_t v2i __attribute__((ext_vector_type(2)));
+typedef int32_t v4i __attribute__((ext_vector_type(4)));
+
+// Pointers read from memory are generic to the compiler; casting them to
+// the global (1) or constant (4) address space gives global_load / s_load
+// instead of flat loads.
+#define GLOBAL __attribute__((address_space(1)))
+#define CONSTANT __attribute__((address_space(4)))
+typedef const CONSTANT DevInstr* CInstr;
+
+namespace {
+
+template <class T>
+__device__ __forceinline__ const GLOBAL T* gptr(const void* p) {
+  return (const GLOBAL T*)p;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------- loads --
+// Raw storage of one lane's 32 rows of a column in a full tile.  All loads
+// of a column are issued before any is used, so each lane keeps 32 rows of
+// loads in flight; they are nontemporal (streamed once, not re-read).
+// int64 columns are loaded in two halves of four steps (16 rows per lane),
+// so one half's loads (8 x 16 B per lane) are in flight at a time.
+template <int TY> struct Raw;
+template <> struct Raw<T_I8> { uint32_t w[kSteps]; };
+template <> struct Raw<T_I16> { v2i w[kSteps]; };
+template <> struct Raw<T_I32> { v4i w[kSteps]; };
+template <> struct Raw<T_I64> { v4i w[kSteps]; };
+
+template <int TY>
+__device__ __forceinline__ void load_full(Raw<TY>& r, const void* data, uint64_t tb, uint32_t lane) {
+  if constexpr (TY == T_I8) {
+    const GLOBAL uint32_t* p = gptr<uint32_t>((const int8_t*)data + tb) + lane;
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+  } else if constexpr (TY == T_I16) {
+    const GLOBAL v2i* p = gptr<v2i>((const int16_t*)data + tb) + lane;
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+  } else if constexpr (TY == T_I32) {
+    const GLOBAL v4i* p = gptr<v4i>((const int32_t*)data + tb) + lane;
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+  }
+}
+
+// one half (steps 4h .. 4h+3) of an int64 column
+__device__ __forceinline__ void load_half64(Raw<T_I64>& r, const void* data, uint64_t tb,
+                                            uint32_t lane, int h) {
+  const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * 4 * h;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    r.w[2 * j] = __builtin_nontemporal_load(p + 128 * j);
+    r.w[2 * j + 1] = __builtin_nontemporal_load(p + 128 * j + 1);
+  }
+}
+
+// value of row bit b (= 4*j + i) from the raw registers; b is a constant
+// after unrolling.  Narrow types are sign-extended to int32.
+template <int TY>
+__device__ __forceinline__ auto get(const Raw<TY>& r, int b) {
+  const int j = b >> 2, i = b & 3;
+  if constexpr (TY == T_I8) {
+    return (int32_t)(int8_t)(r.w[j] >> (8 * i));
+  } else if constexpr (TY == T_I16) {
+    return (int32_t)(int16_t)((uint32_t)r.w[j][i >> 1] >> (16 * (i & 1)));
+  } else if constexpr (TY == T_I32) {
+    return (int32_t)r.w[j][i];
+  } else {  // b indexes the loaded half: 0..15
+    const v4i& q = r.w[2 * j + (i >> 1)];
+    const int k = 2 * (i & 1);
+    return (int64_t)(((uint64_t)(uint32_t)q[k + 1] << 32) | (uint32_t)q[k]);
+  }
+}
+
+template <int TY>
+__device__ __forceinline__ auto load_elem(const void* data, uint64_t row) {
+  if constexpr (TY == T_I8) return (int32_t)gptr<int8_t>(data)[row];
+  else if constexpr (TY == T_I16) return (int32_t)gptr<int16_t>(data)[row];
+  else if constexpr (TY == T_I32) return (int32_t)gptr<int32_t>(data)[row];
+  else return (int64_t)gptr<int64_t>(data)[row];
+}
+
+__device__ __forceinline__ uint64_t row_of(uint64_t tb, uint32_t lane, int b) {
+  return tb + 256u * (uint32_t)(b >> 2) + 4u * lane + (uint32_t)(b & 3);
+}
+
+// Predicate bits of one lane's 32 rows: bit b = pred(value of row b).  The
+// word is built highest row first as P = 2P + bit, one add-with-carry per
+// row after the compare.
+template <int TY, bool FULL, class Pred>
+__device__ __forceinline__ uint32_t pred_bits(const void* data, uint64_t tb, uint32_t lane,
+                                              uint64_t nrows, Pred pred) {
+  uint32_t P = 0;
+  if constexpr (FULL && TY == T_I64) {
+#pragma unroll
+    for (int h = 1; h >= 0; --h) {
+      Raw<TY> r;
+      load_half64(r, data, tb, lane, h);
+#pragma unroll
+      for (int b = 15; b >= 0; --b) P = (P << 1) + (uint32_t)pred(get<TY>(r, b), 16 * h + b);
+    }
+  } else if constexpr (FULL) {
+    Raw<TY> r;
+    load_full<TY>(r, data, tb, lane);
+#pragma unroll
+    for (int b = 31; b >= 0; --b) P = (P << 1) + (uint32_t)pred(get<TY>(r, b), b);
+  } else {
+    // the one partial tile of a table: element loads, kept rolled
+#pragma unroll 1
+    for (int b = 31; b >= 0; --b) {
+      const uint64_t row = row_of(tb, lane, b);
+      uint32_t bit = 0;
+      if (row < nrows) bit = (uint32_t)pred(load_elem<TY>(data, row), b);
+      P = (P << 1) + bit;
+    }
+  }
+  return P;
+}
+
+// Validity bits of the lane's rows (all ones for a column without NULLs).
+template <bool FULL>
+__device__ __forceinline__ uint32_t valid_bits(const uint32_t* valid, uint64_t tb, uint32_t lane,
+                                               uint64_t nrows) {
+  if (valid == nullptr) return ~0u;
+  const GLOBAL uint32_t* vw = gptr<uint32_t>(valid) + tb / 32 + (lane >> 3);
+  const uint32_t sh = 4 * (lane & 7);
+  uint32_t V = 0;
+#pragma unroll
+  for (int j = 0; j < kSteps; ++j) {
+    if (FULL || tb + 256u * j + 4u * lane < nrows)
+      V |= ((vw[8 * j] >> sh) & 0xFu) << (4 * j);
+  }
+  return V;
+}
+
+__device__ __forceinline__ uint32_t inrange_bits(uint64_t tb, uint32_t lane, uint64_t nrows) {
+  uint32_t m = 0;
+#pragma unroll 1
+  for (int b = 0; b < 32; ++b) m |= (uint32_t)(row_of(tb, lane, b) < nrows) << b;
+  return m;
+}
+
+// ---------------------------------------------------------------- leaves --
+template <int TY, bool FULL>
+__device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
+                                              uint64_t nrows, uint32_t need) {
+  const void* data = I->data;
+  const int64_t lo = I->lo;
+  const uint64_t span = I->span;
+  if (op == D_RANGE) {
+    if constexpr (TY == T_I64) {
+      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int) {
+        return (uint64_t)x - (uint64_t)lo <= span;
+      });
+    } else {
+      const uint32_t lo32 = (uint32_t)lo, span32 = (uint32_t)span;
+      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int) {
+        return (uint32_t)x - lo32 <= span32;
+      });
+    }
+  } else if (op == D_BITMAP) {
+    // rows that need no test (guard) or fall outside [lo, lo + nbits) read
+    // word 0 and are masked: no branch, so all 32 lookups issue together
+    const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
+    if constexpr (TY == T_I64) {
+      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
+        const uint64_t d = (uint64_t)x - (uint64_t)lo;
+        const bool ok = d < span && ((need >> b) & 1u);
+        const uint32_t k = ok ? (uint32_t)d : 0u;  // nbits <= 2^32
+        return ok & ((bits[k >> 5] >> (k & 31)) & 1u);
+      });
+    } else {
+      // x - lo in 64 bits: a negative key must not alias a bit when nbits
+      // exceeds 2^31
+      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
+        const uint64_t d = (uint64_t)((int64_t)x - lo);
+        const bool ok = d < span && ((need >> b) & 1u);
+        const uint32_t k = ok ? (uint32_t)d : 0u;
+        return ok & ((bits[k >> 5] >> (k & 31)) & 1u);
+      });
+    }
+  } else {  // D_INLIST: branch-free lower bound over a sorted list
+    // a long sparse list (rare): rows one at a time, loop kept rolled
+    const GLOBAL int64_t* list = gptr<int64_t>(I->aux);
+    const uint32_t n = I->n;
+    return pred_bits<TY, false>(data, tb, lane, nrows, [=](auto x, int b) -> uint32_t {
+      const int64_t xx = (int64_t)x;
+      uint32_t base = 0, len = n;
+      while (len > 1) {
+        const uint32_t half = len >> 1;
+        base = list[base + half] <= xx ? base + half : base;
+        len -= half;
+      }
+      return ((need >> b) & 1u) & (list[base] == xx ? 1u : 0u);
+    });
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void eval_leaf(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
+                                          uint64_t nrows, uint32_t tos_t, uint32_t tos_f,
+                                          uint32_t& t, uint32_t& f) {
+  const uint32_t* valid = I->valid;
+  const uint32_t V = valid_bits<FULL>(valid, tb, lane, nrows);
+  if (op >= D_NN_TRUE) {
+    switch (op) {
+      case D_NN_TRUE: t = V; f = 0; return;
+      case D_NN_FALSE: t = 0; f = V; return;
+      case D_ISNULL: t = ~V; f = V; return;
+      default: t = V; f = ~V; return;  // D_NOTNULL
+    }
+  }
+  const uint32_t flags = I->flags;
+  uint32_t need = ~0u;
+  if (flags & F_GUARD_AND) need = ~tos_f;
+  else if (flags & F_GUARD_OR) need = ~tos_t;
+  uint32_t P;
+  switch (I->type) {
+    case T_I8: P = leaf_pred<T_I8, FULL>(op, I, tb, lane, nrows, need); break;
+    case T_I16: P = leaf_pred<T_I16, FULL>(op, I, tb, lane, nrows, need); break;
+    case T_I32: P = leaf_pred<T_I32, FULL>(op, I, tb, lane, nrows, need); break;
+    default: P = leaf_pred<T_I64, FULL>(op, I, tb, lane, nrows, need); break;
+  }
+  t = P & V;
+  f = ~P & V;
+}
+
+// ---------------------------------------------------------- interpreter --
+// The stack below the top is held in registers; its index is uniform, so
+// the unrolled selects below compile to scalar branches / v_cndmask and no
+// private memory is used.
+__device__ __forceinline__ void spill(uint32_t (&st)[kMaxDepth], uint32_t (&sf)[kMaxDepth],
+                                      int idx, uint32_t t, uint32_t f) {
+#pragma unroll
+  for (int k = 0; k < kMaxDepth; ++k)
+    if (k == idx) { st[k] = t; sf[k] = f; }
+}
+__device__ __forceinline__ void fill(const uint32_t (&st)[kMaxDepth], const uint32_t (&sf)[kMaxDepth],
+                                     int idx, uint32_t& t, uint32_t& f) {
+  t = 0; f = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxDepth; ++k)
+    if (k == idx) { t = st[k]; f = sf[k]; }
+}
+
+// TRUE bits of the lane's 32 rows of the tile starting at row tb.
+template <bool FULL>
+__device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64_t tb,
+                                              uint32_t lane, uint64_t nrows) {
+  uint32_t st[kMaxDepth], sf[kMaxDepth];
+  uint32_t tt = 0, tf = 0;
+  int d = 0;  // values on the stack; the top is (tt, tf)
+  for (uint32_t pc = 0; pc < nins; ++pc) {
+    CInstr I = prog + pc;
+    const uint32_t op = I->op;
+    if (op < D_AND || op == D_TRUE || op == D_FALSE) {
+      uint32_t t, f;
+      if (op == D_TRUE) { t = ~0u; f = 0; }
+      else if (op == D_FALSE) { t = 0; f = ~0u; }
+      else eval_leaf<FULL>(op, I, tb, lane, nrows, tt, tf, t, f);
+      spill(st, sf, d - 1, tt, tf);
+      tt = t; tf = f;
+      ++d;
+    } else if (op == D_NOT) {
+      const uint32_t x = tt; tt = tf; tf = x;
+    } else if (op == D_ISUNK) {
+      const uint32_t k = tt | tf; tt = ~k; tf = k;
+    } else {
+      uint32_t at, af;
+      fill(st, sf, d - 2, at, af);
+      if (op == D_AND) { tt &= at; tf |= af; }
+      else { tt |= at; tf &= af; }
+      --d;
+    }
+  }
+  return tt;
+}
+
+// ------------------------------------------------------------ reductions --
+// Sum over the 64 lanes: DPP within quads and 16-lane rows, then the four
+// row sums by readlane.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);  // row_ror:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+}
+
+// Block sum, one device atomic per workgroup, and the last workgroup (by
+// ticket) publishes the total and resets the slot for the next launch.
+__device__ void finish(DevSlot* slot, unsigned long long* out, uint32_t c0, uint32_t c1, bool two) {
+  __shared__ unsigned long long red0[16], red1[16];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t s0 = wave_sum(c0);
+  const uint32_t s1 = two ? wave_sum(c1) : 0u;
+  if (lane == 0) { red0[wave] = s0; red1[wave] = s1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b0 = 0, b1 = 0;
+    for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) { b0 += red0[w]; b1 += red1[w]; }
+    if (b0) atomicAdd(&slot->acc, b0);
+    if (b1) atomicAdd(&slot->acc2, b1);
+    __threadfence();
+    const unsigned int ticket = atomicAdd(&slot->ticket, 1u);
+    if (ticket == gridDim.x - 1) {
+      __threadfence();
+      out[0] = atomicAdd(&slot->acc, 0ull);
+      if (two) out[1] = atomicAdd(&slot->acc2, 0ull);
+      atomicExch(&slot->acc, 0ull);
+      atomicExch(&slot->acc2, 0ull);
+      __threadfence();
+      atomicExch(&slot->ticket, 0u);
+    }
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_, ScanArgs a) {
+  CInstr prog = (CInstr)prog_;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint64_t W = (uint64_t)gridDim.x * nw;
+  uint32_t cnt = 0, oor = 0;
+  for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
+    const uint64_t tb = tile * kTileRows;
+    uint32_t T;
+    if (tb + kTileRows <= a.nrows) {
+      T = eval_tile<true>(prog, a.nins, tb, lane, a.nrows);
+    } else {
+      T = eval_tile<false>(prog, a.nins, tb, lane, a.nrows) & inrange_bits(tb, lane, a.nrows);
+    }
+    cnt += __builtin_popcount(T);
+    if constexpr (MODE == M_MASK) {
+      a.mask[tile * kWave + lane] = T;
+      const uint32_t tc = wave_sum(__builtin_popcount(T));
+      if (lane == 0) a.tile_counts[tile] = tc;
+    } else if constexpr (MODE == M_KEYBITMAP) {
+      uint32_t m = T;
+      while (m) {
+        const int b = __builtin_ctz(m);
+        m &= m - 1;
+        const uint64_t row = row_of(tb, lane, b);
+        const int64_t key = a.key_type == T_I64 ? ((const int64_t*)a.key_data)[row]
+                                                : (int64_t)((const int32_t*)a.key_data)[row];
+        const uint64_t d = (uint64_t)key - (uint64_t)a.key_min;
+        if (d < a.nbits) atomicOr(&a.bitmap[d >> 5], 1u << (d & 31));
+        else ++oor;
+      }
+    }
+  }
+  finish(a.slot, a.out, cnt, oor, MODE == M_KEYBITMAP);
+}
+
+// Exclusive scan of n tile counts by one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_tiles(const uint32_t* __restrict__ counts,
+                                                     uint32_t* __restrict__ offsets, uint64_t n) {
+  __shared__ uint32_t part[1024];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t chunk = (n + 1023) / 1024;
+  const uint64_t lo = tid * chunk < n ? tid * chunk : n;
+  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+  uint32_t s = 0;
+  for (uint64_t i = lo; i < hi; ++i) s += counts[i];
+  part[tid] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - s;  // exclusive prefix of this thread's chunk
+  for (uint64_t i = lo; i < hi; ++i) {
+    const uint32_t c = counts[i];
+    offsets[i] = run;
+    run += c;
+  }
+}
+
+// Row ids of TRUE rows in ascending order: rows are ordered (step j, lane,
+// i), so a row's rank is the tile offset + TRUE rows of earlier steps +
+// TRUE rows of this step in lower lanes (ballot per bit plane, mbcnt) +
+// TRUE rows earlier in the lane's own nibble.
+__global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint64_t W = (uint64_t)gridDim.x * nw;
+  for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
+    const uint32_t w = a.mask[tile * kWave + lane];
+    uint64_t base = uni(a.offsets[tile]);
+    const uint64_t tb = tile * kTileRows;
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) {
+      const uint32_t nib = (w >> (4 * j)) & 0xFu;
+      uint32_t below = 0, total = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const unsigned long long bal = __ballot((nib >> i) & 1u);
+        below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, below));
+        total += (uint32_t)__builtin_popcountll(bal);
+      }
+      uint64_t pos = base + below;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if ((nib >> i) & 1u) {
+          if (pos < a.cap) a.out[pos] = (uint32_t)(tb + 256u * j + 4u * lane + i);
+          ++pos;
+        }
+      }
+      base += total;
+    }
+  }
+}
+
+__global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+}  // namespace
+
+int sel_launch_scan(int mode, const ScanArgs& a, uint32_t grid, uint32_t block, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  switch (mode) {
+    case M_COUNT: hipLaunchKernelGGL(k_scan<M_COUNT>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
+    case M_MASK: hipLaunchKernelGGL(k_scan<M_MASK>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
+    default: hipLaunchKernelGGL(k_scan<M_KEYBITMAP>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
+  }
+  return (int)hipGetLastError();
+}
+
+int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint64_t n, void* stream) {
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, (hipStream_t)stream, counts, offsets, n);
+  return (int)hipGetLastError();
+}
+
+int sel_launch_compact(const CompactArgs& a, uint32_t grid, uint32_t block, void* stream) {
+  hipLaunchKernelGGL(k_compact, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream) {
+  if (nwords == 0) return 0;
+  uint64_t blocks = (nwords + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, p, nwords, value);
+  return (int)hipGetLastError();
+}
+
+int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu) {
+  hipError_t e;
+  switch (mode) {
+    case M_COUNT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_COUNT>, block, 0); break;
+    case M_MASK: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_MASK>, block, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_KEYBITMAP>, block, 0); break;
+  }
+  return (int)e;
+}

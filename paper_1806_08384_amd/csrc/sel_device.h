@@ -1,0 +1,109 @@
+// sel_device.h -- device form of a compiled predicate program and the
+// launch interface between the host runtime (api.cpp, compile.cpp) and the
+// HIP kernels (kernels.hip).
+#pragma once
+
+#include <stdint.h>
+
+namespace sel {
+
+// Row <-> lane mapping of one wave tile (2048 rows).  Lane L owns rows
+//   tile_base + 256*j + 4*L + i      (j = 0..7 "steps", i = 0..3)
+// and keeps its 32 truth bits in one 32-bit word, bit b = 4*j + i.  Four
+// consecutive rows per lane per step keep every column's loads wide and
+// coalesced for all element widths (int8: 4 B, int16: 8 B, int32: 16 B,
+// int64: 2 x 16 B per lane per step) while every column maps rows to the
+// same (lane, bit), so truth words of different columns combine bitwise.
+constexpr int kWave = 64;
+constexpr int kRowsPerStep = 4;
+constexpr int kSteps = 8;
+constexpr int kTileRows = kWave * kRowsPerStep * kSteps;  // 2048
+constexpr int kMaxDepth = 8;
+
+enum DevType : uint32_t { T_I8 = 1, T_I16 = 2, T_I32 = 3, T_I64 = 4 };
+
+// Device opcodes (the lowered program).
+enum DevOp : uint32_t {
+  D_RANGE = 1,     // lo <= x <= lo + span (unsigned span), x in column type
+  D_BITMAP = 2,    // 0 <= x - lo < nbits and bit (x - lo) of aux
+  D_INLIST = 3,    // x in aux[0..n) (sorted, distinct int64)
+  D_NN_TRUE = 4,   // TRUE on non-NULL rows, UNKNOWN on NULL rows
+  D_NN_FALSE = 5,  // FALSE on non-NULL rows, UNKNOWN on NULL rows
+  D_ISNULL = 6,
+  D_NOTNULL = 7,
+  D_AND = 16,
+  D_OR = 17,
+  D_NOT = 18,
+  D_ISUNK = 19,
+  D_TRUE = 20,
+  D_FALSE = 21
+};
+
+enum DevFlags : uint32_t {
+  F_GUARD_AND = 1,  // leaf is the right operand of the next AND: rows whose
+                    // left operand is FALSE need not be evaluated
+  F_GUARD_OR = 2    // ... of the next OR: rows whose left operand is TRUE
+};
+
+struct DevInstr {          // 64 bytes, read with scalar loads
+  uint32_t op;
+  uint32_t type;           // DevType of the column (leaves)
+  uint32_t flags;          // DevFlags
+  uint32_t n;              // D_INLIST: list length
+  const void* data;        // column values
+  const uint32_t* valid;   // validity words or nullptr
+  int64_t lo;              // D_RANGE lower bound / D_BITMAP base
+  uint64_t span;           // D_RANGE: hi - lo (unsigned) / D_BITMAP: nbits
+  const void* aux;         // D_BITMAP words / D_INLIST values
+  uint64_t pad;
+};
+static_assert(sizeof(DevInstr) == 64, "DevInstr layout");
+
+// Per-launch completion slot: an accumulator and a ticket that the last
+// workgroup resets, so that no memset is needed between launches.
+struct DevSlot {
+  unsigned long long acc;    // running count
+  unsigned long long acc2;   // second counter (out-of-range keys)
+  unsigned int ticket;
+  unsigned int pad[3];
+};
+
+enum ScanMode : int { M_COUNT = 0, M_MASK = 1, M_KEYBITMAP = 2 };
+
+struct ScanArgs {
+  const DevInstr* prog;
+  uint32_t nins;
+  uint32_t pad0;
+  uint64_t nrows;
+  uint64_t ntiles;
+  DevSlot* slot;
+  unsigned long long* out;     // out[0] = count, out[1] = out-of-range keys
+  uint32_t* mask;              // M_MASK: one word per lane per tile
+  uint32_t* tile_counts;       // M_MASK: TRUE rows per tile
+  // M_KEYBITMAP
+  const void* key_data;
+  uint32_t key_type;
+  uint32_t pad1;
+  int64_t key_min;
+  uint64_t nbits;
+  uint32_t* bitmap;
+};
+
+struct CompactArgs {
+  const uint32_t* mask;
+  const uint32_t* offsets;     // exclusive prefix of tile counts
+  uint64_t ntiles;
+  uint32_t* out;
+  uint64_t cap;
+};
+
+}  // namespace sel
+
+// Launchers implemented in kernels.hip (return hipError_t as int).
+extern "C++" {
+int sel_launch_scan(int mode, const sel::ScanArgs& a, uint32_t grid, uint32_t block, void* stream);
+int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint64_t n, void* stream);
+int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
+int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
+int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);
+}

@@ -1,0 +1,368 @@
+"""ctypes binding of libsel (include/sel.h): argument marshalling only.
+
+Every step of the path runs in libsel's HIP kernels; this module converts
+Python values to the C ABI and back.  Predicate trees (nested tuples in SQL
+terms, see ``datagen``) are flattened to the ABI's postfix ``sel_instr``
+program plus its constant pool; all lowering happens in the library.
+
+If libsel.so is missing or cannot be loaded this module raises at import:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsel.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1806_08384_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- ABI constants (include/sel.h) -----------------------------------------
+SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY = 0, 1, 2
+SEL_E_INVALID, SEL_E_TYPE, SEL_E_NOMEM, SEL_E_DEVICE, SEL_E_BUSY, SEL_E_RANGE = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "SEL_OK", 1: "SEL_OVER_LIMIT", 2: "SEL_E_CAPACITY", -1: "SEL_E_INVALID",
+                -2: "SEL_E_TYPE", -3: "SEL_E_NOMEM", -4: "SEL_E_DEVICE", -5: "SEL_E_BUSY",
+                -6: "SEL_E_RANGE"}
+TYPES = {"i8": 1, "i16": 2, "i32": 3, "i64": 4}
+OP = {"=": 1, "<>": 2, "<": 3, "<=": 4, ">": 5, ">=": 6, "between": 7, "in": 8, "codeset": 9,
+      "isnull": 10, "notnull": 11, "and": 16, "or": 17, "not": 18, "isunknown": 19,
+      "true": 20, "false": 21}
+K_COUNT, K_MASK, K_SCAN, K_COMPACT, K_KEYBITMAP, K_STAR, K_BATCH, K_NKINDS = range(8)
+INT64_MIN, INT64_MAX = -(2 ** 63), 2 ** 63 - 1
+UINT64_MAX = 2 ** 64 - 1
+
+
+class SelError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class sel_column(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("dict_card", ctypes.c_uint32),
+                ("data", ctypes.c_void_p), ("valid", ctypes.c_void_p)]
+
+
+class sel_instr(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint16), ("col", ctypes.c_uint16), ("aux", ctypes.c_uint32),
+                ("a", ctypes.c_int64), ("b", ctypes.c_int64)]
+
+
+class sel_launch(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32)]
+
+
+class sel_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * K_NKINDS), ("launches", ctypes.c_uint64 * K_NKINDS)]
+
+
+_vp, _u64, _u32, _i32, _i64 = (ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                               ctypes.c_int32, ctypes.c_int64)
+_P = ctypes.POINTER
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+sel_ctx_create = _sig("sel_ctx_create", _i32, ctypes.c_int, _vp, _P(_vp))
+sel_ctx_destroy = _sig("sel_ctx_destroy", None, _vp)
+sel_last_error = _sig("sel_last_error", ctypes.c_char_p, _vp)
+sel_ctx_num_cus = _sig("sel_ctx_num_cus", _u32, _vp)
+sel_table_create = _sig("sel_table_create", _i32, _vp, _u64, _u32, _P(sel_column), _P(_vp))
+sel_table_destroy = _sig("sel_table_destroy", None, _vp)
+sel_table_nrows = _sig("sel_table_nrows", _u64, _vp)
+sel_program_compile = _sig("sel_program_compile", _i32, _vp, _vp, _P(sel_instr), _u32, _vp, _u32,
+                           _P(_vp))
+sel_program_destroy = _sig("sel_program_destroy", None, _vp)
+sel_program_check = _sig("sel_program_check", _i32, _u64, _u32, _P(sel_column), _P(sel_instr), _u32,
+                         _vp, _u32, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_char_p,
+                         ctypes.c_size_t)
+sel_program_listing = _sig("sel_program_listing", ctypes.c_char_p, _vp)
+sel_program_bytes_per_row = _sig("sel_program_bytes_per_row", ctypes.c_double, _vp)
+sel_count = _sig("sel_count", _i32, _vp, _vp, _vp, _P(_u64))
+sel_count_async = _sig("sel_count_async", _i32, _vp, _vp, _vp, _vp)
+sel_max_rows = _sig("sel_max_rows", _u64, _u64, ctypes.c_double)
+sel_pushdown_rowids = _sig("sel_pushdown_rowids", _i32, _vp, _vp, _vp, _u64, _vp, _u64, _P(_u64))
+sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i64, _vp, _vp, _u64,
+                              _P(_u64))
+sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
+                      _P(_u64))
+sel_ctx_set_launch = _sig("sel_ctx_set_launch", _i32, _vp, _P(sel_launch))
+sel_ctx_enable_timing = _sig("sel_ctx_enable_timing", _i32, _vp, ctypes.c_int)
+sel_ctx_read_timing = _sig("sel_ctx_read_timing", _i32, _vp, _P(sel_timing), ctypes.c_int)
+
+EXPORTED = [n for n in list(globals()) if n.startswith("sel_") and callable(globals()[n])
+            and hasattr(globals()[n], "argtypes")]
+
+
+# ---- predicate tree -> postfix program + pool ----------------------------------
+
+def _lit(v) -> int:
+    v = int(v)
+    if not INT64_MIN <= v <= INT64_MAX:
+        raise ValueError(f"literal {v} outside int64 (the ABI takes int64 literals)")
+    return v
+
+
+def flatten(tree):
+    """Postfix sel_instr array and pool bytes for a predicate tree."""
+    code: list = []
+    pool = bytearray()
+
+    def put(op, col=0, aux=0, a=0, b=0):
+        code.append((OP[op], col, aux, a, b))
+
+    def align(n):
+        while len(pool) % n:
+            pool.append(0)
+
+    def walk(t):
+        k = t[0]
+        if k == "cmp":
+            put(t[2], t[1], 0, _lit(t[3]))
+        elif k == "between":
+            put("between", t[1], 0, _lit(t[2]), _lit(t[3]))
+        elif k == "in":
+            vals = np.asarray([_lit(v) for v in t[2]], dtype=np.int64)
+            align(8)
+            off = len(pool)
+            pool.extend(vals.tobytes())
+            put("in", t[1], off, 0, len(vals))
+        elif k == "codeset":
+            words = np.ascontiguousarray(t[3], dtype=np.uint32)
+            align(4)
+            off = len(pool)
+            pool.extend(words.tobytes())
+            put("codeset", t[1], off, 0, int(t[2]))
+        elif k in ("isnull", "notnull"):
+            put(k, t[1])
+        elif k in ("true", "false"):
+            put(k)
+        elif k in ("not", "isunknown"):
+            walk(t[1])
+            put(k)
+        elif k in ("and", "or"):
+            walk(t[1])
+            for c in t[2:]:
+                walk(c)
+                put(k)
+        else:
+            raise ValueError(f"unknown node {k!r}")
+
+    walk(tree)
+    arr = (sel_instr * len(code))()
+    for i, (op, col, aux, a, b) in enumerate(code):
+        arr[i].op, arr[i].col, arr[i].aux, arr[i].a, arr[i].b = op, col, aux, a, b
+    return arr, bytes(pool)
+
+
+def _columns_struct(cols):
+    arr = (sel_column * len(cols))()
+    for i, (ty, card, data, valid) in enumerate(cols):
+        arr[i].type = TYPES[ty] if isinstance(ty, str) else int(ty)
+        arr[i].dict_card = card
+        arr[i].data = data
+        arr[i].valid = valid
+    return arr
+
+
+def check_program(nrows: int, col_specs, tree):
+    """Host-only validation + lowering (sel_program_check): returns
+    (status, listing, error) without any device work.  col_specs: list of
+    (type, dict_card, nullable)."""
+    cols = _columns_struct([(ty, card, None, 8 if nullable else None)
+                            for ty, card, nullable in col_specs])
+    code, pool = flatten(tree)
+    return check_raw(nrows, cols, code, pool)
+
+
+def check_raw(nrows, cols, code, pool: bytes):
+    text = ctypes.create_string_buffer(16384)
+    err = ctypes.create_string_buffer(512)
+    pbuf = ctypes.create_string_buffer(pool, max(1, len(pool)))
+    st = sel_program_check(nrows, len(cols), cols, code, len(code), pbuf, len(pool), text,
+                           len(text), err, len(err))
+    return st, text.value.decode(), err.value.decode()
+
+
+# ---- object wrappers -------------------------------------------------------------
+
+class Context:
+    """A libsel context bound to a device and a HIP stream (default: torch's
+    current stream on that device)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.torch_stream = stream
+        h = _vp()
+        st = sel_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if st != SEL_OK:
+            raise SelError(st, sel_last_error(None).decode())
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            sel_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return sel_last_error(self.h).decode()
+
+    def check(self, st, ok=(SEL_OK,)):
+        if st not in ok:
+            raise SelError(st, self.error())
+        return st
+
+    @property
+    def num_cus(self) -> int:
+        return int(sel_ctx_num_cus(self.h))
+
+    # ---- tables / programs
+    def table(self, nrows: int, cols, keep=()):
+        """cols: list of (type, dict_card, data_ptr, valid_ptr_or_None)."""
+        return DeviceTable(self, nrows, cols, keep)
+
+    def program(self, table, tree):
+        return Program(self, table, tree)
+
+    # ---- calls
+    def count(self, table, prog) -> int:
+        out = _u64(0)
+        self.check(sel_count(self.h, table.h, prog.h, ctypes.byref(out)))
+        return int(out.value)
+
+    def count_async(self, table, prog, d_count_ptr: int):
+        self.check(sel_count_async(self.h, table.h, prog.h, d_count_ptr))
+
+    def pushdown_rowids(self, table, prog, max_rows: int, out_tensor, cap=None):
+        """Returns (status, count); ids land in out_tensor[:count] on SEL_OK."""
+        out = _u64(0)
+        if cap is None:
+            cap = 0 if out_tensor is None else out_tensor.numel()
+        ptr = None if out_tensor is None else out_tensor.data_ptr()
+        st = sel_pushdown_rowids(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
+        self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
+        return st, int(out.value)
+
+    def pushdown_keybitmap(self, dim, key_col: int, key_min: int, prog, bitmap_tensor, nbits: int):
+        """Returns (status, count); status SEL_OK or SEL_E_RANGE."""
+        out = _u64(0)
+        st = sel_pushdown_keybitmap(self.h, dim.h, key_col, key_min,
+                                    prog.h if prog is not None else None,
+                                    bitmap_tensor.data_ptr(), nbits, ctypes.byref(out))
+        self.check(st, ok=(SEL_OK, SEL_E_RANGE))
+        return st, int(out.value)
+
+    def star_count(self, fact, fk_cols, bitmaps, nbits, fact_pred=None) -> int:
+        n = len(fk_cols)
+        fk = (_u32 * n)(*fk_cols)
+        bm = (_vp * n)(*[b.data_ptr() for b in bitmaps])
+        nb = (_u64 * n)(*nbits)
+        out = _u64(0)
+        self.check(sel_star_count(self.h, fact.h, fact_pred.h if fact_pred is not None else None,
+                                  n, fk, bm, nb, ctypes.byref(out)))
+        return int(out.value)
+
+    def set_launch(self, block=None, grid=0):
+        if block is None:
+            self.check(sel_ctx_set_launch(self.h, None))
+        else:
+            self.check(sel_ctx_set_launch(self.h, ctypes.byref(sel_launch(block, grid))))
+
+    def enable_timing(self, on=True):
+        self.check(sel_ctx_enable_timing(self.h, 1 if on else 0))
+
+    def read_timing(self, reset=True):
+        t = sel_timing()
+        self.check(sel_ctx_read_timing(self.h, ctypes.byref(t), 1 if reset else 0))
+        return [float(x) for x in t.ms], [int(x) for x in t.launches]
+
+
+def max_rows(nrows: int, ratio: float) -> int:
+    return int(sel_max_rows(nrows, ratio))
+
+
+class DeviceTable:
+    def __init__(self, ctx: Context, nrows: int, cols, keep=()):
+        self.ctx = ctx
+        self.nrows = nrows
+        self._keep = list(keep)
+        arr = _columns_struct(cols)
+        h = _vp()
+        ctx.check(sel_table_create(ctx.h, nrows, len(cols), arr, ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        try:
+            if self.h:
+                sel_table_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Program:
+    def __init__(self, ctx: Context, table: DeviceTable, tree):
+        self.ctx = ctx
+        self.table = table
+        code, pool = flatten(tree)
+        pbuf = ctypes.create_string_buffer(pool, max(1, len(pool)))
+        h = _vp()
+        ctx.check(sel_program_compile(ctx.h, table.h, code, len(code), pbuf, len(pool),
+                                      ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def listing(self) -> str:
+        return sel_program_listing(self.h).decode()
+
+    @property
+    def bytes_per_row(self) -> float:
+        return float(sel_program_bytes_per_row(self.h))
+
+    def __del__(self):
+        try:
+            if self.h:
+                sel_program_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def device_table(ctx: Context, host_table, device=None):
+    """Copy a host table (objects with .columns of name/type/data/valid/
+    dict_card numpy arrays) into device memory and describe it to libsel."""
+    import torch
+    dev = torch.device("cuda", ctx.device if device is None else device)
+    cols, keep = [], []
+    for c in host_table.columns:
+        d = torch.from_numpy(np.ascontiguousarray(c.data)).to(dev)
+        keep.append(d)
+        vptr = None
+        if c.valid is not None:
+            v = torch.from_numpy(np.ascontiguousarray(c.valid).view(np.int32)).to(dev)
+            keep.append(v)
+            vptr = v.data_ptr()
+        cols.append((c.type, c.dict_card, d.data_ptr(), vptr))
+    torch.cuda.synchronize(dev)
+    t = ctx.table(host_table.nrows, cols, keep)
+    t.tensors = keep
+    return t

@@ -1,0 +1,267 @@
+"""GPU parity: libsel's HIP path (through the C ABI) against the CPU oracle,
+bit-exact on every count, every row-id array and every key bitmap."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests import sqlite_ref
+from tests.gpu_common import UINT64_MAX, as_u32, ids_tensor, say, slice_table
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    from paper_1806_08384_amd import sel as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(sel):
+    c = sel.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def gpu_ids(sel, ctx, dt, prog, n_hint):
+    out = ids_tensor(n_hint, torch)
+    st, cnt = ctx.pushdown_rowids(dt, prog, UINT64_MAX, out)
+    assert st == sel.SEL_OK
+    return cnt, as_u32(out)[:cnt]
+
+
+def check_tree(sel, ctx, dt, orc, tree, ids=True):
+    prog = ctx.program(dt, tree)
+    want = orc.count(tree)
+    got = ctx.count(dt, prog)
+    assert got == want, (tree, prog.listing)
+    if ids:
+        cnt, got_ids = gpu_ids(sel, ctx, dt, prog, want)
+        assert cnt == want
+        np.testing.assert_array_equal(got_ids, orc.rowids(tree))
+    return want
+
+
+def test_cfg1_count_and_ids(sel, ctx):
+    say("cfg1: 1M rows x 3 int32, P1")
+    t = datagen.cfg1()
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    c = check_tree(sel, ctx, dt, orc, datagen.cfg1_predicate())
+    assert 26_000 < c < 28_000
+
+
+@pytest.mark.parametrize("n", [0, 1, 3, 63, 64, 65, 255, 256, 257, 2047, 2048, 2049,
+                               4096 + 5, 8192, 3 * 2048 + 1000, 100_003])
+def test_ragged_sizes_random_programs(sel, ctx, n):
+    say(f"ragged n={n}")
+    rng = np.random.default_rng(10_000 + n)
+    t = datagen.random_table(rng, n, grid=True, null_rate=0.3)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    for k in range(12):
+        tree = sqlite_ref.clamp_literals(datagen.random_tree(rng, t))
+        check_tree(sel, ctx, dt, orc, tree)
+
+
+def test_random_programs_small_ranges(sel, ctx):
+    """Values in a small range so that comparisons split rows evenly."""
+    rng = np.random.default_rng(77)
+    t = datagen.random_table(rng, 50_000, grid=False, null_rate=0.2)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    for k in range(60):
+        tree = datagen.random_tree(rng, t, grid=False)
+        check_tree(sel, ctx, dt, orc, tree, ids=(k % 3 == 0))
+
+
+def test_kleene_single_rows(sel, ctx):
+    """Every (a, b) in {T, U, F}^2 on one-row tables, through the GPU."""
+    from tests.oracle_pins import GOLDEN, SYM, _leaf_table
+    import os
+    vals = {"T": 1, "F": 0, "U": None}
+    with open(os.path.join(GOLDEN, "kleene_k3.txt")) as f:
+        rows = [l.split("#")[0].split() for l in f if l.split("#")[0].strip()]
+    for op, a, b, res in rows:
+        t = _leaf_table([vals[a]])
+        leaf0, leaf1 = ("cmp", 0, "=", 1), ("cmp", 1, "=", 1)
+        if b == "-":
+            tree = ("not", leaf0) if op == "NOT" else ("isunknown", leaf0)
+        else:
+            t.columns[1].data[:] = 0 if vals[b] is None else vals[b]
+            t.columns[1].valid[:] = 0 if vals[b] is None else 1
+            tree = (op.lower(), leaf0, leaf1)
+        dt = sel.device_table(ctx, t)
+        got = ctx.count(dt, ctx.program(dt, tree))
+        assert got == (1 if SYM[res] == oracle.T else 0), (op, a, b)
+
+
+def test_cfg2_small(sel, ctx):
+    say("cfg2 at 2M rows")
+    t = datagen.cfg2(n=2_000_000)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    check_tree(sel, ctx, dt, orc, datagen.cfg2_predicate())
+    for lo, hi in [(0, 0), (0, 2556), (100, 99), (2000, 2600), (-5, 3)]:
+        check_tree(sel, ctx, dt, orc, datagen.cfg2_predicate(lo, hi))
+    # leaf-count sweep (1..8 leaves) and NULL handling on price
+    leaves = [("between", 0, 365, 729), ("cmp", 1, "<", 25), ("between", 2, 5, 7),
+              ("cmp", 3, ">=", 20000), ("in", 5, tuple(range(0, 20, 2))),
+              ("codeset", 6, 4500, datagen.cfg2_like_bitmap()), ("cmp", 4, "<>", 0),
+              ("isnull", 3)]
+    for k in range(1, len(leaves) + 1):
+        check_tree(sel, ctx, dt, orc, ("and", *leaves[:k]) if k > 1 else leaves[0], ids=(k % 2 == 0))
+    check_tree(sel, ctx, dt, orc, ("isunknown", ("cmp", 3, ">=", 20000)))
+    check_tree(sel, ctx, dt, orc, ("not", ("cmp", 3, "<", 20000)))
+
+
+def test_limits_and_capacity(sel, ctx):
+    """Algorithm 1: count > max_rows aborts with nothing written."""
+    t = datagen.cfg1(200_000, seed=5)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    tree = datagen.cfg1_predicate()
+    prog = ctx.program(dt, tree)
+    c = orc.count(tree)
+    ids = orc.rowids(tree)
+    out = ids_tensor(c + 10, torch)
+    st, cnt = ctx.pushdown_rowids(dt, prog, c - 1, out)
+    assert (st, cnt) == (sel.SEL_OVER_LIMIT, c)
+    assert np.all(as_u32(out) == 0xDEADBEEF)
+    st, cnt = ctx.pushdown_rowids(dt, prog, c + 10, out, cap=c - 1)
+    assert (st, cnt) == (sel.SEL_E_CAPACITY, c)
+    assert np.all(as_u32(out) == 0xDEADBEEF)
+    st, cnt = ctx.pushdown_rowids(dt, prog, c, out)
+    assert (st, cnt) == (sel.SEL_OK, c)
+    np.testing.assert_array_equal(as_u32(out)[:c], ids)
+    assert np.all(as_u32(out)[c:] == 0xDEADBEEF)
+    st, cnt = ctx.pushdown_rowids(dt, prog, sel.max_rows(t.nrows, c / t.nrows), out)
+    assert st == sel.SEL_OK
+    # max_rows = 0 with an empty result is accepted (strict >)
+    p0 = ctx.program(dt, ("false",))
+    assert ctx.pushdown_rowids(dt, p0, 0, out) == (sel.SEL_OK, 0)
+
+
+def test_launch_shapes_agree(sel, ctx):
+    """Results do not depend on block size or grid size (ordered compaction
+    and exact counts under any workgroup interleaving)."""
+    t = datagen.cfg2(n=1_000_003, seed=12)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    tree = datagen.cfg2_predicate(0, 1200)
+    want = orc.count(tree)
+    want_ids = orc.rowids(tree)
+    prog = ctx.program(dt, tree)
+    try:
+        for block, grid in [(64, 1), (64, 7), (128, 33), (256, 0), (256, 3), (128, 10_000)]:
+            ctx.set_launch(block, grid)
+            assert ctx.count(dt, prog) == want, (block, grid)
+            cnt, ids = gpu_ids(sel, ctx, dt, prog, want)
+            assert cnt == want
+            np.testing.assert_array_equal(ids, want_ids)
+    finally:
+        ctx.set_launch(None)
+
+
+def test_async_count(sel, ctx):
+    t = datagen.cfg1(300_000, seed=8)
+    dt = sel.device_table(ctx, t)
+    tree = datagen.cfg1_predicate()
+    prog = ctx.program(dt, tree)
+    out = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for k in range(4):
+        ctx.count_async(dt, prog, out.data_ptr() + 8 * k)
+    torch.cuda.synchronize()
+    want = oracle.Oracle(t).count(tree)
+    assert out.cpu().tolist() == [want] * 4
+
+
+def star_setup(sel, ctx, fact_rows, dim_rows):
+    dims = datagen.star_dims(sizes=dim_rows)
+    preds = datagen.star_dim_predicates()
+    fact = datagen.star_fact(fact_rows, dim_rows=dim_rows)
+    return dims, preds, fact
+
+
+def test_keybitmaps_and_star(sel, ctx):
+    dim_rows = (2556, 3000, 20_000, 320_000)
+    dims, preds, fact = star_setup(sel, ctx, 3_000_003, dim_rows)
+    bitmaps_gpu, bitmaps_cpu, nbits = [], [], []
+    for d, (t, p) in enumerate(zip(dims, preds)):
+        dt = sel.device_table(ctx, t)
+        prog = ctx.program(dt, p)
+        bm = torch.full(((t.nrows + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+        st, cnt = ctx.pushdown_keybitmap(dt, 0, 0, prog, bm, t.nrows)
+        ost, ocnt, owords = oracle.Oracle(t).keybitmap(p, 0, 0, t.nrows)
+        assert st == sel.SEL_OK and ost == 0 and cnt == ocnt
+        np.testing.assert_array_equal(as_u32(bm), owords)
+        bitmaps_gpu.append(bm)
+        bitmaps_cpu.append(owords)
+        nbits.append(t.nrows)
+    dfact = sel.device_table(ctx, fact)
+    ofact = oracle.Oracle(fact)
+    want = ofact.star_count([0, 1, 2, 3], bitmaps_cpu, nbits, threads=8)
+    got = ctx.star_count(dfact, [0, 1, 2, 3], bitmaps_gpu, nbits)
+    assert got == want
+    fp = datagen.star_fact_predicate()
+    want2 = ofact.star_count([0, 1, 2, 3], bitmaps_cpu, nbits, fp, threads=8)
+    got2 = ctx.star_count(dfact, [0, 1, 2, 3], bitmaps_gpu, nbits, ctx.program(dfact, fp))
+    assert got2 == want2
+    # a subset of dimensions, and a single one
+    assert ctx.star_count(dfact, [1, 3], [bitmaps_gpu[1], bitmaps_gpu[3]], [nbits[1], nbits[3]]) == \
+        ofact.star_count([1, 3], [bitmaps_cpu[1], bitmaps_cpu[3]], [nbits[1], nbits[3]], threads=8)
+    assert ctx.star_count(dfact, [0], [bitmaps_gpu[0]], [nbits[0]]) == \
+        ofact.star_count([0], [bitmaps_cpu[0]], [nbits[0]], threads=8)
+
+
+def test_keybitmap_edges(sel, ctx):
+    t = datagen.star_dims(sizes=(100, 40, 70, 33))[1]
+    dt = sel.device_table(ctx, t)
+    bm = torch.zeros(8, dtype=torch.int32, device="cuda")
+    # every row qualifies (no program), keys offset by key_min
+    st, cnt = ctx.pushdown_keybitmap(dt, 0, -3, None, bm, 43)
+    ost, ocnt, owords = oracle.Oracle(t).keybitmap(None, 0, -3, 43)
+    assert (st, cnt) == (sel.SEL_OK, ocnt) and ost == 0
+    np.testing.assert_array_equal(as_u32(bm)[:len(owords)], owords)
+    # a qualifying key outside [key_min, key_min + nbits) is reported
+    st, cnt = ctx.pushdown_keybitmap(dt, 0, 5, None, bm, 40)
+    assert st == sel.SEL_E_RANGE
+
+
+def test_cfg2_full_size(sel, ctx):
+    """cfg2 at its full 300M rows in the default launch shape: exact count
+    against the threaded oracle; row ids checked whole for properties and
+    against the oracle on sampled row ranges."""
+    say("cfg2 full: generating 300M rows")
+    t = datagen.cfg2()
+    dt = sel.device_table(ctx, t)
+    tree = datagen.cfg2_predicate()
+    prog = ctx.program(dt, tree)
+    say("cfg2 full: GPU count")
+    got = ctx.count(dt, prog)
+    say("cfg2 full: oracle count")
+    orc = oracle.Oracle(t)
+    want = orc.count(tree, threads=16)
+    assert got == want
+    say(f"cfg2 full: count {got}; GPU row ids")
+    out = torch.empty(got + 16, dtype=torch.int32, device="cuda")
+    st, cnt = ctx.pushdown_rowids(dt, prog, UINT64_MAX, out)
+    assert (st, cnt) == (sel.SEL_OK, want)
+    ids = as_u32(out)[:cnt].astype(np.int64)
+    assert np.all(np.diff(ids) > 0)
+    rng = np.random.default_rng(3)
+    for k in range(6):
+        lo = int(rng.integers(0, t.nrows - 3_000_000)) // 32 * 32
+        hi = lo + 2_000_000 + int(rng.integers(0, 1000))
+        sub = slice_table(t, lo, hi)
+        want_ids = oracle.Oracle(sub).rowids(tree).astype(np.int64) + lo
+        got_ids = ids[(ids >= lo) & (ids < hi)]
+        np.testing.assert_array_equal(got_ids, want_ids)
+    del dt, out
+    torch.cuda.empty_cache()
