@@ -70,6 +70,9 @@ def main():
     ap.add_argument("--rows", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=50)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB once (a plain "
+                         "copy kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -201,6 +204,16 @@ def main():
             "sample": f"the full {n}-row table, COUNT only (the oracle's count), "
                       f"row ranges split over {threads} threads; {dt_cpu:.2f} s wall",
         }
+    if args.copy_probe_mb:
+        nb = args.copy_probe_mb << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        a.fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nb} bytes read and {nb} bytes written")
+        del a, b
     print(json.dumps(out), flush=True)
     ctx.close()
 

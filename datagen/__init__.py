@@ -322,7 +322,9 @@ def random_table(rng: np.random.Generator, n: int, types=("i8", "i16", "i32", "i
             data = vals[rng.integers(0, len(vals), n)]
         else:
             data = rng.integers(-20, 21, n).astype(NP_DTYPE[ty])
-        col = Column(f"x{k}", ty, np.ascontiguousarray(data))
+        # dictionary-coded (so code-set tests apply); most grid values are
+        # outside [0, dict_card), which a code-set test treats as FALSE
+        col = Column(f"x{k}", ty, np.ascontiguousarray(data), dict_card=64)
         if null_rate > 0 and rng.random() < 0.75:
             isnull = rng.random(n) < null_rate
             words = np.zeros((n + 31) // 32, dtype=np.uint32)

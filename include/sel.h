@@ -30,7 +30,8 @@
  *  - Column data must be 16-byte aligned; validity bitmaps 4-byte aligned.
  *  - Synchronous calls return after results are on the host.  *_async
  *    calls only enqueue work on the context's stream.
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time.  Tables and programs
+ *    made from a context are destroyed before it.
  *  - Rows are numbered 0..nrows-1; nrows < 2^32 (row ids are uint32).
  *
  * Truth values follow SQL three-valued (Kleene) logic: a comparison on a

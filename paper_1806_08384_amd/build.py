@@ -21,7 +21,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
 # device code: gfx950 only; packed fp32 VALU ops stay disabled (no float
 # arithmetic on this path, but the rule holds for every HIP object here)
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-mcode-object-version=5"]
 
 
 def _run(cmd, verbose):

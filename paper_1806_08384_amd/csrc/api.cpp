@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,6 +23,62 @@ thread_local std::string g_create_error;
 struct EventPair {
   hipEvent_t a, b;
 };
+
+// First-fit allocator over one device buffer, for compiled programs: a
+// compile then costs one async copy instead of a hipMalloc.  Blocks are
+// reused in stream order (all work of a context runs on its one stream), so
+// a kernel still reading a freed program finishes before the next copy into
+// that block.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  void init(char* base, size_t size) {
+    base_ = base;
+    free_.clear();
+    free_[0] = size;
+  }
+  char* alloc(size_t n) {
+    n = (n + kAlign - 1) & ~(kAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, left = it->second - n;
+        free_.erase(it);
+        if (left) free_[off + n] = left;
+        used_[off] = n;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  bool owns(const void* p) const { return base_ && used_.count((size_t)((const char*)p - base_)); }
+  void release(void* p) {
+    auto u = used_.find((size_t)((char*)p - base_));
+    if (u == used_.end()) return;
+    size_t off = u->first, n = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+
+ private:
+  char* base_ = nullptr;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  std::map<size_t, size_t> used_;
+};
+
+constexpr size_t kArenaBytes = 8u << 20;
+constexpr size_t kStageBytes = 1u << 20;
 }  // namespace
 
 struct sel_ctx {
@@ -34,9 +91,12 @@ struct sel_ctx {
   DevSlot* slot = nullptr;                 // device
   unsigned long long* dout = nullptr;      // device, 2 values
   unsigned long long* hout = nullptr;      // pinned host, 2 values
-  DevInstr* hstage = nullptr;              // pinned host staging for dstar
+  char* hstage = nullptr;                  // pinned host staging (kStageBytes)
+  hipEvent_t stage_free = nullptr;         // recorded after each copy out of hstage
   DevInstr* dstar = nullptr;               // device, star-count program (128)
   DevInstr* dtrue = nullptr;               // device, the program TRUE
+  void* arena_mem = nullptr;               // device, programs
+  Arena arena;
   void* scratch = nullptr;                 // device, grow-only
   size_t scratch_bytes = 0;
 
@@ -60,7 +120,8 @@ struct sel_table {
 struct sel_program {
   sel_ctx* ctx;
   const sel_table* table;
-  void* dev = nullptr;              // one allocation: code then blob
+  void* dev = nullptr;              // code then blob: in the context's arena,
+  bool own_alloc = false;           // or its own hipMalloc if the arena is full
   DevInstr* dcode = nullptr;
   std::vector<DevInstr> host_code;  // with device pointers (for star programs)
   uint32_t nins = 0;
@@ -181,6 +242,8 @@ void scan_shape(sel_ctx* ctx, int mode, uint64_t ntiles, uint32_t& grid, uint32_
   if (ctx->launch.grid) {
     g = ctx->launch.grid;
   } else {
+    // 16 resident waves per CU (fewer if occupancy is lower): more waves
+    // per CU measured slower on the 300M-row scan (HBM contention)
     int occ = 0;
     if (block == 256) {
       occ = ctx->occ[mode];
@@ -188,7 +251,8 @@ void scan_shape(sel_ctx* ctx, int mode, uint64_t ntiles, uint32_t& grid, uint32_
       occ = 1;
     }
     if (occ < 1) occ = 1;
-    g = (uint64_t)occ * ctx->num_cus;
+    const int per_cu = std::min(occ, (int)(16 * kWave / block));
+    g = (uint64_t)per_cu * ctx->num_cus;
   }
   grid = (uint32_t)std::min<uint64_t>(need, std::max<uint64_t>(g, 1));
 }
@@ -213,6 +277,17 @@ sel_status run_scan(sel_ctx* ctx, int mode, ScanArgs& a, int kind) {
   int e = sel_launch_scan(mode, a, grid, block, ctx->stream);
   tl.done();
   if (e != 0) return hip_err(ctx, (hipError_t)e, "scan kernel launch");
+  return SEL_OK;
+}
+
+// Copy host bytes to device memory in stream order through the pinned
+// staging buffer (which is free once the previous such copy has run).
+sel_status stage_copy(sel_ctx* ctx, void* dst, const void* src, size_t n) {
+  if (n > kStageBytes) return set_err(ctx, SEL_E_INVALID, "staged copy too large");
+  HIP_TRY(ctx, hipEventSynchronize(ctx->stage_free), "hipEventSynchronize");
+  std::memcpy(ctx->hstage, src, n);
+  HIP_TRY(ctx, hipMemcpyAsync(dst, ctx->hstage, n, hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync(stage)");
+  HIP_TRY(ctx, hipEventRecord(ctx->stage_free, ctx->stream), "hipEventRecord");
   return SEL_OK;
 }
 
@@ -260,6 +335,24 @@ extern "C" {
 
 // ---------------------------------------------------------------- context --
 
+namespace {
+void release_ctx(sel_ctx* ctx) {
+  for (auto& p : ctx->pending) ctx->free_events.push_back(p.second);
+  for (auto& p : ctx->free_events) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  if (ctx->stage_free) (void)hipEventDestroy(ctx->stage_free);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
+  if (ctx->slot) (void)hipFree(ctx->slot);
+  if (ctx->hout) (void)hipHostFree(ctx->hout);
+  if (ctx->hstage) (void)hipHostFree(ctx->hstage);
+  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+}  // namespace
+
 sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
   if (!out) return set_err(nullptr, SEL_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -271,50 +364,38 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
   if (!ctx) return set_err(nullptr, SEL_E_NOMEM, "host allocation failed");
   ctx->device = device;
   DeviceGuard g(device);
-  hipDeviceProp_t prop;
-  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
-    delete ctx;
-    return hip_err(nullptr, e, "hipGetDeviceProperties");
-  }
-  ctx->num_cus = (uint32_t)prop.multiProcessorCount;
-  if (hip_stream) {
-    ctx->stream = (hipStream_t)hip_stream;
-  } else {
-    if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) {
-      delete ctx;
-      return hip_err(nullptr, e, "hipStreamCreate");
+  const char* where = "";
+  do {
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) { where = "hipGetDeviceProperties"; break; }
+    ctx->num_cus = (uint32_t)prop.multiProcessorCount;
+    if (hip_stream) {
+      ctx->stream = (hipStream_t)hip_stream;
+    } else {
+      if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { where = "hipStreamCreate"; break; }
+      ctx->own_stream = true;
     }
-    ctx->own_stream = true;
-  }
-  void* dmem = nullptr;
-  const size_t dbytes = 256 + 129 * sizeof(DevInstr);
-  if ((e = hipMalloc(&dmem, dbytes)) != hipSuccess || (e = hipMemset(dmem, 0, dbytes)) != hipSuccess) {
-    if (dmem) (void)hipFree(dmem);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-    delete ctx;
-    return hip_err(nullptr, e, "hipMalloc(ctx)");
-  }
-  ctx->slot = (DevSlot*)dmem;
-  ctx->dout = (unsigned long long*)((char*)dmem + 128);
-  ctx->dstar = (DevInstr*)((char*)dmem + 256);
-  ctx->dtrue = ctx->dstar + 128;
-  if ((e = hipHostMalloc((void**)&ctx->hout, 64 + 128 * sizeof(DevInstr), hipHostMallocDefault)) != hipSuccess) {
-    (void)hipFree(dmem);
-    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-    delete ctx;
-    return hip_err(nullptr, e, "hipHostMalloc");
-  }
-  ctx->hstage = (DevInstr*)((char*)ctx->hout + 64);
-  {
+    void* dmem = nullptr;
+    const size_t dbytes = 256 + 129 * sizeof(DevInstr);
+    if ((e = hipMalloc(&dmem, dbytes)) != hipSuccess) { where = "hipMalloc(ctx)"; break; }
+    ctx->slot = (DevSlot*)dmem;
+    if ((e = hipMemset(dmem, 0, dbytes)) != hipSuccess) { where = "hipMemset(ctx)"; break; }
+    ctx->dout = (unsigned long long*)((char*)dmem + 128);
+    ctx->dstar = (DevInstr*)((char*)dmem + 256);
+    ctx->dtrue = ctx->dstar + 128;
+    if ((e = hipMalloc(&ctx->arena_mem, kArenaBytes)) != hipSuccess) { where = "hipMalloc(arena)"; break; }
+    ctx->arena.init((char*)ctx->arena_mem, kArenaBytes);
+    if ((e = hipHostMalloc((void**)&ctx->hout, 64, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
+    if ((e = hipHostMalloc((void**)&ctx->hstage, kStageBytes, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
+    if ((e = hipEventCreateWithFlags(&ctx->stage_free, hipEventDisableTiming)) != hipSuccess) { where = "hipEventCreate"; break; }
     DevInstr t{};
     t.op = D_TRUE;
-    if ((e = hipMemcpy(ctx->dtrue, &t, sizeof t, hipMemcpyHostToDevice)) != hipSuccess) {
-      (void)hipHostFree(ctx->hout);
-      (void)hipFree(dmem);
-      if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-      delete ctx;
-      return hip_err(nullptr, e, "hipMemcpy(ctx)");
-    }
+    if ((e = hipMemcpy(ctx->dtrue, &t, sizeof t, hipMemcpyHostToDevice)) != hipSuccess) { where = "hipMemcpy(ctx)"; break; }
+  } while (0);
+  if (e != hipSuccess) {
+    sel_status st = hip_err(nullptr, e, where);
+    release_ctx(ctx);
+    return st;
   }
   for (int m = 0; m < 3; ++m)
     if (sel_scan_occupancy(m, 256, &ctx->occ[m]) != 0 || ctx->occ[m] < 1) ctx->occ[m] = 1;
@@ -326,16 +407,7 @@ void sel_ctx_destroy(sel_ctx* ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (auto& p : ctx->pending) ctx->free_events.push_back(p.second);
-  for (auto& p : ctx->free_events) {
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
-  }
-  if (ctx->scratch) (void)hipFree(ctx->scratch);
-  if (ctx->slot) (void)hipFree(ctx->slot);
-  if (ctx->hout) (void)hipHostFree(ctx->hout);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-  delete ctx;
+  release_ctx(ctx);
 }
 
 const char* sel_last_error(const sel_ctx* ctx) {
@@ -458,10 +530,14 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   p->text = L.text;
   const size_t code_bytes = L.code.size() * sizeof(DevInstr);
   const size_t total = code_bytes + L.blob.size();
-  hipError_t he = hipMalloc(&p->dev, total);
-  if (he != hipSuccess) {
-    delete p;
-    return hip_err(ctx, he, "hipMalloc(program)");
+  p->dev = ctx->arena.alloc(total);
+  if (!p->dev) {
+    hipError_t he = hipMalloc(&p->dev, total);
+    if (he != hipSuccess) {
+      delete p;
+      return hip_err(ctx, he, "hipMalloc(program)");
+    }
+    p->own_alloc = true;
   }
   p->dcode = (DevInstr*)p->dev;
   const uintptr_t blob_base = (uintptr_t)p->dev + code_bytes;
@@ -470,11 +546,12 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   std::vector<uint8_t> host(total);
   std::memcpy(host.data(), L.code.data(), code_bytes);
   if (!L.blob.empty()) std::memcpy(host.data() + code_bytes, L.blob.data(), L.blob.size());
-  he = hipMemcpy(p->dev, host.data(), total, hipMemcpyHostToDevice);
-  if (he != hipSuccess) {
-    (void)hipFree(p->dev);
+  sel_status cst = stage_copy(ctx, p->dev, host.data(), total);
+  if (cst != SEL_OK) {
+    if (p->own_alloc) (void)hipFree(p->dev);
+    else ctx->arena.release(p->dev);
     delete p;
-    return hip_err(ctx, he, "hipMemcpy(program)");
+    return cst;
   }
   p->host_code = L.code;
   double bpr = 0.0;
@@ -489,8 +566,12 @@ void sel_program_destroy(sel_program* p) {
   if (!p) return;
   if (p->dev) {
     DeviceGuard g(p->ctx->device);
-    (void)hipStreamSynchronize(p->ctx->stream);
-    (void)hipFree(p->dev);
+    if (p->own_alloc) {
+      (void)hipStreamSynchronize(p->ctx->stream);
+      (void)hipFree(p->dev);
+    } else {
+      p->ctx->arena.release(p->dev);  // reused in stream order
+    }
   }
   delete p;
 }
@@ -554,11 +635,15 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   const uint64_t ntiles = ntiles_of(table->nrows);
   const size_t mask_bytes = (size_t)ntiles * kWave * 4;
   const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
-  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 256);
+  const size_t chunk_bytes = 2048 * 4;
+  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * chunk_bytes);
   if (st != SEL_OK) return st;
-  uint32_t* mask = (uint32_t*)ctx->scratch;
-  uint32_t* counts = (uint32_t*)((char*)ctx->scratch + mask_bytes);
-  uint32_t* offsets = (uint32_t*)((char*)ctx->scratch + mask_bytes + counts_bytes);
+  char* sp = (char*)ctx->scratch;
+  uint32_t* mask = (uint32_t*)sp;
+  uint32_t* counts = (uint32_t*)(sp + mask_bytes);
+  uint32_t* offsets = (uint32_t*)(sp + mask_bytes + counts_bytes);
+  uint32_t* chunk_sums = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes);
+  uint32_t* chunk_offs = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes + chunk_bytes);
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
@@ -578,18 +663,21 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   if (count == 0) return SEL_OK;
   {
     TimedLaunch tl(ctx, SEL_K_SCAN);
-    int e = sel_launch_scan_tiles(counts, offsets, ntiles, ctx->stream);
+    int e = sel_launch_scan_tiles(counts, offsets, chunk_sums, chunk_offs, ntiles, ctx->stream);
     tl.done();
     if (e) return hip_err(ctx, (hipError_t)e, "tile scan launch");
   }
   CompactArgs c{};
   c.mask = mask;
   c.offsets = offsets;
+  c.chunk_offs = chunk_offs;
   c.ntiles = ntiles;
   c.out = d_out;
   c.cap = cap;
-  uint32_t grid, block;
-  scan_shape(ctx, M_MASK, ntiles, grid, block);
+  // one wave per tile: compaction is latency-bound, so every tile gets a
+  // wave of its own rather than a grid-stride loop
+  const uint32_t block = 256;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((ntiles + 15) / 16, 1u << 20);
   {
     TimedLaunch tl(ctx, SEL_K_COMPACT);
     int e = sel_launch_compact(c, grid, block, ctx->stream);
@@ -698,10 +786,8 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
   }
   if (code.size() > 128) return set_err(ctx, SEL_E_INVALID, "combined program too long");
   DeviceGuard g(ctx->device);
-  // the staging buffer is free: every earlier call on this context synchronised
-  std::memcpy(ctx->hstage, code.data(), code.size() * sizeof(DevInstr));
-  HIP_TRY(ctx, hipMemcpyAsync(ctx->dstar, ctx->hstage, code.size() * sizeof(DevInstr),
-                              hipMemcpyHostToDevice, ctx->stream), "hipMemcpyAsync(star program)");
+  sel_status sst = stage_copy(ctx, ctx->dstar, code.data(), code.size() * sizeof(DevInstr));
+  if (sst != SEL_OK) return sst;
   ScanArgs a{};
   a.prog = ctx->dstar;
   a.nins = (uint32_t)code.size();

@@ -6,7 +6,8 @@
 //                       (Algorithm 1: count first, then materialise)
 //  k_scan<M_KEYBITMAP>  same, setting bit (key - key_min) for every TRUE
 //                       row of a pushed-down dimension (Ch.3 sec.3.3)
-//  k_scan_tiles         exclusive scan of the per-tile counts
+//  k_chunk_scan,        exclusive scan of the per-tile counts (two levels)
+//  k_chunk_offsets
 //  k_compact            mask -> ascending row ids (LDS-free wave prefix by
 //                       ballot + mbcnt)
 //
@@ -385,63 +386,114 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   finish(a.slot, a.out, cnt, oor, MODE == M_KEYBITMAP);
 }
 
-// Exclusive scan of n tile counts by one workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_scan_tiles(const uint32_t* __restrict__ counts,
-                                                     uint32_t* __restrict__ offsets, uint64_t n) {
-  __shared__ uint32_t part[1024];
-  const uint32_t tid = threadIdx.x;
-  const uint64_t chunk = (n + 1023) / 1024;
-  const uint64_t lo = tid * chunk < n ? tid * chunk : n;
-  const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-  uint32_t s = 0;
-  for (uint64_t i = lo; i < hi; ++i) s += counts[i];
-  part[tid] = s;
+// Exclusive scan of the tile counts in two levels.  k_chunk_scan: one
+// workgroup of 1024 threads per chunk of 1024 tiles writes each tile's
+// offset within its chunk and the chunk's total.  k_chunk_offsets: one
+// workgroup scans the chunk totals (at most 2048 for 2^32 rows).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, uint32_t lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= (uint32_t)off) x += y;
+  }
+  return x;
+}
+
+// exclusive prefix of v over the (up to 1024) threads of the block
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t inc = wave_incl_scan(v, lane);
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
-  for (uint32_t off = 1; off < 1024; off <<= 1) {
-    const uint32_t v = tid >= off ? part[tid - off] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
+  if (wave == 0) {
+    const uint32_t nw = blockDim.x >> 6;
+    const uint32_t w = lane < nw ? wsum[lane] : 0u;
+    const uint32_t wi = wave_incl_scan(w, lane);
+    if (lane < nw) wsum[lane] = wi - w;
   }
-  uint32_t run = part[tid] - s;  // exclusive prefix of this thread's chunk
-  for (uint64_t i = lo; i < hi; ++i) {
-    const uint32_t c = counts[i];
-    offsets[i] = run;
-    run += c;
-  }
+  __syncthreads();
+  return wsum[wave] + inc - v;
+}
+
+__global__ void __launch_bounds__(1024) k_chunk_scan(const uint32_t* __restrict__ counts,
+                                                     uint32_t* __restrict__ offsets,
+                                                     uint32_t* __restrict__ chunk_sums, uint64_t n) {
+  __shared__ uint32_t tot;
+  const uint64_t i = (uint64_t)blockIdx.x * 1024 + threadIdx.x;
+  const uint32_t v = i < n ? counts[i] : 0u;
+  const uint32_t ex = block_excl_scan(v);
+  if (i < n) offsets[i] = ex;
+  if (threadIdx.x == 1023) tot = ex + v;
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_sums[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_chunk_offsets(const uint32_t* __restrict__ chunk_sums,
+                                                        uint32_t* __restrict__ chunk_offs,
+                                                        uint64_t nchunks) {
+  // two chunks per thread: up to 2048 chunks
+  const uint64_t i0 = 2 * (uint64_t)threadIdx.x, i1 = i0 + 1;
+  const uint32_t a = i0 < nchunks ? chunk_sums[i0] : 0u;
+  const uint32_t b = i1 < nchunks ? chunk_sums[i1] : 0u;
+  const uint32_t ex = block_excl_scan(a + b);
+  if (i0 < nchunks) chunk_offs[i0] = ex;
+  if (i1 < nchunks) chunk_offs[i1] = ex + a;
 }
 
 // Row ids of TRUE rows in ascending order: rows are ordered (step j, lane,
 // i), so a row's rank is the tile offset + TRUE rows of earlier steps +
 // TRUE rows of this step in lower lanes (ballot per bit plane, mbcnt) +
-// TRUE rows earlier in the lane's own nibble.
+// TRUE rows earlier in the lane's own nibble.  Each wave takes kCompactTiles
+// consecutive tiles and issues all their loads before using any.
+constexpr int kCompactTiles = 4;
+
+__device__ __forceinline__ void compact_tile(uint32_t w, uint64_t base, uint64_t tile,
+                                             uint32_t lane, uint32_t* __restrict__ out,
+                                             uint64_t cap) {
+  const uint64_t tb = tile * kTileRows;
+#pragma unroll
+  for (int j = 0; j < kSteps; ++j) {
+    const uint32_t nib = (w >> (4 * j)) & 0xFu;
+    uint32_t below = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const unsigned long long bal = __ballot((nib >> i) & 1u);
+      below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, below));
+      total += (uint32_t)__builtin_popcountll(bal);
+    }
+    uint64_t pos = base + below;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if ((nib >> i) & 1u) {
+        if (pos < cap) out[pos] = (uint32_t)(tb + 256u * j + 4u * lane + i);
+        ++pos;
+      }
+    }
+    base += total;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
-  const uint64_t W = (uint64_t)gridDim.x * nw;
-  for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
-    const uint32_t w = a.mask[tile * kWave + lane];
-    uint64_t base = uni(a.offsets[tile]);
-    const uint64_t tb = tile * kTileRows;
+  const uint64_t step = (uint64_t)gridDim.x * nw * kCompactTiles;
+  for (uint64_t t0 = uni64(((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)) * kCompactTiles);
+       t0 < a.ntiles; t0 += step) {
+    uint32_t w[kCompactTiles];
+    uint32_t off[kCompactTiles], coff[kCompactTiles];
 #pragma unroll
-    for (int j = 0; j < kSteps; ++j) {
-      const uint32_t nib = (w >> (4 * j)) & 0xFu;
-      uint32_t below = 0, total = 0;
+    for (int k = 0; k < kCompactTiles; ++k) {
+      const uint64_t tile = t0 + k;
+      const bool in = tile < a.ntiles;
+      w[k] = in ? a.mask[tile * kWave + lane] : 0u;
+      off[k] = in ? a.offsets[tile] : 0u;
+      coff[k] = in ? a.chunk_offs[tile >> 10] : 0u;
+    }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const unsigned long long bal = __ballot((nib >> i) & 1u);
-        below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, below));
-        total += (uint32_t)__builtin_popcountll(bal);
-      }
-      uint64_t pos = base + below;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if ((nib >> i) & 1u) {
-          if (pos < a.cap) a.out[pos] = (uint32_t)(tb + 256u * j + 4u * lane + i);
-          ++pos;
-        }
-      }
-      base += total;
+    for (int k = 0; k < kCompactTiles; ++k) {
+      if (__ballot(w[k] != 0u) == 0ull) continue;  // no TRUE row in the tile
+      compact_tile(w[k], (uint64_t)uni(coff[k]) + uni(off[k]), t0 + k, lane, a.out, a.cap);
     }
   }
 }
@@ -463,8 +515,15 @@ int sel_launch_scan(int mode, const ScanArgs& a, uint32_t grid, uint32_t block, 
   return (int)hipGetLastError();
 }
 
-int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint64_t n, void* stream) {
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, (hipStream_t)stream, counts, offsets, n);
+int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* chunk_sums,
+                          uint32_t* chunk_offs, uint64_t n, void* stream) {
+  const uint64_t nchunks = (n + 1023) / 1024;
+  if (nchunks == 0) return 0;
+  if (nchunks > 2048) return (int)hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chunk_scan, dim3((uint32_t)nchunks), dim3(1024), 0, (hipStream_t)stream,
+                     counts, offsets, chunk_sums, n);
+  hipLaunchKernelGGL(k_chunk_offsets, dim3(1), dim3(1024), 0, (hipStream_t)stream, chunk_sums,
+                     chunk_offs, nchunks);
   return (int)hipGetLastError();
 }
 

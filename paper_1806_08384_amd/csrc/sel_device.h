@@ -91,7 +91,8 @@ struct ScanArgs {
 
 struct CompactArgs {
   const uint32_t* mask;
-  const uint32_t* offsets;     // exclusive prefix of tile counts
+  const uint32_t* offsets;     // exclusive prefix of tile counts within a chunk
+  const uint32_t* chunk_offs;  // exclusive prefix of chunk (1024 tiles) totals
   uint64_t ntiles;
   uint32_t* out;
   uint64_t cap;
@@ -102,7 +103,8 @@ struct CompactArgs {
 // Launchers implemented in kernels.hip (return hipError_t as int).
 extern "C++" {
 int sel_launch_scan(int mode, const sel::ScanArgs& a, uint32_t grid, uint32_t block, void* stream);
-int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint64_t n, void* stream);
+int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* chunk_sums,
+                          uint32_t* chunk_offs, uint64_t n, void* stream);
 int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
 int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);

@@ -12,8 +12,13 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
+# torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+# libsel binds to, so the process holds a single HIP runtime and both share
+# devices, streams and memory.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsel.so")
@@ -211,9 +216,17 @@ class Context:
             raise SelError(st, sel_last_error(None).decode())
         self.h = h
         self.device = device
+        self._children = weakref.WeakSet()
 
     def close(self):
+        """Destroy the context after every table and program made from it."""
         if self.h:
+            kids = list(self._children)
+            for k in kids:
+                if isinstance(k, Program):
+                    k.destroy()
+            for k in kids:
+                k.destroy()
             sel_ctx_destroy(self.h)
             self.h = None
 
@@ -309,12 +322,16 @@ class DeviceTable:
         h = _vp()
         ctx.check(sel_table_create(ctx.h, nrows, len(cols), arr, ctypes.byref(h)))
         self.h = h
+        ctx._children.add(self)
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            sel_table_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
-            if self.h:
-                sel_table_destroy(self.h)
-                self.h = None
+            self.destroy()
         except Exception:
             pass
 
@@ -329,6 +346,7 @@ class Program:
         ctx.check(sel_program_compile(ctx.h, table.h, code, len(code), pbuf, len(pool),
                                       ctypes.byref(h)))
         self.h = h
+        ctx._children.add(self)
 
     @property
     def listing(self) -> str:
@@ -338,11 +356,14 @@ class Program:
     def bytes_per_row(self) -> float:
         return float(sel_program_bytes_per_row(self.h))
 
+    def destroy(self):
+        if getattr(self, "h", None):
+            sel_program_destroy(self.h)
+            self.h = None
+
     def __del__(self):
         try:
-            if self.h:
-                sel_program_destroy(self.h)
-                self.h = None
+            self.destroy()
         except Exception:
             pass
 
