@@ -62,6 +62,130 @@ def cpu_baseline(table, tree, threads):
     return c, dt
 
 
+def _timed(fn, reps):
+    """Median wall time of fn() over reps runs, in ms (fn synchronises)."""
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = fn()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], r
+
+
+def bench_batch(ctx, fact_dt, fact_table, threads, log):
+    """64 candidate predicates (2-8 leaves, selectivity 1e-5..0.9) over four
+    tables of 10k / 2M / 60M / 300M rows: one persistent launch (eager and
+    graph-replayed) against 64 plain count launches.  The 300M-row table is
+    the resident fact table (same schema)."""
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+    log("batch: generating the 10k / 2M / 60M-row tables")
+    small = datagen.cfg3_tables(rows=datagen.CFG3_ROWS[:3], threads=threads)
+    dts = [sel.device_table(ctx, t) for t in small] + [fact_dt]
+    progs = datagen.cfg3_programs()
+    pairs = [(dts[t], ctx.program(dts[t], tree)) for t, tree in progs]
+    reps = 5
+    for _ in range(2):
+        want = [ctx.count(t, p) for t, p in pairs]
+
+    def plain_sync():
+        return [ctx.count(t, p) for t, p in pairs]
+
+    d_out = torch.zeros(len(pairs), dtype=torch.int64, device="cuda")
+
+    def plain_async():
+        for i, (t, p) in enumerate(pairs):
+            ctx.count_async(t, p, d_out.data_ptr() + 8 * i)
+        torch.cuda.synchronize()
+        return d_out.cpu().tolist()
+
+    def eager():
+        return ctx.count_batch(pairs)
+
+    b = ctx.batch(pairs)
+    t_sync, r1 = _timed(plain_sync, reps)
+    t_async, r2 = _timed(plain_async, reps)
+    t_eager, r3 = _timed(eager, reps)
+    t_graph, r4 = _timed(b.run, reps)
+    assert r1 == want and r2 == want and r3 == want and r4 == want, "batch counts differ"
+    # bytes: plain reads each program's columns; the batch reads each table's
+    # union of referenced columns once from HBM
+    plain_bytes = sum(t.nrows * p.bytes_per_row for t, p in pairs)
+    best_plain = min(t_sync, t_async)
+    res = {
+        "programs": len(pairs),
+        "tables_rows": [int(datagen.CFG3_ROWS[0]), int(datagen.CFG3_ROWS[1]),
+                        int(datagen.CFG3_ROWS[2]), int(fact_table.nrows)],
+        "plain_sync_ms": t_sync,
+        "plain_async_ms": t_async,
+        "batch_eager_ms": t_eager,
+        "batch_graph_ms": t_graph,
+        "speedup_vs_best_plain": best_plain / t_graph,
+        "plain_bytes": plain_bytes,
+        "counts_equal": True,
+    }
+    b.destroy()
+    for t, p in pairs:
+        p.destroy()
+    for d in dts[:3]:
+        d.destroy()
+    return res
+
+
+def bench_star(ctx, fact_rows, threads, log):
+    """Star push-down: dimension predicates become key bitmaps (2556 / 30k /
+    200k / 3.2M-row dimensions), then the exact fact count by a conjunctive
+    bitmap semi-join probe over a 480M-row fact table (4 int32 foreign keys)."""
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+    log(f"star: generating dimensions and a {fact_rows}-row fact table")
+    dims = datagen.star_dims()
+    preds = datagen.star_dim_predicates()
+    fact = datagen.star_fact(fact_rows, threads=threads)
+    ddims = [sel.device_table(ctx, d) for d in dims]
+    dfact = sel.device_table(ctx, fact)
+    del fact
+    bitmaps, nbits, dim_ms = [], [], []
+    for d, p in zip(ddims, preds):
+        prog = ctx.program(d, p)
+        bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+        ms, (st, c) = _timed(lambda: ctx.pushdown_keybitmap(d, 0, 0, prog, bm, d.nrows), 5)
+        assert st == sel.SEL_OK
+        bitmaps.append(bm)
+        nbits.append(d.nrows)
+        dim_ms.append(ms)
+    fk = [0, 1, 2, 3]
+    for _ in range(3):
+        c = ctx.star_count(dfact, fk, bitmaps, nbits)
+    ctx.read_timing(reset=True)
+    reps = 10
+    for _ in range(reps):
+        c2 = ctx.star_count(dfact, fk, bitmaps, nbits)
+    ms, l = ctx.read_timing(reset=True)
+    assert c2 == c
+    kms = ms[sel.K_STAR] / max(1, l[sel.K_STAR])
+    bytes_ = fact_rows * 16
+    res = {
+        "fact_rows": fact_rows,
+        "dim_rows": [d.nrows for d in ddims],
+        "keybitmap_call_ms": dim_ms,
+        "star_count": c,
+        "star_kernel_ms": kms,
+        "star_rows_per_s": fact_rows / (kms / 1e3),
+        "star_GBps": bytes_ / (kms / 1e3) / 1e9,
+        "star_frac_of_peak": bytes_ / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+    }
+    dfact.destroy()
+    for d in ddims:
+        d.destroy()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +194,11 @@ def main():
     ap.add_argument("--rows", type=int, default=300_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-reps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-predicate batching measurement")
+    ap.add_argument("--no-star", action="store_true",
+                    help="skip the star-schema push-down measurement")
+    ap.add_argument("--star-rows", type=int, default=480_000_000)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain "
                          "copy kernel of known size, to calibrate HBM byte counters)")
@@ -204,6 +333,10 @@ def main():
             "sample": f"the full {n}-row table, COUNT only (the oracle's count), "
                       f"row ranges split over {threads} threads; {dt_cpu:.2f} s wall",
         }
+    if not args.no_batch:
+        out["batch"] = bench_batch(ctx, dt, table, threads, log)
+    if not args.no_star:
+        out["star"] = bench_star(ctx, args.star_rows, threads, log)
     if args.copy_probe_mb:
         nb = args.copy_probe_mb << 20
         a = torch.empty(nb, dtype=torch.uint8, device="cuda")

@@ -304,6 +304,91 @@ def star_fact_predicate():
     return ("cmp", 5, "<", 50)
 
 
+# ---- batching: many candidate predicates over tables of uneven size --------
+
+CFG3_ROWS = (10_000, 2_000_000, 60_000_000, 300_000_000)
+CFG3_SEEDS = (31, 32, 33, 34)
+
+
+def cfg3_tables(rows=CFG3_ROWS, threads=None):
+    """Four tables with the fact-table schema (seeds 31..34)."""
+    return [lineorder_like(f"T{k}", n, seed, threads)
+            for k, (n, seed) in enumerate(zip(rows, CFG3_SEEDS))]
+
+
+def _inv_norm_sf(q: float) -> float:
+    """z with P(Z >= z) = q for a standard normal (bisection on erfc)."""
+    lo, hi = -40.0, 40.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if 0.5 * math.erfc(mid / math.sqrt(2.0)) > q:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def _leaf_for(rng: np.random.Generator, q: float):
+    """A leaf over the fact-table schema whose selectivity is about q, set
+    from the column's known marginal distribution."""
+    q = min(max(q, 1e-7), 1.0)
+    col = int(rng.choice([0, 1, 2, 3, 5, 6]))
+    if col == 0:                                  # date uniform over 2557 days
+        w = max(1, int(round(q * 2557)))
+        a = int(rng.integers(0, 2557 - w + 1))
+        return ("between", 0, a, a + w - 1)
+    if col == 1:                                  # qty uniform 1..50
+        w = max(1, int(round(q * 50)))
+        return ("cmp", 1, "<", 1 + w) if rng.random() < 0.5 else ("cmp", 1, ">", 50 - w)
+    if col == 2:                                  # disc uniform 0..10
+        w = max(1, int(round(q * 11)))
+        a = int(rng.integers(0, 11 - w + 1))
+        return ("between", 2, a, a + w - 1)
+    if col == 3:                                  # price log-normal(10, 1)
+        v = int(round(math.exp(10.0 + _inv_norm_sf(q))))
+        return ("cmp", 3, ">=", v)
+    card = 25 if col == 5 else 4500               # Zipf(1.1) dictionary codes
+    pmf = zipf_pmf(1.1, card)
+    order = rng.permutation(card)
+    codes, mass = [], 0.0
+    for c in order:
+        if mass >= q:
+            break
+        if mass + pmf[c] > q * 1.5 and codes:
+            continue
+        codes.append(int(c))
+        mass += pmf[c]
+    if col == 5:
+        return ("in", 5, tuple(sorted(codes)))
+    return ("codeset", 6, 4500, words_from_codes(codes, 4500))
+
+
+def cfg3_programs(seed: int = 35, per_table: int = 16, ntables: int = 4):
+    """Candidate predicates: for each table, per_table programs with 2..8
+    leaves and target selectivity log-uniform in [1e-5, 0.9]; each is an AND
+    of m factors of selectivity about s^(1/m), some factors 2-leaf ORs.
+    Returns a list of (table index, tree)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for t in range(ntables):
+        for _ in range(per_table):
+            k = int(rng.integers(2, 9))
+            s = math.exp(rng.uniform(math.log(1e-5), math.log(0.9)))
+            n_or = int(rng.integers(0, k // 2 + 1))
+            m = k - n_or
+            q = s ** (1.0 / m)
+            factors = []
+            for f in range(m):
+                if f < n_or:
+                    q2 = 1.0 - math.sqrt(max(0.0, 1.0 - q))
+                    factors.append(("or", _leaf_for(rng, q2), _leaf_for(rng, q2)))
+                else:
+                    factors.append(_leaf_for(rng, q))
+            tree = factors[0] if m == 1 else ("and", *factors)
+            out.append((t, tree))
+    return out
+
+
 # ---------------------------------------------------- random tiny inputs --
 
 def grid_values(t: str):

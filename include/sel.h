@@ -251,6 +251,40 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact,
                           const uint32_t* const* d_bitmaps,
                           const uint64_t* nbits, uint64_t* out_count);
 
+/* ---- batching (Algorithm 1 counts every candidate relation) ------------- */
+
+/* Exact counts of n (table, program) pairs in ONE persistent launch
+ * (n in 1..1024; progs[i] must be bound to tables[i]; tables may repeat and
+ * may differ in size).  Tiles of every table form one index space; a wave
+ * takes a tile and evaluates every program of that tile's table on it, so a
+ * table's columns are read from HBM once per batch.  out_counts (host, n)
+ * receives count i for pair i; each equals what sel_count returns for it.
+ * Algorithm 1 computes one count per candidate relation in its loop over
+ * the relation queue; a batch computes all of them at once.
+ * Errors: SEL_E_INVALID (n out of range, NULL entries, program bound to
+ * another table), SEL_E_NOMEM, SEL_E_DEVICE. */
+sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                           const sel_program* const* progs, uint64_t* out_counts);
+
+/* A batch captured once in a HIP graph (the persistent kernel + the copy of
+ * the counts to pinned host memory) and replayed by sel_batch_run.  The
+ * batch owns its device descriptors, accumulators and stream; it reads the
+ * tables and programs, which must outlive it.  Same argument rules and
+ * errors as sel_count_batch. */
+typedef struct sel_batch sel_batch;
+sel_status sel_batch_create(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                            const sel_program* const* progs, sel_batch** out);
+
+/* Replace program i by another program bound to the same table.  Only the
+ * device descriptor is rewritten (in stream order); the graph is not
+ * captured again.  Errors: SEL_E_INVALID. */
+sel_status sel_batch_set_program(sel_batch* b, uint32_t i, const sel_program* prog);
+
+/* Replay the graph after all work already enqueued on the context's stream,
+ * wait for it, and write the n counts to out_counts (host). */
+sel_status sel_batch_run(sel_batch* b, uint64_t* out_counts);
+void sel_batch_destroy(sel_batch* b);
+
 /* ---- launch configuration and timing ------------------------------------ */
 
 typedef struct sel_launch {
@@ -261,6 +295,30 @@ typedef struct sel_launch {
 /* Override (or with NULL, restore) the launch shape used by the scan kernels
  * of this context.  Errors: SEL_E_INVALID for an unsupported block size. */
 sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch);
+
+/* ---- autotuning (offline: launches real kernels; not for the latency path) */
+
+/* Time every candidate launch shape (workgroups of 64/128/256 threads, 4..32
+ * resident waves per CU) of the count scan (with_mask = 0) or the
+ * count + mask scan (with_mask != 0) of `prog` on `table`, `reps` times each
+ * (0 = 5), and record the fastest (median) for this program class (bytes
+ * per row, length) and table size on the context; later calls with no fixed
+ * shape use it.  *best / *best_ms (either may be NULL) receive the winner. */
+sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                        int with_mask, uint32_t reps, sel_launch* best, double* best_ms);
+
+/* Same for the batched count of these n pairs (see sel_count_batch). */
+sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                              const sel_program* const* progs, uint32_t reps,
+                              sel_launch* best, double* best_ms);
+
+/* Save / load the context's tuned shapes as text ("key block grid" lines;
+ * grids are rescaled if the file was written on a device with another
+ * number of CUs).  sel_ctx_create loads the file named by the environment
+ * variable SEL_TUNE_CACHE, if set. */
+sel_status sel_tune_save(const sel_ctx* ctx, const char* path);
+sel_status sel_tune_load(sel_ctx* ctx, const char* path);
+uint32_t sel_tune_entries(const sel_ctx* ctx);
 
 /* Kernel timing: when enabled, the library brackets each scan-kernel launch
  * with HIP events on the context's stream and accumulates the elapsed time

@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libsel.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "api.cpp", "compile.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "compile.cpp", "batch.cpp", "autotune.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # device code: gfx950 only; packed fp32 VALU ops stay disabled (no float
@@ -37,9 +37,9 @@ def build(verbose: bool = False, out: str = LIB) -> str:
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip", *DEVICE]
+        # every translation unit is HIP for gfx950; only kernels.hip has
+        # device code
+        cmd = [HIPCC, "-x", "hip", *DEVICE, *COMMON, "-c", path, "-o", obj]
         _run(cmd, verbose)
         objs.append(obj)
     tmp = out + ".tmp"

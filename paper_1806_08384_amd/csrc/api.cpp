@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -14,138 +15,14 @@
 #include "../../include/sel.h"
 #include "sel_device.h"
 #include "sel_internal.h"
+#include "runtime.h"
 
 using namespace sel;
 
-namespace {
+namespace selrt {
+
 thread_local std::string g_create_error;
 
-struct EventPair {
-  hipEvent_t a, b;
-};
-
-// First-fit allocator over one device buffer, for compiled programs: a
-// compile then costs one async copy instead of a hipMalloc.  Blocks are
-// reused in stream order (all work of a context runs on its one stream), so
-// a kernel still reading a freed program finishes before the next copy into
-// that block.
-class Arena {
- public:
-  static constexpr size_t kAlign = 256;
-  void init(char* base, size_t size) {
-    base_ = base;
-    free_.clear();
-    free_[0] = size;
-  }
-  char* alloc(size_t n) {
-    n = (n + kAlign - 1) & ~(kAlign - 1);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        const size_t off = it->first, left = it->second - n;
-        free_.erase(it);
-        if (left) free_[off + n] = left;
-        used_[off] = n;
-        return base_ + off;
-      }
-    }
-    return nullptr;
-  }
-  bool owns(const void* p) const { return base_ && used_.count((size_t)((const char*)p - base_)); }
-  void release(void* p) {
-    auto u = used_.find((size_t)((char*)p - base_));
-    if (u == used_.end()) return;
-    size_t off = u->first, n = u->second;
-    used_.erase(u);
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + n == next->first) {
-      n += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += n;
-        return;
-      }
-    }
-    free_[off] = n;
-  }
-
- private:
-  char* base_ = nullptr;
-  std::map<size_t, size_t> free_;  // offset -> bytes
-  std::map<size_t, size_t> used_;
-};
-
-constexpr size_t kArenaBytes = 8u << 20;
-constexpr size_t kStageBytes = 1u << 20;
-}  // namespace
-
-struct sel_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  uint32_t num_cus = 0;
-  std::string err;
-
-  DevSlot* slot = nullptr;                 // device
-  unsigned long long* dout = nullptr;      // device, 2 values
-  unsigned long long* hout = nullptr;      // pinned host, 2 values
-  char* hstage = nullptr;                  // pinned host staging (kStageBytes)
-  hipEvent_t stage_free = nullptr;         // recorded after each copy out of hstage
-  DevInstr* dstar = nullptr;               // device, star-count program (128)
-  DevInstr* dtrue = nullptr;               // device, the program TRUE
-  void* arena_mem = nullptr;               // device, programs
-  Arena arena;
-  void* scratch = nullptr;                 // device, grow-only
-  size_t scratch_bytes = 0;
-
-  sel_launch launch{256, 0};
-  bool launch_fixed = false;
-  int occ[3] = {0, 0, 0};                  // blocks per CU per scan mode at 256 threads
-
-  bool timing = false;
-  std::vector<EventPair> free_events;
-  std::vector<std::pair<int, EventPair>> pending;
-  double ms[SEL_K_NKINDS] = {};
-  uint64_t launches[SEL_K_NKINDS] = {};
-};
-
-struct sel_table {
-  sel_ctx* ctx;
-  uint64_t nrows;
-  std::vector<sel_column> cols;
-};
-
-struct sel_program {
-  sel_ctx* ctx;
-  const sel_table* table;
-  void* dev = nullptr;              // code then blob: in the context's arena,
-  bool own_alloc = false;           // or its own hipMalloc if the arena is full
-  DevInstr* dcode = nullptr;
-  std::vector<DevInstr> host_code;  // with device pointers (for star programs)
-  uint32_t nins = 0;
-  int depth = 0;
-  double bytes_per_row = 0.0;
-  std::string text;
-};
-
-namespace {
-
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-    if (prev_ != dev) (void)hipSetDevice(dev);
-    dev_ = dev;
-  }
-  ~DeviceGuard() {
-    if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
-  }
-
- private:
-  int prev_ = -1, dev_ = 0;
-};
 
 sel_status set_err(sel_ctx* ctx, sel_status st, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -158,11 +35,6 @@ sel_status hip_err(sel_ctx* ctx, hipError_t e, const char* where) {
   return set_err(ctx, e == hipErrorOutOfMemory ? SEL_E_NOMEM : SEL_E_DEVICE, m);
 }
 
-#define HIP_TRY(ctx, call, where)                      \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return hip_err(ctx, e_, where); \
-  } while (0)
 
 uint32_t dev_type(int32_t t) {
   switch (t) {
@@ -209,41 +81,53 @@ EventPair take_events(sel_ctx* ctx) {
   return p;
 }
 
-// Brackets one kernel launch with events when timing is on.
-struct TimedLaunch {
-  sel_ctx* ctx;
-  int kind;
-  EventPair ev{};
-  bool on;
-  TimedLaunch(sel_ctx* c, int k) : ctx(c), kind(k), on(c->timing) {
-    if (on) {
-      ev = take_events(ctx);
-      (void)hipEventRecord(ev.a, ctx->stream);
-    }
+TimedLaunch::TimedLaunch(sel_ctx* c, int k) : ctx(c), kind(k), on(c->timing) {
+  if (on) {
+    ev = take_events(ctx);
+    (void)hipEventRecord(ev.a, ctx->stream);
   }
-  void done() {
-    if (on) {
-      (void)hipEventRecord(ev.b, ctx->stream);
-      ctx->pending.push_back({kind, ev});
-      on = false;
-    }
+}
+
+void TimedLaunch::done() {
+  if (on) {
+    (void)hipEventRecord(ev.b, ctx->stream);
+    ctx->pending.push_back({kind, ev});
+    on = false;
   }
-};
+}
 
 uint64_t ntiles_of(uint64_t nrows) { return (nrows + kTileRows - 1) / kTileRows; }
 
-// Launch shape of a scan over ntiles wave tiles.
-void scan_shape(sel_ctx* ctx, int mode, uint64_t ntiles, uint32_t& grid, uint32_t& block) {
+uint32_t tune_class_of(double bytes_per_row, uint32_t nins) {
+  const uint32_t b = (uint32_t)std::min(63.0, std::floor(bytes_per_row + 0.5));
+  const uint32_t l = nins <= 4 ? 0 : nins <= 8 ? 1 : nins <= 16 ? 2 : 3;
+  return (b << 2) | l;
+}
+
+uint64_t tune_key(int kind, uint32_t cls, uint64_t ntiles) {
+  uint32_t lg = 0;
+  while ((1ull << lg) < ntiles + 1) ++lg;
+  return (uint64_t)kind | ((uint64_t)cls << 4) | ((uint64_t)lg << 24);
+}
+
+// Launch shape of a scan over ntiles wave tiles: a fixed shape if the
+// caller set one, else the tuned shape of this (kernel, program class,
+// size) if the tuner recorded one, else 16 resident waves per CU (more
+// measured slower on the 300M-row scan).
+void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
+                uint32_t& block) {
   block = ctx->launch.block;
-  const uint32_t wpb = block / kWave;
-  uint64_t need = (ntiles + wpb - 1) / wpb;
-  if (need == 0) need = 1;
-  uint64_t g;
-  if (ctx->launch.grid) {
+  uint64_t g = 0;
+  if (ctx->launch_fixed) {
     g = ctx->launch.grid;
   } else {
-    // 16 resident waves per CU (fewer if occupancy is lower): more waves
-    // per CU measured slower on the 300M-row scan (HBM contention)
+    auto it = ctx->tune.find(tune_key(mode, cls, ntiles));
+    if (it != ctx->tune.end()) {
+      block = it->second.block;
+      g = it->second.grid;
+    }
+  }
+  if (g == 0) {
     int occ = 0;
     if (block == 256) {
       occ = ctx->occ[mode];
@@ -254,6 +138,9 @@ void scan_shape(sel_ctx* ctx, int mode, uint64_t ntiles, uint32_t& grid, uint32_
     const int per_cu = std::min(occ, (int)(16 * kWave / block));
     g = (uint64_t)per_cu * ctx->num_cus;
   }
+  const uint32_t wpb = block / kWave;
+  uint64_t need = (ntiles + wpb - 1) / wpb;
+  if (need == 0) need = 1;
   grid = (uint32_t)std::min<uint64_t>(need, std::max<uint64_t>(g, 1));
 }
 
@@ -269,9 +156,9 @@ bool check_prog(sel_ctx* ctx, const sel_table* t, const sel_program* p) {
   return true;
 }
 
-sel_status run_scan(sel_ctx* ctx, int mode, ScanArgs& a, int kind) {
+sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, ScanArgs& a, int kind) {
   uint32_t grid, block;
-  scan_shape(ctx, mode, a.ntiles, grid, block);
+  scan_shape(ctx, mode, cls, a.ntiles, grid, block);
   a.slot = ctx->slot;
   TimedLaunch tl(ctx, kind);
   int e = sel_launch_scan(mode, a, grid, block, ctx->stream);
@@ -329,7 +216,9 @@ sel_status check_columns(sel_ctx* ctx, uint64_t nrows, uint32_t ncols, const sel
   return SEL_OK;
 }
 
-}  // namespace
+}  // namespace selrt
+
+using namespace selrt;
 
 extern "C" {
 
@@ -345,6 +234,8 @@ void release_ctx(sel_ctx* ctx) {
   if (ctx->stage_free) (void)hipEventDestroy(ctx->stage_free);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->arena_mem) (void)hipFree(ctx->arena_mem);
+  if (ctx->batch_mem) (void)hipFree(ctx->batch_mem);
+  if (ctx->hbatch) (void)hipHostFree(ctx->hbatch);
   if (ctx->slot) (void)hipFree(ctx->slot);
   if (ctx->hout) (void)hipHostFree(ctx->hout);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);
@@ -387,6 +278,7 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
     ctx->arena.init((char*)ctx->arena_mem, kArenaBytes);
     if ((e = hipHostMalloc((void**)&ctx->hout, 64, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
     if ((e = hipHostMalloc((void**)&ctx->hstage, kStageBytes, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
+    if ((e = hipHostMalloc((void**)&ctx->hbatch, kBatchMaxProgs * 8, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
     if ((e = hipEventCreateWithFlags(&ctx->stage_free, hipEventDisableTiming)) != hipSuccess) { where = "hipEventCreate"; break; }
     DevInstr t{};
     t.op = D_TRUE;
@@ -399,6 +291,11 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
   }
   for (int m = 0; m < 3; ++m)
     if (sel_scan_occupancy(m, 256, &ctx->occ[m]) != 0 || ctx->occ[m] < 1) ctx->occ[m] = 1;
+  // tuned launch shapes saved earlier (sel_tune_save); a missing or
+  // unreadable file is ignored
+  if (const char* path = std::getenv("SEL_TUNE_CACHE")) {
+    if (sel_tune_load(ctx, path) != SEL_OK) ctx->err.clear();
+  }
   *out = ctx;
   return SEL_OK;
 }
@@ -558,6 +455,7 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   for (uint32_t c : L.columns) bpr += type_bytes(ci[c].type);
   bpr += (double)L.valid_columns.size() / 8.0;
   p->bytes_per_row = bpr;
+  p->tune_class = tune_class_of(bpr, p->nins);
   *out = p;
   return SEL_OK;
 }
@@ -593,7 +491,7 @@ sel_status sel_count_async(sel_ctx* ctx, const sel_table* table, const sel_progr
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = (unsigned long long*)d_count;
-  return run_scan(ctx, M_COUNT, a, SEL_K_COUNT);
+  return run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT);
 }
 
 sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
@@ -607,7 +505,7 @@ sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* pr
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = ctx->dout;
-  sel_status st = run_scan(ctx, M_COUNT, a, SEL_K_COUNT);
+  sel_status st = run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT);
   if (st != SEL_OK) return st;
   return read_out(ctx, out_count, nullptr);
 }
@@ -652,7 +550,7 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   a.out = ctx->dout;
   a.mask = mask;
   a.tile_counts = counts;
-  st = run_scan(ctx, M_MASK, a, SEL_K_MASK);
+  st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK);
   if (st != SEL_OK) return st;
   uint64_t count = 0;
   st = read_out(ctx, &count, nullptr);
@@ -719,7 +617,7 @@ sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t k
   a.key_min = key_min;
   a.nbits = nbits;
   a.bitmap = d_bitmap;
-  sel_status st = run_scan(ctx, M_KEYBITMAP, a, SEL_K_KEYBITMAP);
+  sel_status st = run_scan(ctx, M_KEYBITMAP, prog ? prog->tune_class : 0, a, SEL_K_KEYBITMAP);
   if (st != SEL_OK) return st;
   uint64_t count = 0, oor = 0;
   st = read_out(ctx, &count, &oor);
@@ -788,13 +686,16 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
   DeviceGuard g(ctx->device);
   sel_status sst = stage_copy(ctx, ctx->dstar, code.data(), code.size() * sizeof(DevInstr));
   if (sst != SEL_OK) return sst;
+  double star_bpr = fact_pred ? fact_pred->bytes_per_row : 0.0;
+  for (uint32_t d = 0; d < nfk; ++d) star_bpr += type_bytes(dev_type(fact->cols[fk_cols[d]].type));
+  const uint32_t star_cls = tune_class_of(star_bpr, (uint32_t)code.size());
   ScanArgs a{};
   a.prog = ctx->dstar;
   a.nins = (uint32_t)code.size();
   a.nrows = fact->nrows;
   a.ntiles = ntiles_of(fact->nrows);
   a.out = ctx->dout;
-  sel_status st = run_scan(ctx, M_COUNT, a, SEL_K_STAR);
+  sel_status st = run_scan(ctx, M_COUNT, star_cls, a, SEL_K_STAR);
   if (st != SEL_OK) return st;
   return read_out(ctx, out_count, nullptr);
 }

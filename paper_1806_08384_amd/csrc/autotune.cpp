@@ -1,0 +1,193 @@
+// autotune.cpp -- offline search of launch shapes (workgroup size and
+// number of workgroups) for the scan and batch kernels, keyed by program
+// class and table size; the result feeds the launch-shape lookup of every
+// later call on the context and can be saved to / loaded from a file.
+// Tuning launches the real kernels on the real table, so it belongs before
+// serving, never on its latency path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace sel;
+using namespace selrt;
+
+namespace {
+
+struct Candidate {
+  uint32_t block, grid;
+};
+
+std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, bool batch) {
+  std::vector<Candidate> c;
+  for (uint32_t block : {64u, 128u, 256u}) {
+    int occ = 0;
+    const int e = batch ? sel_batch_occupancy(block, &occ) : sel_scan_occupancy(occ_mode, block, &occ);
+    if (e != 0 || occ < 1) occ = 1;
+    const int max_waves = occ * (int)(block / kWave);
+    for (int waves : {4, 8, 12, 16, 20, 24, 32}) {
+      if (waves > max_waves) break;
+      const uint32_t per_cu = (uint32_t)waves / (block / kWave);
+      if (per_cu == 0) continue;
+      c.push_back({block, per_cu * ctx->num_cus});
+    }
+  }
+  return c;
+}
+
+template <class Launch>
+sel_status time_candidates(sel_ctx* ctx, const std::vector<Candidate>& cands, uint32_t reps,
+                           Launch launch, Candidate& best, double& best_ms) {
+  hipEvent_t a, b;
+  HIP_TRY(ctx, hipEventCreate(&a), "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return set_err(ctx, SEL_E_DEVICE, "hipEventCreate");
+  }
+  best_ms = 1e30;
+  sel_status st = SEL_OK;
+  for (const Candidate& c : cands) {
+    if (launch(c) != 0) { st = set_err(ctx, SEL_E_DEVICE, "launch failed while tuning"); break; }
+    std::vector<float> t;
+    for (uint32_t r = 0; r < reps; ++r) {
+      (void)hipEventRecord(a, ctx->stream);
+      const int e = launch(c);
+      (void)hipEventRecord(b, ctx->stream);
+      if (e != 0 || hipEventSynchronize(b) != hipSuccess) {
+        st = set_err(ctx, SEL_E_DEVICE, "launch failed while tuning");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      t.push_back(ms);
+    }
+    if (st != SEL_OK) break;
+    std::sort(t.begin(), t.end());
+    const double med = t[t.size() / 2];
+    if (med < best_ms) {
+      best_ms = med;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program* prog, int with_mask,
+                        uint32_t reps, sel_launch* best, double* best_ms) {
+  if (!ctx || !table || !prog) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  if (prog->table != table) return set_err(ctx, SEL_E_INVALID, "program is bound to another table");
+  if (reps == 0) reps = 5;
+  DeviceGuard g(ctx->device);
+  const int mode = with_mask ? M_MASK : M_COUNT;
+  const uint64_t ntiles = ntiles_of(table->nrows);
+  ScanArgs a{};
+  a.prog = prog->dcode;
+  a.nins = prog->nins;
+  a.nrows = table->nrows;
+  a.ntiles = ntiles;
+  a.out = ctx->dout;
+  a.slot = ctx->slot;
+  if (with_mask) {
+    const size_t mask_bytes = (size_t)ntiles * kWave * 4;
+    const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
+    sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * 2048 * 4);
+    if (st != SEL_OK) return st;
+    a.mask = (uint32_t*)ctx->scratch;
+    a.tile_counts = (uint32_t*)((char*)ctx->scratch + mask_bytes);
+  }
+  Candidate b{256, 0};
+  double ms = 0;
+  const uint64_t need_waves = std::max<uint64_t>(1, ntiles);
+  sel_status st = time_candidates(ctx, candidates(ctx, mode, false), reps, [&](const Candidate& c) {
+    const uint64_t need = (need_waves + c.block / kWave - 1) / (c.block / kWave);
+    return sel_launch_scan(mode, a, (uint32_t)std::min<uint64_t>(c.grid, need), c.block, ctx->stream);
+  }, b, ms);
+  if (st != SEL_OK) return st;
+  ctx->tune[tune_key(mode, prog->tune_class, ntiles)] = sel_launch{b.block, b.grid};
+  if (best) *best = sel_launch{b.block, b.grid};
+  if (best_ms) *best_ms = ms;
+  return SEL_OK;
+}
+
+sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                              const sel_program* const* progs, uint32_t reps, sel_launch* best,
+                              double* best_ms) {
+  if (!ctx) return SEL_E_INVALID;
+  if (reps == 0) reps = 3;
+  // time each candidate through the eager batch call with a fixed shape
+  const sel_launch saved = ctx->launch;
+  const bool saved_fixed = ctx->launch_fixed;
+  std::vector<uint64_t> out(n ? n : 1);
+  uint64_t total_tiles = 0;
+  std::vector<const sel_table*> seen;
+  for (uint32_t i = 0; i < n && tables; ++i) {
+    if (!tables[i]) return set_err(ctx, SEL_E_INVALID, "NULL table");
+    if (std::find(seen.begin(), seen.end(), tables[i]) == seen.end()) {
+      seen.push_back(tables[i]);
+      total_tiles += ntiles_of(tables[i]->nrows);
+    }
+  }
+  DeviceGuard g(ctx->device);
+  Candidate b{256, 0};
+  double ms = 0;
+  sel_status st = time_candidates(ctx, candidates(ctx, 0, true), reps, [&](const Candidate& c) {
+    ctx->launch = sel_launch{c.block, c.grid};
+    ctx->launch_fixed = true;
+    return (int)sel_count_batch(ctx, n, tables, progs, out.data()) == SEL_OK ? 0 : 1;
+  }, b, ms);
+  ctx->launch = saved;
+  ctx->launch_fixed = saved_fixed;
+  if (st != SEL_OK) return st;
+  ctx->tune[tune_key(TK_BATCH, batch_class(n), total_tiles)] = sel_launch{b.block, b.grid};
+  if (best) *best = sel_launch{b.block, b.grid};
+  if (best_ms) *best_ms = ms;
+  return SEL_OK;
+}
+
+// One line per entry: "key block grid".
+sel_status sel_tune_save(const sel_ctx* ctx, const char* path) {
+  if (!ctx || !path) return SEL_E_INVALID;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return set_err(const_cast<sel_ctx*>(ctx), SEL_E_INVALID, std::string("cannot write ") + path);
+  std::fprintf(f, "# libsel launch tuning: key block grid (device with %u CUs)\n", ctx->num_cus);
+  for (const auto& kv : ctx->tune)
+    std::fprintf(f, "%llu %u %u\n", (unsigned long long)kv.first, kv.second.block, kv.second.grid);
+  std::fclose(f);
+  return SEL_OK;
+}
+
+sel_status sel_tune_load(sel_ctx* ctx, const char* path) {
+  if (!ctx || !path) return SEL_E_INVALID;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return set_err(ctx, SEL_E_INVALID, std::string("cannot read ") + path);
+  char line[256];
+  unsigned cus = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#') {
+      std::sscanf(line, "# libsel launch tuning: key block grid (device with %u CUs)", &cus);
+      continue;
+    }
+    unsigned long long key;
+    unsigned block, grid;
+    if (std::sscanf(line, "%llu %u %u", &key, &block, &grid) != 3) continue;
+    if (block != 64 && block != 128 && block != 256) continue;
+    if (cus && cus != ctx->num_cus) grid = (uint32_t)((uint64_t)grid * ctx->num_cus / cus);
+    ctx->tune[key] = sel_launch{block, grid};
+  }
+  std::fclose(f);
+  return SEL_OK;
+}
+
+uint32_t sel_tune_entries(const sel_ctx* ctx) { return ctx ? (uint32_t)ctx->tune.size() : 0; }
+
+}  // extern "C"

@@ -10,6 +10,8 @@
 //  k_chunk_offsets
 //  k_compact            mask -> ascending row ids (LDS-free wave prefix by
 //                       ballot + mbcnt)
+//  k_batch              many programs over several tables in one launch,
+//                       one count per program
 //
 // Evaluation is bit-sliced: each lane owns 32 rows of a 2048-row wave tile
 // (sel_device.h) and every truth value of SQL's three-valued logic is a pair
@@ -498,6 +500,63 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
   }
 }
 
+// Batched count.  Per workgroup, per-program counts accumulate in LDS; at
+// the end each workgroup adds them to per-program accumulators (one 128-byte
+// line each, so atomics on different programs do not contend), and the last
+// workgroup by ticket copies them out and zeroes them for the next launch.
+__global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
+  __shared__ uint32_t acc[kBatchMaxProgs];
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint64_t W = (uint64_t)gridDim.x * nw;
+  for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x) acc[p] = 0;
+  __syncthreads();
+  const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
+  const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
+  for (uint64_t flat = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); flat < a.total_tiles;
+       flat += W) {
+    // table holding this tile: last t with tile_begin <= flat (uniform search)
+    uint32_t lo = 0, hi = a.ntables;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tables[mid].tile_begin <= flat) lo = mid; else hi = mid;
+    }
+    const uint64_t nrows = tables[lo].nrows;
+    const uint64_t tb = (flat - tables[lo].tile_begin) * kTileRows;
+    const uint32_t pb = tables[lo].prog_begin, pn = tables[lo].prog_count;
+    const bool full = tb + kTileRows <= nrows;
+    const uint32_t inr = full ? ~0u : inrange_bits(tb, lane, nrows);
+    for (uint32_t k = 0; k < pn; ++k) {
+      const CInstr code = (CInstr)progs[pb + k].code;
+      const uint32_t nins = progs[pb + k].nins;
+      const uint32_t T = full ? eval_tile<true>(code, nins, tb, lane, nrows)
+                              : eval_tile<false>(code, nins, tb, lane, nrows) & inr;
+      const uint32_t c = wave_sum(__builtin_popcount(T));
+      if (lane == 0 && c) atomicAdd(&acc[pb + k], c);
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x)
+    if (acc[p]) atomicAdd(&a.acc[(uint64_t)p * kBatchAccStride], (unsigned long long)acc[p]);
+  __threadfence();
+  __syncthreads();
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    const unsigned int ticket = atomicAdd(&a.slot->ticket, 1u);
+    last = ticket == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x) {
+      a.out[p] = atomicExch(&a.acc[(uint64_t)p * kBatchAccStride], 0ull);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(&a.slot->ticket, 0u);
+  }
+}
+
 __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -548,4 +607,13 @@ int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu) {
     default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_KEYBITMAP>, block, 0); break;
   }
   return (int)e;
+}
+
+int sel_launch_batch(const BatchArgs& a, uint32_t grid, uint32_t block, void* stream) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int sel_batch_occupancy(uint32_t block, int* blocks_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, block, 0);
 }

@@ -1,0 +1,192 @@
+// runtime.h -- host runtime objects of libsel (contexts, tables, programs)
+// and the helpers the C-ABI translation units share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/sel.h"
+#include "sel_device.h"
+#include "sel_internal.h"
+
+using sel::DevInstr;
+using sel::DevSlot;
+
+namespace selrt {
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+// First-fit allocator over one device buffer, for compiled programs: a
+// compile then costs one async copy instead of a hipMalloc.  Blocks are
+// reused in stream order (all work of a context runs on its one stream), so
+// a kernel still reading a freed program finishes before the next copy into
+// that block.
+class Arena {
+ public:
+  static constexpr size_t kAlign = 256;
+  void init(char* base, size_t size) {
+    base_ = base;
+    free_.clear();
+    free_[0] = size;
+  }
+  char* alloc(size_t n) {
+    n = (n + kAlign - 1) & ~(kAlign - 1);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const size_t off = it->first, left = it->second - n;
+        free_.erase(it);
+        if (left) free_[off + n] = left;
+        used_[off] = n;
+        return base_ + off;
+      }
+    }
+    return nullptr;
+  }
+  bool owns(const void* p) const { return base_ && used_.count((size_t)((const char*)p - base_)); }
+  void release(void* p) {
+    auto u = used_.find((size_t)((char*)p - base_));
+    if (u == used_.end()) return;
+    size_t off = u->first, n = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + n == next->first) {
+      n += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += n;
+        return;
+      }
+    }
+    free_[off] = n;
+  }
+
+ private:
+  char* base_ = nullptr;
+  std::map<size_t, size_t> free_;  // offset -> bytes
+  std::map<size_t, size_t> used_;
+};
+
+constexpr size_t kArenaBytes = 8u << 20;
+constexpr size_t kStageBytes = 1u << 20;
+}  // namespace selrt
+
+struct sel_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint32_t num_cus = 0;
+  std::string err;
+
+  DevSlot* slot = nullptr;                 // device
+  unsigned long long* dout = nullptr;      // device, 2 values
+  unsigned long long* hout = nullptr;      // pinned host, 2 values
+  char* hstage = nullptr;                  // pinned host staging (kStageBytes)
+  hipEvent_t stage_free = nullptr;         // recorded after each copy out of hstage
+  DevInstr* dstar = nullptr;               // device, star-count program (128)
+  DevInstr* dtrue = nullptr;               // device, the program TRUE
+  void* arena_mem = nullptr;               // device, programs
+  void* batch_mem = nullptr;               // device, sel_count_batch workspace
+  size_t batch_bytes = 0;
+  unsigned long long* hbatch = nullptr;    // pinned host, kBatchMaxProgs counts
+  selrt::Arena arena;
+  void* scratch = nullptr;                 // device, grow-only
+  size_t scratch_bytes = 0;
+
+  sel_launch launch{256, 0};
+  bool launch_fixed = false;
+  std::map<uint64_t, sel_launch> tune;     // autotuned launch shapes by class
+  int occ[3] = {0, 0, 0};                  // blocks per CU per scan mode at 256 threads
+
+  bool timing = false;
+  std::vector<selrt::EventPair> free_events;
+  std::vector<std::pair<int, selrt::EventPair>> pending;
+  double ms[SEL_K_NKINDS] = {};
+  uint64_t launches[SEL_K_NKINDS] = {};
+};
+
+struct sel_table {
+  sel_ctx* ctx;
+  uint64_t nrows;
+  std::vector<sel_column> cols;
+};
+
+struct sel_program {
+  sel_ctx* ctx;
+  const sel_table* table;
+  void* dev = nullptr;              // code then blob: in the context's arena,
+  bool own_alloc = false;           // or its own hipMalloc if the arena is full
+  DevInstr* dcode = nullptr;
+  std::vector<DevInstr> host_code;  // with device pointers (for star programs)
+  uint32_t nins = 0;
+  uint32_t tune_class = 0;          // bytes-per-row and length bucket
+  int depth = 0;
+  double bytes_per_row = 0.0;
+  std::string text;
+};
+
+namespace selrt {
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) (void)hipSetDevice(dev);
+    dev_ = dev;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0 && prev_ != dev_) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1, dev_ = 0;
+};
+
+sel_status set_err(sel_ctx* ctx, sel_status st, const std::string& msg);
+sel_status hip_err(sel_ctx* ctx, hipError_t e, const char* where);
+uint32_t dev_type(int32_t t);
+uint32_t type_bytes(uint32_t dt);
+sel_status ensure_scratch(sel_ctx* ctx, size_t bytes);
+sel_status stage_copy(sel_ctx* ctx, void* dst, const void* src, size_t n);
+sel_status read_out(sel_ctx* ctx, uint64_t* v0, uint64_t* v1);
+EventPair take_events(sel_ctx* ctx);
+uint64_t ntiles_of(uint64_t nrows);
+
+// Launch-shape classes for the tuner: a class of programs (bytes per row,
+// length) and a size bucket of the table (log2 of its tile count).
+uint32_t tune_class_of(double bytes_per_row, uint32_t nins);
+uint64_t tune_key(int kind, uint32_t cls, uint64_t ntiles);
+enum TuneKind { TK_COUNT = 0, TK_MASK = 1, TK_KEYBITMAP = 2, TK_BATCH = 3 };
+inline uint32_t batch_class(uint32_t nprogs) {
+  uint32_t c = 0;
+  while ((1u << c) < nprogs) ++c;
+  return c;
+}
+void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
+                uint32_t& block);
+sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int kind);
+
+// Brackets one kernel launch with events when timing is on.
+struct TimedLaunch {
+  sel_ctx* ctx;
+  int kind;
+  EventPair ev{};
+  bool on;
+  TimedLaunch(sel_ctx* c, int k);
+  void done();
+};
+
+}  // namespace selrt
+
+#define HIP_TRY(ctx, call, where)                                   \
+  do {                                                              \
+    hipError_t e_ = (call);                                         \
+    if (e_ != hipSuccess) return selrt::hip_err(ctx, e_, where);    \
+  } while (0)

@@ -98,6 +98,38 @@ struct CompactArgs {
   uint64_t cap;
 };
 
+// Batched count (many programs over several tables in one launch).  Tiles
+// of all tables form one flat index space; a wave takes a tile and runs every
+// program bound to that tile's table on it, so programs sharing a table read
+// its columns from HBM once and from cache afterwards.
+struct BatchTable {            // 32 bytes
+  uint64_t nrows;
+  uint64_t tile_begin;         // first flat tile index of this table
+  uint32_t prog_begin;         // into the BatchProg array
+  uint32_t prog_count;
+  uint64_t pad;
+};
+
+struct BatchProg {             // 16 bytes
+  const DevInstr* code;
+  uint32_t nins;
+  uint32_t pad;
+};
+
+constexpr int kBatchMaxProgs = 1024;
+constexpr int kBatchAccStride = 16;   // u64 per accumulator: one 128-byte line each
+
+struct BatchArgs {
+  const BatchTable* tables;
+  const BatchProg* progs;
+  uint32_t ntables;
+  uint32_t nprogs;
+  uint64_t total_tiles;
+  unsigned long long* acc;     // nprogs * kBatchAccStride, zero between launches
+  unsigned long long* out;     // nprogs counts
+  DevSlot* slot;
+};
+
 }  // namespace sel
 
 // Launchers implemented in kernels.hip (return hipError_t as int).
@@ -108,4 +140,6 @@ int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* c
 int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
 int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);
+int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, void* stream);
+int sel_batch_occupancy(uint32_t block, int* blocks_per_cu);
 }

@@ -101,6 +101,18 @@ sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i
                               _P(_u64))
 sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
                       _P(_u64))
+sel_count_batch = _sig("sel_count_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_u64))
+sel_batch_create = _sig("sel_batch_create", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_vp))
+sel_batch_set_program = _sig("sel_batch_set_program", _i32, _vp, _u32, _vp)
+sel_batch_run = _sig("sel_batch_run", _i32, _vp, _P(_u64))
+sel_batch_destroy = _sig("sel_batch_destroy", None, _vp)
+sel_autotune = _sig("sel_autotune", _i32, _vp, _vp, _vp, ctypes.c_int, _u32, _P(sel_launch),
+                    _P(ctypes.c_double))
+sel_autotune_batch = _sig("sel_autotune_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _u32,
+                          _P(sel_launch), _P(ctypes.c_double))
+sel_tune_save = _sig("sel_tune_save", _i32, _vp, ctypes.c_char_p)
+sel_tune_load = _sig("sel_tune_load", _i32, _vp, ctypes.c_char_p)
+sel_tune_entries = _sig("sel_tune_entries", _u32, _vp)
 sel_ctx_set_launch = _sig("sel_ctx_set_launch", _i32, _vp, _P(sel_launch))
 sel_ctx_enable_timing = _sig("sel_ctx_enable_timing", _i32, _vp, ctypes.c_int)
 sel_ctx_read_timing = _sig("sel_ctx_read_timing", _i32, _vp, _P(sel_timing), ctypes.c_int)
@@ -222,11 +234,10 @@ class Context:
         """Destroy the context after every table and program made from it."""
         if self.h:
             kids = list(self._children)
-            for k in kids:
-                if isinstance(k, Program):
-                    k.destroy()
-            for k in kids:
-                k.destroy()
+            for kind in (Batch, Program, DeviceTable):
+                for k in kids:
+                    if isinstance(k, kind):
+                        k.destroy()
             sel_ctx_destroy(self.h)
             self.h = None
 
@@ -294,6 +305,45 @@ class Context:
                                   n, fk, bm, nb, ctypes.byref(out)))
         return int(out.value)
 
+    def count_batch(self, pairs):
+        """Exact counts of [(table, program), ...] in one launch."""
+        n = len(pairs)
+        ts = (_vp * n)(*[t.h.value for t, _ in pairs])
+        ps = (_vp * n)(*[p.h.value for _, p in pairs])
+        out = (_u64 * n)()
+        self.check(sel_count_batch(self.h, n, ts, ps, out))
+        return [int(x) for x in out]
+
+    def batch(self, pairs):
+        """A graph-captured batch (see Batch)."""
+        return Batch(self, pairs)
+
+    def autotune(self, table, prog, with_mask=False, reps=5):
+        """Tune the scan's launch shape for this program class and table size;
+        returns ((block, grid), median ms)."""
+        best, ms = sel_launch(), ctypes.c_double(0)
+        self.check(sel_autotune(self.h, table.h, prog.h, 1 if with_mask else 0, reps,
+                                ctypes.byref(best), ctypes.byref(ms)))
+        return (best.block, best.grid), ms.value
+
+    def autotune_batch(self, pairs, reps=3):
+        n = len(pairs)
+        ts = (_vp * n)(*[t.h.value for t, _ in pairs])
+        ps = (_vp * n)(*[p.h.value for _, p in pairs])
+        best, ms = sel_launch(), ctypes.c_double(0)
+        self.check(sel_autotune_batch(self.h, n, ts, ps, reps, ctypes.byref(best), ctypes.byref(ms)))
+        return (best.block, best.grid), ms.value
+
+    def tune_save(self, path):
+        self.check(sel_tune_save(self.h, str(path).encode()))
+
+    def tune_load(self, path):
+        self.check(sel_tune_load(self.h, str(path).encode()))
+
+    @property
+    def tune_entries(self) -> int:
+        return int(sel_tune_entries(self.h))
+
     def set_launch(self, block=None, grid=0):
         if block is None:
             self.check(sel_ctx_set_launch(self.h, None))
@@ -307,6 +357,43 @@ class Context:
         t = sel_timing()
         self.check(sel_ctx_read_timing(self.h, ctypes.byref(t), 1 if reset else 0))
         return [float(x) for x in t.ms], [int(x) for x in t.launches]
+
+
+class Batch:
+    """sel_batch: the batched count captured once in a HIP graph; run()
+    replays it.  set_program(i, prog) swaps program i (same table) without a
+    new capture."""
+
+    def __init__(self, ctx: Context, pairs):
+        self.ctx = ctx
+        self.n = len(pairs)
+        self._keep = list(pairs)
+        ts = (_vp * self.n)(*[t.h.value for t, _ in pairs])
+        ps = (_vp * self.n)(*[p.h.value for _, p in pairs])
+        h = _vp()
+        ctx.check(sel_batch_create(ctx.h, self.n, ts, ps, ctypes.byref(h)))
+        self.h = h
+        self._out = (_u64 * self.n)()
+        ctx._children.add(self)
+
+    def run(self):
+        self.ctx.check(sel_batch_run(self.h, self._out))
+        return [int(x) for x in self._out]
+
+    def set_program(self, i: int, prog):
+        self.ctx.check(sel_batch_set_program(self.h, i, prog.h))
+        self._keep[i] = (self._keep[i][0], prog)
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            sel_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
 
 
 def max_rows(nrows: int, ratio: float) -> int:

@@ -1,0 +1,144 @@
+"""GPU: batched counts (one persistent launch, eager and graph-replayed)
+equal the plain counts and the oracle, bit-exactly."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    from paper_1806_08384_amd import sel as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(sel):
+    c = sel.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def setup(sel, ctx):
+    """Four tables of uneven size (10k .. 3M rows, partial last tiles) and the
+    64 candidate programs of the batching workload."""
+    say("batch: generating tables")
+    rows = (10_000, 200_003, 1_000_000, 3_000_001)
+    tables = datagen.cfg3_tables(rows=rows)
+    dts = [sel.device_table(ctx, t) for t in tables]
+    progs = datagen.cfg3_programs()
+    pairs = [(dts[t], ctx.program(dts[t], tree)) for t, tree in progs]
+    want = [oracle.Oracle(tables[t]).count(tree, threads=8) for t, tree in progs]
+    return tables, dts, progs, pairs, want
+
+
+def test_batch_equals_plain_and_oracle(sel, ctx, setup):
+    tables, dts, progs, pairs, want = setup
+    plain = [ctx.count(t, p) for t, p in pairs]
+    assert plain == want
+    got = ctx.count_batch(pairs)
+    assert got == want
+    # selectivities span orders of magnitude
+    sel_ = [w / tables[t].nrows for (t, _), w in zip(progs, want)]
+    assert min(sel_) < 1e-3 and max(sel_) > 0.1
+
+
+def test_batch_subsets_and_repeats(sel, ctx, setup):
+    tables, dts, progs, pairs, want = setup
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        idx = [int(i) for i in rng.integers(0, len(pairs), int(rng.integers(1, 40)))]
+        got = ctx.count_batch([pairs[i] for i in idx])
+        assert got == [want[i] for i in idx]
+    # a single pair, and one table only
+    assert ctx.count_batch([pairs[5]]) == [want[5]]
+    only3 = [i for i, (t, _) in enumerate(progs) if t == 3]
+    assert ctx.count_batch([pairs[i] for i in only3]) == [want[i] for i in only3]
+
+
+def test_graph_replay(sel, ctx, setup):
+    """Replay several times with the program's own eager work between the
+    replays; every replay equals the eager result."""
+    tables, dts, progs, pairs, want = setup
+    b = ctx.batch(pairs)
+    for r in range(4):
+        assert b.run() == want, f"replay {r}"
+        # eager work on the same context in between
+        assert ctx.count_batch(pairs[:7]) == want[:7]
+        assert ctx.count(*pairs[r]) == want[r]
+    b.destroy()
+
+
+def test_graph_descriptor_update(sel, ctx, setup):
+    """Swapping a program rewrites the descriptor only; the replay then
+    equals a fresh eager batch."""
+    tables, dts, progs, pairs, want = setup
+    b = ctx.batch(pairs)
+    assert b.run() == want
+    t3 = [i for i, (t, _) in enumerate(progs) if t == 3]
+    i = t3[0]
+    new_tree = datagen.cfg2_predicate(100, 900)
+    newp = ctx.program(dts[3], new_tree)
+    b.set_program(i, newp)
+    w2 = list(want)
+    w2[i] = oracle.Oracle(tables[3]).count(new_tree, threads=8)
+    for _ in range(3):
+        assert b.run() == w2
+    pairs2 = list(pairs)
+    pairs2[i] = (dts[3], newp)
+    assert ctx.count_batch(pairs2) == w2
+    with pytest.raises(sel.SelError):
+        b.set_program(i, pairs[0][1])     # a program of another table
+    b.destroy()
+
+
+def test_batch_empty_and_tiny_tables(sel, ctx):
+    t0 = datagen.cfg1(0, seed=1)
+    t1 = datagen.cfg1(1, seed=2)
+    t2 = datagen.cfg1(2049, seed=3)
+    dts = [sel.device_table(ctx, t) for t in (t0, t1, t2)]
+    tree = ("cmp", 0, "<", 5000)
+    pairs = [(d, ctx.program(d, tree)) for d in dts]
+    want = [oracle.Oracle(t).count(tree) for t in (t0, t1, t2)]
+    assert ctx.count_batch(pairs) == want
+    assert ctx.count_batch(pairs[:1]) == [0]
+    b = ctx.batch(pairs)
+    assert b.run() == want
+    b.destroy()
+
+
+def test_batch_rejects_bad_input(sel, ctx, setup):
+    tables, dts, progs, pairs, want = setup
+    with pytest.raises(sel.SelError):
+        ctx.count_batch([(dts[0], pairs[-1][1])])   # program of another table
+    with pytest.raises(sel.SelError):
+        ctx.count_batch([])
+
+
+def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
+    """Tuning changes launch shapes only: counts stay exact, and the tuned
+    table survives a save/load round trip into a fresh context."""
+    tables, dts, progs, pairs, want = setup
+    (block, grid), ms = ctx.autotune(*pairs[-1], with_mask=False, reps=2)
+    assert block in (64, 128, 256) and grid > 0 and ms > 0
+    ctx.autotune(*pairs[-1], with_mask=True, reps=2)
+    (bb, bg), bms = ctx.autotune_batch(pairs, reps=1)
+    assert bb in (64, 128, 256) and bg > 0
+    assert ctx.tune_entries >= 3
+    assert ctx.count(*pairs[-1]) == want[-1]
+    assert ctx.count_batch(pairs) == want
+    path = tmp_path / "tune.txt"
+    ctx.tune_save(path)
+    c2 = sel.Context(0)
+    c2.tune_load(path)
+    assert c2.tune_entries == ctx.tune_entries
+    c2.close()
