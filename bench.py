@@ -73,7 +73,7 @@ def _timed(fn, reps):
     return ts[len(ts) // 2], r
 
 
-def bench_batch(ctx, fact_dt, fact_table, threads, log):
+def bench_batch(ctx, fact_dt, threads, log):
     """64 candidate predicates (2-8 leaves, selectivity 1e-5..0.9) over four
     tables of 10k / 2M / 60M / 300M rows: one persistent launch (eager and
     graph-replayed) against 64 plain count launches.  The 300M-row table is
@@ -118,7 +118,7 @@ def bench_batch(ctx, fact_dt, fact_table, threads, log):
     res = {
         "programs": len(pairs),
         "tables_rows": [int(datagen.CFG3_ROWS[0]), int(datagen.CFG3_ROWS[1]),
-                        int(datagen.CFG3_ROWS[2]), int(fact_table.nrows)],
+                        int(datagen.CFG3_ROWS[2]), int(fact_dt.nrows)],
         "plain_sync_ms": t_sync,
         "plain_async_ms": t_async,
         "batch_eager_ms": t_eager,
@@ -130,9 +130,7 @@ def bench_batch(ctx, fact_dt, fact_table, threads, log):
     b.destroy()
     for t, p in pairs:
         p.destroy()
-    for d in dts[:3]:
-        d.destroy()
-    return res
+    return res, dts[:3]
 
 
 def bench_star(ctx, fact_rows, threads, log):
@@ -180,9 +178,138 @@ def bench_star(ctx, fact_rows, threads, log):
         "star_GBps": bytes_ / (kms / 1e3) / 1e9,
         "star_frac_of_peak": bytes_ / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
     }
-    dfact.destroy()
-    for d in ddims:
-        d.destroy()
+    return res, (dfact, ddims, dims)
+
+
+def bench_serve(ctx, small, fact_dt, star, threads, log, seconds):
+    """Poisson stream (2000 requests/s) of estimate requests, 1-12 programs
+    each over the resident tables (1M uniform, 2M, 60M, the 300M fact table
+    and the 480M star fact table), 10 % with a push-down with row ids, served
+    with continuous batching after a 1 s warm-up; against serial plain calls
+    (FIFO) on the first second of the same arrival trace."""
+    import threading
+
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+    dfact, ddims, dims = star
+    log("serve: building the 1M table and program pools")
+    t1m = sel.device_table(ctx, datagen.cfg1(1_000_000, seed=51, threads=threads))
+    tables = [t1m, small[1], small[2], fact_dt, dfact]
+    pools = [[ctx.program(t1m, t) for t in datagen.uniform3_programs(52, 32)]]
+    for k, tb in ((1, small[1]), (2, small[2]), (3, fact_dt)):
+        trees = [tree for _, tree in datagen.cfg3_programs(seed=60 + k, per_table=32, ntables=1)]
+        pools.append([ctx.program(tb, t) for t in trees])
+    star_pool, keep = [], []
+    for combo in datagen.star_dim_programs(53, 16, dims):
+        bms = []
+        for d, p in zip(ddims, combo):
+            bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+            st, _ = ctx.pushdown_keybitmap(d, 0, 0, ctx.program(d, p), bm, d.nrows)
+            assert st == sel.SEL_OK
+            bms.append(bm)
+        keep.append(bms)
+        star_pool.append(ctx.star_program(dfact, [0, 1, 2, 3], bms, [d.nrows for d in ddims]))
+    pools.append(star_pool)
+    alone = [[ctx.count(tables[k], p) for p in pool] for k, pool in enumerate(pools)]
+    warm = 1.0
+    trace = datagen.serving_trace(seed=52, rate=2000.0, duration=warm + seconds,
+                                  pool_sizes=tuple(len(p) for p in pools))
+    n_warm = sum(1 for t, _, _ in trace if t < warm)
+    pd_bufs = {}
+    for tb in range(4):
+        mx = sel.max_rows(tables[tb].nrows, 0.05)
+        pd_bufs[tb] = (mx, [torch.empty(max(1, mx), dtype=torch.int32, device="cuda")
+                            for _ in range(4)])
+    srv = ctx.server(hbm_budget_bytes=4 << 30)
+    tickets = [None] * len(trace)
+    err = []
+
+    def client():
+        t0 = time.perf_counter()
+        try:
+            for i, (t, items, pd) in enumerate(trace):
+                while True:
+                    dt_ = t - (time.perf_counter() - t0)
+                    if dt_ <= 0:
+                        break
+                    time.sleep(dt_ if dt_ > 0.002 else 0)
+                pairs = [(tables[tb], pools[tb][pi]) for tb, pi in items]
+                pdarg = None
+                if pd is not None:
+                    tb, pi = pd
+                    mx, bufs = pd_bufs[tb]
+                    pdarg = (tables[tb], pools[tb][pi], mx, bufs[i % len(bufs)])
+                tickets[i] = srv.submit(pairs, pdarg)
+                if i + 1 == n_warm:
+                    srv.stats(reset=True)
+        except Exception as e:
+            err.append(e)
+
+    log(f"serve: {len(trace)} requests over {warm + seconds:.0f} s")
+    th = threading.Thread(target=client)
+    th.start()
+    lat, mismatches = [], 0
+    for i in range(len(trace)):
+        while tickets[i] is None and not err:
+            time.sleep(0.0002)
+        if err:
+            break
+        counts, st, pdc, ms = srv.wait(tickets[i])
+        if counts != [alone[tb][pi] for tb, pi in trace[i][1]]:
+            mismatches += 1
+        if i >= n_warm:
+            lat.append(ms)
+    th.join()
+    if err:
+        raise err[0]
+    stats = srv.stats()
+    srv.destroy()
+    assert mismatches == 0, f"{mismatches} served results differ from the same requests alone"
+
+    # serial plain launches on the first second of the same trace
+    n_serial = min(len(trace), 2000)
+    log(f"serve: serial baseline over {n_serial} requests")
+    service = []
+    for i in range(n_serial):
+        t, items, pd = trace[i]
+        t0 = time.perf_counter()
+        for tb, pi in items:
+            ctx.count(tables[tb], pools[tb][pi])
+        if pd is not None:
+            tb, pi = pd
+            mx, bufs = pd_bufs[tb]
+            ctx.pushdown_rowids(tables[tb], pools[tb][pi], mx, bufs[0])
+        service.append(time.perf_counter() - t0)
+    finish, serial_lat = 0.0, []
+    for i in range(n_serial):
+        start = max(trace[i][0], finish)
+        finish = start + service[i]
+        serial_lat.append((finish - trace[i][0]) * 1e3)
+    serial_lat.sort()
+    res = {
+        "rate_per_s": 2000.0,
+        "requests": len(trace) - n_warm,
+        "programs_per_request_mean": sum(len(x[1]) for x in trace) / len(trace),
+        "pushdown_fraction": sum(1 for x in trace if x[2]) / len(trace),
+        "throughput_req_per_s": stats["completed"] / stats["elapsed_s"] if stats["elapsed_s"] else None,
+        "p50_ms": stats["p50_ms"],
+        "p99_ms": stats["p99_ms"],
+        "mean_ms": stats["mean_ms"],
+        "max_ms": stats["max_ms"],
+        "rounds": stats["rounds"],
+        "programs_per_round": stats["round_programs"] / max(1, stats["rounds"]),
+        "shared_rounds": stats["shared_rounds"],
+        "max_admitted": stats["max_admitted"],
+        "results_equal_alone": True,
+        "serial_plain": {
+            "requests": n_serial,
+            "throughput_req_per_s": n_serial / sum(service),
+            "p50_ms": percentile(serial_lat, 50),
+            "p99_ms": percentile(serial_lat, 99),
+        },
+    }
     return res
 
 
@@ -199,6 +326,9 @@ def main():
     ap.add_argument("--no-star", action="store_true",
                     help="skip the star-schema push-down measurement")
     ap.add_argument("--star-rows", type=int, default=480_000_000)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving (Poisson request stream) measurement")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain "
                          "copy kernel of known size, to calibrate HBM byte counters)")
@@ -333,10 +463,14 @@ def main():
             "sample": f"the full {n}-row table, COUNT only (the oracle's count), "
                       f"row ranges split over {threads} threads; {dt_cpu:.2f} s wall",
         }
+    del table
+    small = star = None
     if not args.no_batch:
-        out["batch"] = bench_batch(ctx, dt, table, threads, log)
+        out["batch"], small = bench_batch(ctx, dt, threads, log)
     if not args.no_star:
-        out["star"] = bench_star(ctx, args.star_rows, threads, log)
+        out["star"], star = bench_star(ctx, args.star_rows, threads, log)
+    if not args.no_serve and small is not None and star is not None:
+        out["serving"] = bench_serve(ctx, small, dt, star, threads, log, args.serve_seconds)
     if args.copy_probe_mb:
         nb = args.copy_probe_mb << 20
         a = torch.empty(nb, dtype=torch.uint8, device="cuda")

@@ -389,6 +389,73 @@ def cfg3_programs(seed: int = 35, per_table: int = 16, ntables: int = 4):
     return out
 
 
+# ---- serving: a Poisson stream of estimate requests --------------------------
+
+SERVE_TABLES = ("cfg1_1M", "T_2M", "T_60M", "fact_300M", "star_480M")
+
+
+def uniform3_programs(seed: int, n: int):
+    """Programs over three int32 columns uniform in [0, 10000): ANDs of 1..3
+    range leaves with per-leaf selectivity log-uniform in [1e-3, 0.9]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        k = int(rng.integers(1, 4))
+        leaves = []
+        for c in rng.permutation(3)[:k]:
+            q = math.exp(rng.uniform(math.log(1e-3), math.log(0.9)))
+            w = max(1, int(round(q * 10000)))
+            a = int(rng.integers(0, 10000 - w + 1))
+            leaves.append(("between", int(c), a, a + w - 1))
+        out.append(leaves[0] if k == 1 else ("and", *leaves))
+    return out
+
+
+def star_dim_programs(seed: int, n: int, dims):
+    """n combinations of one predicate per dimension (on its non-key
+    attributes), with selectivities spread over orders of magnitude."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        combo = []
+        for d in dims:
+            col = int(rng.integers(1, len(d.columns)))
+            card = d.columns[col].dict_card
+            k = max(1, int(round(card * math.exp(rng.uniform(math.log(0.02), math.log(0.6))))))
+            codes = tuple(sorted(int(c) for c in rng.choice(card, size=min(k, card), replace=False)))
+            combo.append(("in", col, codes))
+        out.append(combo)
+    return out
+
+
+def serving_trace(seed: int = 52, rate: float = 2000.0, duration: float = 10.0,
+                  pool_sizes=(32, 32, 32, 32, 16), pushdown_rate: float = 0.1,
+                  max_programs: int = 12):
+    """Poisson arrivals (rate per second over `duration` seconds); each
+    request has 1..max_programs programs, each on a table drawn uniformly
+    from the five resident tables and a program drawn from that table's
+    pool; a fraction asks, in addition, for one push-down with row ids on a
+    non-star table.  Returns [(arrival_s, [(table, prog)], pushdown)] with
+    pushdown None or (table, prog)."""
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += float(rng.exponential(1.0 / rate))
+        if t >= duration:
+            break
+        k = int(rng.integers(1, max_programs + 1))
+        items = []
+        for _ in range(k):
+            tb = int(rng.integers(0, len(pool_sizes)))
+            items.append((tb, int(rng.integers(0, pool_sizes[tb]))))
+        pd = None
+        if rng.random() < pushdown_rate:
+            tb = int(rng.integers(0, len(pool_sizes) - 1))
+            pd = (tb, int(rng.integers(0, pool_sizes[tb])))
+        out.append((t, items, pd))
+    return out
+
+
 # ---------------------------------------------------- random tiny inputs --
 
 def grid_values(t: str):

@@ -285,6 +285,96 @@ sel_status sel_batch_set_program(sel_batch* b, uint32_t i, const sel_program* pr
 sel_status sel_batch_run(sel_batch* b, uint64_t* out_counts);
 void sel_batch_destroy(sel_batch* b);
 
+/* The same star semi-join as a program over the fact table (bitmap-probe
+ * leaves ANDed with the optional fact predicate), usable wherever a program
+ * is: sel_count of it equals sel_star_count, and it can join batches and
+ * served requests.  The bitmaps are BORROWED: they must stay valid and
+ * unchanged while the program is used.  Same argument rules and errors as
+ * sel_star_count. */
+sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
+                            uint32_t nfk, const uint32_t* fk_cols,
+                            const uint32_t* const* d_bitmaps, const uint64_t* nbits,
+                            sel_program** out);
+
+/* ---- serving: continuous batching of estimate requests ------------------ */
+
+/* A server keeps the tables resident (they are the caller's) and answers
+ * requests as they arrive.  A request is a set of count queries (one exact
+ * count per (table, program), Ch.3 sec.3.1) and optionally one push-down
+ * with materialisation (Algorithm 1's Execute: count, limit check, ascending
+ * row ids).  Count queries are served by cooperative scans: each table with
+ * pending programs is cut into chunks of chunk_rows rows, and a round is one
+ * batched launch over the current chunk of every such table for every
+ * program attached to it.  A program attaches at the next round and is done
+ * after one revolution over its table, so requests arriving while others are
+ * on the GPU share their scans.  A request is admitted (FIFO) when its
+ * device footprint (accumulators, program code, and for a push-down the
+ * result mask, tile counts and its id capacity) fits the budget beside the
+ * admitted ones; push-downs run on their own stream, overlapping the rounds.
+ * Counts are exact: a request's results do not depend on what else runs. */
+typedef struct sel_server sel_server;
+
+typedef struct sel_server_config {
+  uint64_t hbm_budget_bytes;   /* device bytes admitted requests may hold (0 = 1 GiB) */
+  uint64_t chunk_rows;         /* rows per cooperative-scan chunk (0 = 2^26) */
+  uint32_t max_programs;       /* programs in flight (<= 4096; 0 = 4096) */
+  uint32_t rounds_in_flight;   /* rounds queued on the device (1..4; 0 = 2) */
+} sel_server_config;
+
+typedef struct sel_request {
+  uint32_t nprog;                      /* count queries (may be 0 with a push-down) */
+  const sel_table* const* tables;      /* nprog entries */
+  const sel_program* const* progs;     /* progs[i] bound to tables[i] */
+  const sel_table* pd_table;           /* push-down, or NULL for none */
+  const sel_program* pd_prog;
+  uint64_t pd_max_rows;                /* Algorithm 1's maxSize */
+  uint32_t* pd_out;                    /* device, caller-owned, pd_cap ids */
+  uint64_t pd_cap;
+} sel_request;
+
+typedef struct sel_result {
+  sel_status status;                   /* the push-down's status (SEL_OK without one) */
+  int32_t pad;
+  uint64_t pd_count;                   /* the push-down's count */
+  double latency_ms;                   /* submit -> completion */
+} sel_result;
+
+typedef struct sel_server_stats {
+  uint64_t submitted, completed, rejected;
+  uint64_t rounds;                     /* batched launches */
+  uint64_t round_programs;             /* programs summed over rounds */
+  uint64_t shared_rounds;              /* table scans serving programs of >= 2 requests */
+  uint32_t max_admitted;               /* most requests admitted at once */
+  uint32_t pad;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* request latency, submit -> completion */
+  double elapsed_s;                    /* first submit -> last completion */
+} sel_server_stats;
+
+/* Start a server (two worker threads, its own streams and a push-down
+ * context) on ctx's device.  cfg may be NULL for defaults. */
+sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_server** out);
+
+/* Queue a request; *ticket names it.  The arrays are copied; tables,
+ * programs and pd_out must stay valid until the request completes.
+ * Errors: SEL_E_INVALID (bad entries), SEL_E_BUSY (the request alone needs
+ * more than the budget: it is rejected, never queued), SEL_E_DEVICE (a
+ * worker failed). */
+sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ticket);
+
+/* *done = 1 once the request completed. */
+sel_status sel_server_poll(sel_server* s, uint64_t ticket, int* done);
+
+/* Block until the request completes; counts (host, nprog) and *res (either
+ * may be NULL) receive its results; the ticket is then released. */
+sel_status sel_server_wait(sel_server* s, uint64_t ticket, uint64_t* counts, sel_result* res);
+
+/* Counters and latency percentiles of completed requests (reset != 0
+ * clears them). */
+sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset);
+
+/* Finish in-flight work and stop.  Requests still queued are dropped. */
+void sel_server_destroy(sel_server* s);
+
 /* ---- launch configuration and timing ------------------------------------ */
 
 typedef struct sel_launch {

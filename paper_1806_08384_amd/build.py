@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libsel.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "api.cpp", "compile.cpp", "batch.cpp", "autotune.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "compile.cpp", "batch.cpp", "autotune.cpp", "serve.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # device code: gfx950 only; packed fp32 VALU ops stay disabled (no float
@@ -43,7 +43,7 @@ def build(verbose: bool = False, out: str = LIB) -> str:
         _run(cmd, verbose)
         objs.append(obj)
     tmp = out + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", *objs, "-o", tmp], verbose)
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", *objs, "-lpthread", "-o", tmp], verbose)
     os.replace(tmp, out)
     return out
 

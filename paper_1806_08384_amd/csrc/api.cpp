@@ -627,10 +627,19 @@ sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t k
   return SEL_OK;
 }
 
-sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
-                          uint32_t nfk, const uint32_t* fk_cols, const uint32_t* const* d_bitmaps,
-                          const uint64_t* nbits, uint64_t* out_count) {
-  if (!ctx || !fact || !out_count || !fk_cols || !d_bitmaps || !nbits)
+}  // extern "C"
+
+namespace {
+
+// The star semi-join as a program over the fact table: one bitmap-probe leaf
+// per foreign key (smallest bitmap first; each later probe only looks up rows
+// every earlier probe left TRUE or UNKNOWN), ANDed, then AND the optional
+// fact predicate.
+sel_status build_star_code(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
+                           uint32_t nfk, const uint32_t* fk_cols, const uint32_t* const* d_bitmaps,
+                           const uint64_t* nbits, std::vector<DevInstr>& code, double& bpr,
+                           int& depth) {
+  if (!ctx || !fact || !fk_cols || !d_bitmaps || !nbits)
     return set_err(ctx, SEL_E_INVALID, "NULL argument");
   if (nfk < 1 || nfk > 8) return set_err(ctx, SEL_E_INVALID, "nfk must be 1..8");
   if (fact_pred && fact_pred->table != fact)
@@ -647,10 +656,9 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
     if (!d_bitmaps[d]) return set_err(ctx, SEL_E_INVALID, "NULL bitmap");
     if (nbits[d] > (1ull << 32)) return set_err(ctx, SEL_E_INVALID, "nbits must be <= 2^32");
   }
-  // probe the smallest bitmaps first; each later probe only looks up rows
-  // that every earlier probe left TRUE or UNKNOWN
   std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return nbits[x] < nbits[y]; });
-  std::vector<DevInstr> code;
+  code.clear();
+  bpr = fact_pred ? fact_pred->bytes_per_row : 0.0;
   for (uint32_t k = 0; k < nfk; ++k) {
     const uint32_t d = order[k];
     const sel_column& c = fact->cols[fk_cols[d]];
@@ -668,7 +676,9 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
       I.span = nbits[d];
       I.aux = d_bitmaps[d];
       I.flags = k > 0 ? F_GUARD_AND : 0u;
+      bpr += type_bytes(I.type);
     }
+    if (c.valid) bpr += 1.0 / 8.0;
     code.push_back(I);
     if (k > 0) {
       DevInstr A{};
@@ -676,28 +686,86 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
       code.push_back(A);
     }
   }
+  depth = nfk > 1 ? 2 : 1;
   if (fact_pred) {
     for (const DevInstr& I : fact_pred->host_code) code.push_back(I);
     DevInstr A{};
     A.op = D_AND;
     code.push_back(A);
+    depth = std::max(depth, 1 + fact_pred->depth);
   }
   if (code.size() > 128) return set_err(ctx, SEL_E_INVALID, "combined program too long");
+  return SEL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
+                          uint32_t nfk, const uint32_t* fk_cols, const uint32_t* const* d_bitmaps,
+                          const uint64_t* nbits, uint64_t* out_count) {
+  if (!out_count) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  std::vector<DevInstr> code;
+  double bpr = 0;
+  int depth = 0;
+  sel_status st = build_star_code(ctx, fact, fact_pred, nfk, fk_cols, d_bitmaps, nbits, code, bpr, depth);
+  if (st != SEL_OK) return st;
   DeviceGuard g(ctx->device);
-  sel_status sst = stage_copy(ctx, ctx->dstar, code.data(), code.size() * sizeof(DevInstr));
-  if (sst != SEL_OK) return sst;
-  double star_bpr = fact_pred ? fact_pred->bytes_per_row : 0.0;
-  for (uint32_t d = 0; d < nfk; ++d) star_bpr += type_bytes(dev_type(fact->cols[fk_cols[d]].type));
-  const uint32_t star_cls = tune_class_of(star_bpr, (uint32_t)code.size());
+  st = stage_copy(ctx, ctx->dstar, code.data(), code.size() * sizeof(DevInstr));
+  if (st != SEL_OK) return st;
   ScanArgs a{};
   a.prog = ctx->dstar;
   a.nins = (uint32_t)code.size();
   a.nrows = fact->nrows;
   a.ntiles = ntiles_of(fact->nrows);
   a.out = ctx->dout;
-  sel_status st = run_scan(ctx, M_COUNT, star_cls, a, SEL_K_STAR);
+  st = run_scan(ctx, M_COUNT, tune_class_of(bpr, a.nins), a, SEL_K_STAR);
   if (st != SEL_OK) return st;
   return read_out(ctx, out_count, nullptr);
+}
+
+sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_program* fact_pred,
+                            uint32_t nfk, const uint32_t* fk_cols, const uint32_t* const* d_bitmaps,
+                            const uint64_t* nbits, sel_program** out) {
+  if (!out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  *out = nullptr;
+  std::vector<DevInstr> code;
+  double bpr = 0;
+  int depth = 0;
+  sel_status st = build_star_code(ctx, fact, fact_pred, nfk, fk_cols, d_bitmaps, nbits, code, bpr, depth);
+  if (st != SEL_OK) return st;
+  DeviceGuard g(ctx->device);
+  sel_program* p = new (std::nothrow) sel_program();
+  if (!p) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
+  p->ctx = ctx;
+  p->table = fact;
+  p->nins = (uint32_t)code.size();
+  p->depth = depth;
+  p->bytes_per_row = bpr;
+  p->tune_class = tune_class_of(bpr, p->nins);
+  p->host_code = code;
+  p->text = "STAR\n";
+  const size_t bytes = code.size() * sizeof(DevInstr);
+  p->dev = ctx->arena.alloc(bytes);
+  if (!p->dev) {
+    hipError_t he = hipMalloc(&p->dev, bytes);
+    if (he != hipSuccess) {
+      delete p;
+      return hip_err(ctx, he, "hipMalloc(program)");
+    }
+    p->own_alloc = true;
+  }
+  p->dcode = (DevInstr*)p->dev;
+  st = stage_copy(ctx, p->dev, code.data(), bytes);
+  if (st != SEL_OK) {
+    if (p->own_alloc) (void)hipFree(p->dev);
+    else ctx->arena.release(p->dev);
+    delete p;
+    return st;
+  }
+  *out = p;
+  return SEL_OK;
 }
 
 }  // extern "C"

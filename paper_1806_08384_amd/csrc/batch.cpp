@@ -63,6 +63,7 @@ sel_status plan(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
     BatchTable d{};
     d.nrows = t->nrows;
     d.tile_begin = tile;
+    d.row_begin = 0;
     d.prog_begin = (uint32_t)b.dp.size();
     for (uint32_t i = 0; i < n; ++i) {
       if (tables[i] != t) continue;
@@ -70,6 +71,7 @@ sel_status plan(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
       BatchProg p{};
       p.code = progs[i]->dcode;
       p.nins = progs[i]->nins;
+      p.acc_index = (uint32_t)b.dp.size();
       b.dp.push_back(p);
     }
     d.prog_count = (uint32_t)b.dp.size() - d.prog_begin;
@@ -135,6 +137,8 @@ BatchArgs args_of(const sel_batch& b) {
   a.nprogs = (uint32_t)b.dp.size();
   a.total_tiles = b.total_tiles;
   a.acc = b.d_acc;
+  a.done = nullptr;
+  a.ndone = (uint32_t)b.dp.size();
   a.out = b.d_out;
   a.slot = b.d_slot;
   return a;

@@ -501,9 +501,11 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
 }
 
 // Batched count.  Per workgroup, per-program counts accumulate in LDS; at
-// the end each workgroup adds them to per-program accumulators (one 128-byte
-// line each, so atomics on different programs do not contend), and the last
-// workgroup by ticket copies them out and zeroes them for the next launch.
+// the end each workgroup adds them to per-program accumulator lines (128
+// bytes each, so atomics on different programs do not contend), and the last
+// workgroup by ticket moves the finished lines out and zeroes them.  Entries
+// may be chunks of tables (row_begin), and lines not finished by this launch
+// keep accumulating: a cooperative scan adds one chunk per launch.
 __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   __shared__ uint32_t acc[kBatchMaxProgs];
   const uint32_t lane = threadIdx.x & 63;
@@ -522,7 +524,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
       if (tables[mid].tile_begin <= flat) lo = mid; else hi = mid;
     }
     const uint64_t nrows = tables[lo].nrows;
-    const uint64_t tb = (flat - tables[lo].tile_begin) * kTileRows;
+    const uint64_t tb = tables[lo].row_begin + (flat - tables[lo].tile_begin) * kTileRows;
     const uint32_t pb = tables[lo].prog_begin, pn = tables[lo].prog_count;
     const bool full = tb + kTileRows <= nrows;
     const uint32_t inr = full ? ~0u : inrange_bits(tb, lane, nrows);
@@ -537,7 +539,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   }
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x)
-    if (acc[p]) atomicAdd(&a.acc[(uint64_t)p * kBatchAccStride], (unsigned long long)acc[p]);
+    if (acc[p]) atomicAdd(&a.acc[(uint64_t)progs[p].acc_index * kBatchAccStride], (unsigned long long)acc[p]);
   __threadfence();
   __syncthreads();
   __shared__ bool last;
@@ -548,8 +550,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   __syncthreads();
   if (last) {
     __threadfence();
-    for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x) {
-      a.out[p] = atomicExch(&a.acc[(uint64_t)p * kBatchAccStride], 0ull);
+    for (uint32_t k = threadIdx.x; k < a.ndone; k += blockDim.x) {
+      const uint64_t line = a.done ? a.done[k] : k;
+      a.out[k] = atomicExch(&a.acc[line * kBatchAccStride], 0ull);
     }
     __threadfence();
     __syncthreads();

@@ -102,18 +102,18 @@ struct CompactArgs {
 // of all tables form one flat index space; a wave takes a tile and runs every
 // program bound to that tile's table on it, so programs sharing a table read
 // its columns from HBM once and from cache afterwards.
-struct BatchTable {            // 32 bytes
-  uint64_t nrows;
-  uint64_t tile_begin;         // first flat tile index of this table
+struct BatchTable {            // 32 bytes: one table, or one chunk of a table
+  uint64_t nrows;              // rows of the whole table
+  uint64_t tile_begin;         // first flat tile index of this entry
   uint32_t prog_begin;         // into the BatchProg array
   uint32_t prog_count;
-  uint64_t pad;
+  uint64_t row_begin;          // first row of the entry (a multiple of kTileRows)
 };
 
 struct BatchProg {             // 16 bytes
   const DevInstr* code;
   uint32_t nins;
-  uint32_t pad;
+  uint32_t acc_index;          // accumulator line this program adds into
 };
 
 constexpr int kBatchMaxProgs = 1024;
@@ -125,8 +125,14 @@ struct BatchArgs {
   uint32_t ntables;
   uint32_t nprogs;
   uint64_t total_tiles;
-  unsigned long long* acc;     // nprogs * kBatchAccStride, zero between launches
-  unsigned long long* out;     // nprogs counts
+  unsigned long long* acc;     // accumulator lines (kBatchAccStride u64 each)
+  // After the launch, the last workgroup moves accumulator done[k] to out[k]
+  // and zeroes it (k < ndone); done == nullptr means lines 0 .. ndone-1.
+  // Lines not listed keep accumulating across launches.
+  const uint32_t* done;
+  uint32_t ndone;
+  uint32_t pad;
+  unsigned long long* out;
   DevSlot* slot;
 };
 

@@ -1,0 +1,574 @@
+// serve.cpp -- continuous batching of estimate requests (the count queries
+// of Ch.3 sec.3.1 and the push-downs of Algorithm 1) over resident tables.
+//
+// Cooperative scans: every table with pending programs is cut into chunks
+// of chunk_rows rows.  A round is ONE batched launch that scans the current
+// chunk of every such table for every program attached to it, then advances
+// each table to its next chunk (wrapping around).  A program attaches at a
+// round boundary and is complete after one revolution over its table (one
+// round per chunk); counts of disjoint chunks add up to the exact count.
+// Requests arriving while rounds run are admitted as accumulator lines and
+// HBM budget free up, and their programs share the next round's scan.
+// Push-downs (count, limit check, ascending row ids) run on a second worker
+// with its own stream, concurrently with the rounds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace sel;
+using namespace selrt;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr uint32_t kMaxLines = 4096;        // accumulator lines (programs in flight)
+constexpr uint32_t kMaxRoundsInFlight = 4;
+
+struct Request {
+  uint64_t ticket = 0;
+  Clock::time_point t_submit, t_done;
+  std::vector<const sel_table*> tables;
+  std::vector<const sel_program*> progs;
+  std::vector<uint64_t> counts;
+  uint32_t remaining = 0;                   // programs not finished
+  bool has_pd = false, pd_done = true;
+  const sel_table* pd_table = nullptr;
+  const sel_program* pd_prog = nullptr;
+  uint64_t pd_max_rows = 0, pd_cap = 0, pd_count = 0;
+  uint32_t* pd_out = nullptr;
+  sel_status pd_status = SEL_OK;
+  uint64_t footprint = 0;
+  bool done = false;
+};
+
+struct Active {                             // one attached program
+  Request* req;
+  uint32_t index;                           // program index in the request
+  uint32_t line;                            // accumulator line
+  uint32_t chunks_left;
+};
+
+struct TableState {
+  const sel_table* table;
+  uint64_t nchunks;
+  uint64_t cur = 0;                         // chunk of the next round
+  std::vector<Active> progs;
+};
+
+struct RoundSlot {                          // per in-flight round
+  void* dev = nullptr;                      // descriptors | done list | out
+  size_t dev_bytes = 0;
+  char* host = nullptr;                     // pinned staging for descriptors
+  unsigned long long* h_out = nullptr;      // pinned, finished counts
+  hipEvent_t done_ev = nullptr;
+  DevSlot* slot = nullptr;                  // ticket of this slot's launches
+  std::vector<Active> finishing;            // programs finished by this round
+  bool busy = false;
+};
+
+}  // namespace
+
+struct sel_server {
+  sel_ctx* ctx = nullptr;
+  sel_server_config cfg{};
+  sel_ctx* pd_ctx = nullptr;                // own stream and scratch for push-downs
+  hipStream_t stream = nullptr;             // rounds
+  unsigned long long* d_acc = nullptr;      // kMaxLines lines
+  std::vector<uint32_t> free_lines;
+  std::vector<RoundSlot> slots;
+  std::deque<uint32_t> inflight;            // slot indices, oldest first
+  uint32_t next_slot = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> incoming;            // submitted, not admitted (FIFO)
+  std::deque<Request*> pd_queue;            // admitted push-downs
+  std::unordered_map<uint64_t, Request*> by_ticket;
+  std::map<const sel_table*, TableState> tables;
+  uint64_t next_ticket = 1;
+  uint64_t in_use = 0;                      // admitted footprint
+  uint32_t admitted = 0, lines_used = 0;
+  bool stop = false;
+  std::string error;                        // first device error of a worker
+
+  // statistics
+  uint64_t submitted = 0, completed = 0, rejected = 0, rounds = 0, round_programs = 0,
+           shared_rounds = 0;
+  uint32_t max_admitted = 0;
+  std::vector<double> latencies;
+  Clock::time_point t_first{}, t_last{};
+  bool any = false;
+
+  std::thread worker, pd_worker;
+};
+
+namespace {
+
+uint64_t chunk_rows_of(const sel_server* s) {
+  uint64_t c = s->cfg.chunk_rows ? s->cfg.chunk_rows : (1ull << 26);
+  return (c + kTileRows - 1) / kTileRows * kTileRows;
+}
+
+uint64_t footprint_of(const sel_server* s, const Request& r) {
+  uint64_t f = (uint64_t)r.progs.size() * kBatchAccStride * 8;
+  for (const sel_program* p : r.progs) f += p->nins * sizeof(DevInstr);
+  if (r.has_pd) {
+    const uint64_t nt = ntiles_of(r.pd_table->nrows);
+    f += nt * kWave * 4 + 2 * nt * 4 + r.pd_cap * 4;  // mask, tile counts, offsets, ids
+  }
+  return f;
+}
+
+void finish_request_locked(sel_server* s, Request* r) {
+  r->done = true;
+  r->t_done = Clock::now();
+  s->in_use -= r->footprint;
+  s->admitted -= 1;
+  s->completed += 1;
+  s->latencies.push_back(std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count());
+  s->t_last = r->t_done;
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();   // budget freed: admission may proceed
+}
+
+// Whether the oldest queued request fits the budget and the free lines now.
+bool admissible_locked(const sel_server* s) {
+  if (s->incoming.empty()) return false;
+  const uint64_t budget = s->cfg.hbm_budget_bytes ? s->cfg.hbm_budget_bytes : (1ull << 30);
+  const uint32_t max_lines = std::min<uint32_t>(s->cfg.max_programs ? s->cfg.max_programs : kMaxLines, kMaxLines);
+  const Request* r = s->incoming.front();
+  return s->in_use + r->footprint <= budget && s->lines_used + r->progs.size() <= max_lines;
+}
+
+// Admit queued requests in arrival order while budget and lines allow.
+void admit_locked(sel_server* s) {
+  while (admissible_locked(s)) {
+    Request* r = s->incoming.front();
+    s->incoming.pop_front();
+    s->in_use += r->footprint;
+    s->admitted += 1;
+    s->max_admitted = std::max(s->max_admitted, s->admitted);
+    for (uint32_t i = 0; i < r->progs.size(); ++i) {
+      auto it = s->tables.find(r->tables[i]);
+      if (it == s->tables.end()) {
+        TableState ts;
+        ts.table = r->tables[i];
+        ts.nchunks = std::max<uint64_t>(1, (r->tables[i]->nrows + chunk_rows_of(s) - 1) / chunk_rows_of(s));
+        it = s->tables.emplace(r->tables[i], ts).first;
+      }
+      const uint32_t line = s->free_lines.back();
+      s->free_lines.pop_back();
+      s->lines_used += 1;
+      it->second.progs.push_back(Active{r, i, line, (uint32_t)it->second.nchunks});
+    }
+    if (r->has_pd) s->pd_queue.push_back(r);
+    if (r->remaining == 0 && r->pd_done) finish_request_locked(s, r);
+  }
+}
+
+// Host side of a finished round: hand out the counts it finished.
+void retire_round(sel_server* s, RoundSlot& rs) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (size_t k = 0; k < rs.finishing.size(); ++k) {
+    const Active& a = rs.finishing[k];
+    a.req->counts[a.index] = rs.h_out[k];
+    a.req->remaining -= 1;
+    s->free_lines.push_back(a.line);
+    s->lines_used -= 1;
+    if (a.req->remaining == 0 && a.req->pd_done) finish_request_locked(s, a.req);
+  }
+  rs.finishing.clear();
+  rs.busy = false;
+}
+
+bool wait_oldest(sel_server* s) {
+  const uint32_t k = s->inflight.front();
+  s->inflight.pop_front();
+  if (hipEventSynchronize(s->slots[k].done_ev) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->error.empty()) s->error = "round failed on the device";
+    return false;
+  }
+  retire_round(s, s->slots[k]);
+  return true;
+}
+
+// Build and launch one round; returns false if there was nothing to do.
+bool launch_round(sel_server* s) {
+  RoundSlot& rs = s->slots[s->next_slot];
+  std::vector<BatchTable> dt;
+  std::vector<BatchProg> dp;
+  std::vector<uint32_t> done;
+  uint64_t tile = 0;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    const uint64_t crow = chunk_rows_of(s);
+    for (auto& kv : s->tables) {
+      TableState& ts = kv.second;
+      if (ts.progs.empty()) continue;
+      const uint64_t row_begin = ts.cur * crow;
+      const uint64_t row_end = std::min(ts.table->nrows, row_begin + crow);
+      BatchTable d{};
+      d.nrows = ts.table->nrows;
+      d.tile_begin = tile;
+      d.row_begin = row_begin;
+      d.prog_begin = (uint32_t)dp.size();
+      const Request* first = nullptr;
+      bool shared = false;
+      for (Active& a : ts.progs) {
+        BatchProg p{};
+        p.code = a.req->progs[a.index]->dcode;
+        p.nins = a.req->progs[a.index]->nins;
+        p.acc_index = a.line;
+        dp.push_back(p);
+        if (!first) first = a.req;
+        else if (a.req != first) shared = true;
+        a.chunks_left -= 1;
+        if (a.chunks_left == 0) {
+          done.push_back(a.line);
+          rs.finishing.push_back(a);
+        }
+      }
+      d.prog_count = (uint32_t)dp.size() - d.prog_begin;
+      ts.progs.erase(std::remove_if(ts.progs.begin(), ts.progs.end(),
+                                    [](const Active& a) { return a.chunks_left == 0; }),
+                     ts.progs.end());
+      ts.cur = (ts.cur + 1) % ts.nchunks;
+      if (row_end > row_begin) {
+        tile += (row_end - row_begin + kTileRows - 1) / kTileRows;
+        dt.push_back(d);
+      } else {
+        d.tile_begin = tile;
+        dt.push_back(d);   // an empty table: no tiles, its programs still finish
+      }
+      s->shared_rounds += shared ? 1 : 0;
+    }
+    if (dp.empty()) {
+      rs.finishing.clear();
+      return false;
+    }
+    s->rounds += 1;
+    s->round_programs += dp.size();
+  }
+  // descriptors: tables | progs | done list, staged through pinned memory
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_progs = up(dt.size() * sizeof(BatchTable));
+  const size_t o_done = up(o_progs + dp.size() * sizeof(BatchProg));
+  const size_t o_out = up(o_done + std::max<size_t>(1, done.size()) * 4);
+  const size_t need = o_out + std::max<size_t>(1, done.size()) * 8;
+  if (need > rs.dev_bytes) {
+    if (rs.dev) (void)hipFree(rs.dev);
+    if (rs.host) (void)hipHostFree(rs.host);
+    if (rs.h_out) (void)hipHostFree(rs.h_out);
+    rs.dev = nullptr;
+    rs.host = nullptr;
+    rs.h_out = nullptr;
+    const size_t want = std::max(need * 2, size_t(1) << 16);
+    if (hipMalloc(&rs.dev, want) != hipSuccess || hipHostMalloc((void**)&rs.host, want, 0) != hipSuccess ||
+        hipHostMalloc((void**)&rs.h_out, want, 0) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->error = "out of memory for round descriptors";
+      return false;
+    }
+    rs.dev_bytes = want;
+  }
+  std::memcpy(rs.host, dt.data(), dt.size() * sizeof(BatchTable));
+  std::memcpy(rs.host + o_progs, dp.data(), dp.size() * sizeof(BatchProg));
+  if (!done.empty()) std::memcpy(rs.host + o_done, done.data(), done.size() * 4);
+  BatchArgs a{};
+  a.tables = (const BatchTable*)rs.dev;
+  a.progs = (const BatchProg*)((char*)rs.dev + o_progs);
+  a.ntables = (uint32_t)dt.size();
+  a.nprogs = (uint32_t)dp.size();
+  a.total_tiles = tile;
+  a.acc = s->d_acc;
+  a.done = (const uint32_t*)((char*)rs.dev + o_done);
+  a.ndone = (uint32_t)done.size();
+  a.out = (unsigned long long*)((char*)rs.dev + o_out);
+  a.slot = rs.slot;
+  const uint32_t block = 256;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>((uint64_t)4 * s->ctx->num_cus, (tile + 3) / 4));
+  bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
+  ok = ok && sel_launch_batch(a, grid, block, s->stream) == 0;
+  if (!done.empty())
+    ok = ok && hipMemcpyAsync(rs.h_out, a.out, done.size() * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+  ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
+  if (!ok) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->error.empty()) s->error = "round launch failed";
+    return false;
+  }
+  rs.busy = true;
+  s->inflight.push_back(s->next_slot);
+  s->next_slot = (s->next_slot + 1) % (uint32_t)s->slots.size();
+  return true;
+}
+
+void worker_main(sel_server* s) {
+  (void)hipSetDevice(s->ctx->device);
+  const uint32_t depth = std::min<uint32_t>(
+      s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 2, kMaxRoundsInFlight);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      admit_locked(s);
+      bool active = false;
+      for (auto& kv : s->tables) active |= !kv.second.progs.empty();
+      if (!active && s->inflight.empty()) {
+        if (s->stop) break;
+        // sleep until a request can be admitted (a finished push-down frees
+        // budget and notifies) or the server stops
+        s->cv_work.wait(lk, [&] { return s->stop || admissible_locked(s); });
+        continue;
+      }
+    }
+    // keep `depth` rounds queued on the device; prepare the next meanwhile
+    if (s->inflight.size() >= depth || s->slots[s->next_slot].busy) {
+      if (!wait_oldest(s)) break;
+      continue;
+    }
+    if (!launch_round(s)) {
+      if (!s->inflight.empty()) {
+        if (!wait_oldest(s)) break;
+      } else {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->error.empty()) break;
+      }
+    }
+  }
+  while (!s->inflight.empty()) {
+    if (!wait_oldest(s)) break;
+  }
+}
+
+void pd_worker_main(sel_server* s) {
+  (void)hipSetDevice(s->ctx->device);
+  for (;;) {
+    Request* r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_work.wait(lk, [&] { return s->stop || !s->pd_queue.empty(); });
+      if (s->pd_queue.empty()) break;   // stop and nothing left
+      r = s->pd_queue.front();
+      s->pd_queue.pop_front();
+    }
+    uint64_t cnt = 0;
+    sel_status st = sel_pushdown_rowids(s->pd_ctx, r->pd_table, r->pd_prog, r->pd_max_rows, r->pd_out,
+                                        r->pd_cap, &cnt);
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->pd_status = st;
+    r->pd_count = cnt;
+    r->pd_done = true;
+    if (st < 0 && s->error.empty()) s->error = sel_last_error(s->pd_ctx);
+    if (r->remaining == 0) finish_request_locked(s, r);
+  }
+}
+
+void release_server(sel_server* s) {
+  for (RoundSlot& rs : s->slots) {
+    if (rs.done_ev) (void)hipEventDestroy(rs.done_ev);
+    if (rs.dev) (void)hipFree(rs.dev);
+    if (rs.host) (void)hipHostFree(rs.host);
+    if (rs.h_out) (void)hipHostFree(rs.h_out);
+  }
+  if (s->d_acc) (void)hipFree(s->d_acc);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  if (s->pd_ctx) sel_ctx_destroy(s->pd_ctx);
+  for (auto& kv : s->by_ticket) delete kv.second;
+  delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_server** out) {
+  if (!ctx || !out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
+  *out = nullptr;
+  sel_server* s = new (std::nothrow) sel_server();
+  if (!s) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
+  s->ctx = ctx;
+  if (cfg) s->cfg = *cfg;
+  DeviceGuard g(ctx->device);
+  const uint32_t depth = std::min<uint32_t>(s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 2, kMaxRoundsInFlight);
+  s->slots.resize(depth + 1);
+  hipError_t e = hipSuccess;
+  const char* where = "";
+  do {
+    if ((e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking)) != hipSuccess) { where = "hipStreamCreate"; break; }
+    const size_t acc_bytes = (size_t)kMaxLines * kBatchAccStride * 8;
+    const size_t slot_bytes = 256 * s->slots.size();
+    if ((e = hipMalloc((void**)&s->d_acc, acc_bytes + slot_bytes)) != hipSuccess) { where = "hipMalloc(server)"; break; }
+    if ((e = hipMemset(s->d_acc, 0, acc_bytes + slot_bytes)) != hipSuccess) { where = "hipMemset(server)"; break; }
+    for (size_t k = 0; k < s->slots.size(); ++k) {
+      s->slots[k].slot = (DevSlot*)((char*)s->d_acc + acc_bytes + 256 * k);
+      if ((e = hipEventCreateWithFlags(&s->slots[k].done_ev, hipEventDisableTiming)) != hipSuccess) { where = "hipEventCreate"; break; }
+    }
+  } while (0);
+  if (e != hipSuccess) {
+    sel_status st = hip_err(ctx, e, where);
+    release_server(s);
+    return st;
+  }
+  sel_status st = sel_ctx_create(ctx->device, nullptr, &s->pd_ctx);
+  if (st != SEL_OK) {
+    set_err(ctx, st, "push-down context");
+    release_server(s);
+    return st;
+  }
+  for (uint32_t l = 0; l < kMaxLines; ++l) s->free_lines.push_back(kMaxLines - 1 - l);
+  s->worker = std::thread(worker_main, s);
+  s->pd_worker = std::thread(pd_worker_main, s);
+  *out = s;
+  return SEL_OK;
+}
+
+sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ticket) {
+  if (!s || !req || !ticket) return SEL_E_INVALID;
+  sel_ctx* ctx = s->ctx;
+  if (req->nprog > 0 && (!req->tables || !req->progs)) return set_err(ctx, SEL_E_INVALID, "NULL arrays");
+  if (req->nprog == 0 && !req->pd_table) return set_err(ctx, SEL_E_INVALID, "empty request");
+  Request* r = new (std::nothrow) Request();
+  if (!r) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
+  r->t_submit = Clock::now();
+  for (uint32_t i = 0; i < req->nprog; ++i) {
+    if (!req->tables[i] || !req->progs[i] || req->progs[i]->table != req->tables[i]) {
+      delete r;
+      return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " missing or bound to another table");
+    }
+    r->tables.push_back(req->tables[i]);
+    r->progs.push_back(req->progs[i]);
+  }
+  r->counts.assign(req->nprog, 0);
+  r->remaining = req->nprog;
+  if (req->pd_table) {
+    if (!req->pd_prog || req->pd_prog->table != req->pd_table ||
+        (!req->pd_out && req->pd_cap > 0)) {
+      delete r;
+      return set_err(ctx, SEL_E_INVALID, "bad push-down item");
+    }
+    r->has_pd = true;
+    r->pd_done = false;
+    r->pd_table = req->pd_table;
+    r->pd_prog = req->pd_prog;
+    r->pd_max_rows = req->pd_max_rows;
+    r->pd_out = req->pd_out;
+    r->pd_cap = req->pd_cap;
+  }
+  r->footprint = footprint_of(s, *r);
+  const uint64_t budget = s->cfg.hbm_budget_bytes ? s->cfg.hbm_budget_bytes : (1ull << 30);
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (!s->error.empty()) {
+    delete r;
+    return set_err(ctx, SEL_E_DEVICE, s->error);
+  }
+  if (r->footprint > budget || r->progs.size() > kMaxLines) {
+    s->rejected += 1;
+    delete r;
+    return set_err(ctx, SEL_E_BUSY, "request needs more device memory than the server's budget");
+  }
+  r->ticket = s->next_ticket++;
+  s->by_ticket[r->ticket] = r;
+  s->incoming.push_back(r);
+  s->submitted += 1;
+  if (!s->any) {
+    s->any = true;
+    s->t_first = r->t_submit;
+  }
+  *ticket = r->ticket;
+  s->cv_work.notify_all();
+  return SEL_OK;
+}
+
+sel_status sel_server_poll(sel_server* s, uint64_t ticket, int* done) {
+  if (!s || !done) return SEL_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return set_err(s->ctx, SEL_E_INVALID, "unknown ticket");
+  *done = it->second->done ? 1 : 0;
+  return SEL_OK;
+}
+
+sel_status sel_server_wait(sel_server* s, uint64_t ticket, uint64_t* counts, sel_result* res) {
+  if (!s) return SEL_E_INVALID;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->by_ticket.find(ticket);
+  if (it == s->by_ticket.end()) return set_err(s->ctx, SEL_E_INVALID, "unknown ticket");
+  Request* r = it->second;
+  s->cv_done.wait(lk, [&] { return r->done || !s->error.empty(); });
+  if (!r->done) return set_err(s->ctx, SEL_E_DEVICE, s->error);
+  if (counts) std::copy(r->counts.begin(), r->counts.end(), counts);
+  if (res) {
+    res->status = r->pd_status;
+    res->pd_count = r->pd_count;
+    res->latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  }
+  s->by_ticket.erase(it);
+  delete r;
+  return SEL_OK;
+}
+
+sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset) {
+  if (!s || !out) return SEL_E_INVALID;
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof *out);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->rejected = s->rejected;
+  out->rounds = s->rounds;
+  out->round_programs = s->round_programs;
+  out->shared_rounds = s->shared_rounds;
+  out->max_admitted = s->max_admitted;
+  std::vector<double> v = s->latencies;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double q) {
+      size_t k = (size_t)std::min<double>((double)v.size() - 1, std::max(0.0, q * (double)(v.size() - 1) + 0.5));
+      return v[k];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_ms = sum / (double)v.size();
+    out->max_ms = v.back();
+  }
+  if (s->any && s->completed) out->elapsed_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
+  if (reset) {
+    s->submitted = s->completed = s->rejected = s->rounds = s->round_programs = s->shared_rounds = 0;
+    s->max_admitted = s->admitted;
+    s->latencies.clear();
+    s->any = false;
+  }
+  return SEL_OK;
+}
+
+void sel_server_destroy(sel_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  if (s->pd_worker.joinable()) s->pd_worker.join();
+  DeviceGuard g(s->ctx->device);
+  (void)hipStreamSynchronize(s->stream);
+  release_server(s);
+}
+
+}  // extern "C"

@@ -62,6 +62,33 @@ class sel_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32)]
 
 
+class sel_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_uint64),
+                ("max_programs", ctypes.c_uint32), ("rounds_in_flight", ctypes.c_uint32)]
+
+
+class sel_request(ctypes.Structure):
+    _fields_ = [("nprog", ctypes.c_uint32), ("tables", ctypes.POINTER(ctypes.c_void_p)),
+                ("progs", ctypes.POINTER(ctypes.c_void_p)), ("pd_table", ctypes.c_void_p),
+                ("pd_prog", ctypes.c_void_p), ("pd_max_rows", ctypes.c_uint64),
+                ("pd_out", ctypes.c_void_p), ("pd_cap", ctypes.c_uint64)]
+
+
+class sel_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("pd_count", ctypes.c_uint64),
+                ("latency_ms", ctypes.c_double)]
+
+
+class sel_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("rejected", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("round_programs", ctypes.c_uint64), ("shared_rounds", ctypes.c_uint64),
+                ("max_admitted", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("elapsed_s", ctypes.c_double)]
+
+
 class sel_timing(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * K_NKINDS), ("launches", ctypes.c_uint64 * K_NKINDS)]
 
@@ -113,6 +140,14 @@ sel_autotune_batch = _sig("sel_autotune_batch", _i32, _vp, _u32, _P(_vp), _P(_vp
 sel_tune_save = _sig("sel_tune_save", _i32, _vp, ctypes.c_char_p)
 sel_tune_load = _sig("sel_tune_load", _i32, _vp, ctypes.c_char_p)
 sel_tune_entries = _sig("sel_tune_entries", _u32, _vp)
+sel_program_star = _sig("sel_program_star", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
+                        _P(_vp))
+sel_server_create = _sig("sel_server_create", _i32, _vp, _P(sel_server_config), _P(_vp))
+sel_server_submit = _sig("sel_server_submit", _i32, _vp, _P(sel_request), _P(_u64))
+sel_server_poll = _sig("sel_server_poll", _i32, _vp, _u64, _P(ctypes.c_int))
+sel_server_wait = _sig("sel_server_wait", _i32, _vp, _u64, _P(_u64), _P(sel_result))
+sel_server_get_stats = _sig("sel_server_get_stats", _i32, _vp, _P(sel_server_stats), ctypes.c_int)
+sel_server_destroy = _sig("sel_server_destroy", None, _vp)
 sel_ctx_set_launch = _sig("sel_ctx_set_launch", _i32, _vp, _P(sel_launch))
 sel_ctx_enable_timing = _sig("sel_ctx_enable_timing", _i32, _vp, ctypes.c_int)
 sel_ctx_read_timing = _sig("sel_ctx_read_timing", _i32, _vp, _P(sel_timing), ctypes.c_int)
@@ -234,7 +269,7 @@ class Context:
         """Destroy the context after every table and program made from it."""
         if self.h:
             kids = list(self._children)
-            for kind in (Batch, Program, DeviceTable):
+            for kind in (Server, Batch, Program, DeviceTable):
                 for k in kids:
                     if isinstance(k, kind):
                         k.destroy()
@@ -344,6 +379,14 @@ class Context:
     def tune_entries(self) -> int:
         return int(sel_tune_entries(self.h))
 
+    def star_program(self, fact, fk_cols, bitmaps, nbits, fact_pred=None):
+        """The star semi-join as a program over the fact table (bitmaps are
+        borrowed: keep the tensors alive while the program is used)."""
+        return Program(self, fact, None, star=(fk_cols, bitmaps, nbits, fact_pred))
+
+    def server(self, **cfg):
+        return Server(self, **cfg)
+
     def set_launch(self, block=None, grid=0):
         if block is None:
             self.check(sel_ctx_set_launch(self.h, None))
@@ -396,6 +439,70 @@ class Batch:
             pass
 
 
+class Server:
+    """sel_server: continuous batching of estimate requests over resident
+    tables (cooperative scans, HBM-footprint admission, push-downs on their
+    own stream)."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes=0, chunk_rows=0, max_programs=0,
+                 rounds_in_flight=0):
+        self.ctx = ctx
+        cfg = sel_server_config(hbm_budget_bytes, chunk_rows, max_programs, rounds_in_flight)
+        h = _vp()
+        ctx.check(sel_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+        self._pending = {}
+        ctx._children.add(self)
+
+    def submit(self, pairs, pushdown=None):
+        """pairs: [(table, program), ...]; pushdown: None or (table, program,
+        max_rows, out_tensor).  Returns a ticket."""
+        n = len(pairs)
+        ts = (_vp * max(1, n))(*[t.h.value for t, _ in pairs])
+        ps = (_vp * max(1, n))(*[p.h.value for _, p in pairs])
+        req = sel_request()
+        req.nprog = n
+        req.tables = ctypes.cast(ts, ctypes.POINTER(_vp))
+        req.progs = ctypes.cast(ps, ctypes.POINTER(_vp))
+        if pushdown is not None:
+            pt, pp, mx, out = pushdown
+            req.pd_table, req.pd_prog, req.pd_max_rows = pt.h.value, pp.h.value, mx
+            req.pd_out, req.pd_cap = out.data_ptr(), out.numel()
+        tk = _u64(0)
+        self.ctx.check(sel_server_submit(self.h, ctypes.byref(req), ctypes.byref(tk)))
+        self._pending[int(tk.value)] = (n, pairs, pushdown)
+        return int(tk.value)
+
+    def poll(self, ticket) -> bool:
+        d = ctypes.c_int(0)
+        self.ctx.check(sel_server_poll(self.h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket):
+        """Returns (counts, pushdown status, pushdown count, latency ms)."""
+        n, _, _ = self._pending.pop(ticket)
+        counts = (_u64 * max(1, n))()
+        res = sel_result()
+        self.ctx.check(sel_server_wait(self.h, ticket, counts, ctypes.byref(res)))
+        return [int(counts[i]) for i in range(n)], int(res.status), int(res.pd_count), res.latency_ms
+
+    def stats(self, reset=False):
+        st = sel_server_stats()
+        self.ctx.check(sel_server_get_stats(self.h, ctypes.byref(st), 1 if reset else 0))
+        return {k: getattr(st, k) for k, _ in sel_server_stats._fields_ if k != "pad"}
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            sel_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
 def max_rows(nrows: int, ratio: float) -> int:
     return int(sel_max_rows(nrows, ratio))
 
@@ -424,14 +531,23 @@ class DeviceTable:
 
 
 class Program:
-    def __init__(self, ctx: Context, table: DeviceTable, tree):
+    def __init__(self, ctx: Context, table: DeviceTable, tree, star=None):
         self.ctx = ctx
         self.table = table
-        code, pool = flatten(tree)
-        pbuf = ctypes.create_string_buffer(pool, max(1, len(pool)))
         h = _vp()
-        ctx.check(sel_program_compile(ctx.h, table.h, code, len(code), pbuf, len(pool),
-                                      ctypes.byref(h)))
+        if star is None:
+            code, pool = flatten(tree)
+            pbuf = ctypes.create_string_buffer(pool, max(1, len(pool)))
+            ctx.check(sel_program_compile(ctx.h, table.h, code, len(code), pbuf, len(pool),
+                                          ctypes.byref(h)))
+        else:
+            fk_cols, bitmaps, nbits, fact_pred = star
+            n = len(fk_cols)
+            self._bitmaps = list(bitmaps)
+            ctx.check(sel_program_star(ctx.h, table.h, fact_pred.h if fact_pred is not None else None,
+                                       n, (_u32 * n)(*fk_cols),
+                                       (_vp * n)(*[b.data_ptr() for b in bitmaps]),
+                                       (_u64 * n)(*nbits), ctypes.byref(h)))
         self.h = h
         ctx._children.add(self)
 

@@ -1,0 +1,192 @@
+"""GPU: the serving loop (continuous batching with cooperative scans).
+Every request's results in a mixed, overlapping stream equal its results
+alone (counts exact, row ids bit-identical), and admission by device
+footprint holds requests back or rejects them without failing."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.gpu_common import say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sel():
+    if not torch.cuda.is_available():
+        pytest.fail("gpu test run without a GPU")
+    from paper_1806_08384_amd import sel as s
+    return s
+
+
+@pytest.fixture(scope="module")
+def ctx(sel):
+    c = sel.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def world(sel, ctx):
+    """Five resident tables (a uniform int32 table, three fact-schema tables
+    and a star fact table with four dimensions) and a program pool each."""
+    say("serve: building tables and pools")
+    host = [datagen.cfg1(200_000, seed=7),
+            datagen.lineorder_like("t1", 300_000, 32),
+            datagen.lineorder_like("t2", 1_000_003, 33),
+            datagen.lineorder_like("t3", 3_000_000, 2)]
+    dims = datagen.star_dims(seed=42, sizes=(2556, 3000, 20_000, 32_000))
+    fact = datagen.star_fact(2_000_000, dim_rows=(2556, 3000, 20_000, 32_000))
+    dts = [sel.device_table(ctx, t) for t in host]
+    dfact = sel.device_table(ctx, fact)
+    ddims = [sel.device_table(ctx, d) for d in dims]
+    pools = [[ctx.program(dts[0], t) for t in datagen.uniform3_programs(11, 16)]]
+    for k in (1, 2, 3):
+        trees = [tree for _, tree in datagen.cfg3_programs(seed=100 + k, per_table=16, ntables=1)]
+        pools.append([ctx.program(dts[k], t) for t in trees])
+    star_pool, keep = [], []
+    for combo in datagen.star_dim_programs(9, 8, dims):
+        bms, nbits = [], []
+        for d, p in zip(ddims, combo):
+            bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+            st, _ = ctx.pushdown_keybitmap(d, 0, 0, ctx.program(d, p), bm, d.nrows)
+            assert st == sel.SEL_OK
+            bms.append(bm)
+            nbits.append(d.nrows)
+        keep.append(bms)
+        star_pool.append(ctx.star_program(dfact, [0, 1, 2, 3], bms, nbits))
+    pools.append(star_pool)
+    tables = dts + [dfact]
+    alone = [[ctx.count(tables[k], p) for p in pool] for k, pool in enumerate(pools)]
+    # the star programs equal the star count call, and (a sample) the oracle
+    assert alone[4][0] == ctx.star_count(dfact, [0, 1, 2, 3], keep[0],
+                                         [d.nrows for d in ddims])
+    o3 = oracle.Oracle(host[3])
+    trees3 = [tree for _, tree in datagen.cfg3_programs(seed=103, per_table=16, ntables=1)]
+    assert [o3.count(t, threads=8) for t in trees3[:4]] == alone[3][:4]
+    return dict(tables=tables, pools=pools, alone=alone, keep=keep, host=host)
+
+
+def run_trace(sel, ctx, world, trace, srv, time_scale=1.0):
+    """Submit the trace at its (scaled) arrival times from a client thread;
+    return [(counts, pd_status, pd_count, latency, ids)] in trace order."""
+    tables, pools = world["tables"], world["pools"]
+    tickets = [None] * len(trace)
+    outs = [None] * len(trace)
+    err = []
+
+    def client():
+        t0 = time.perf_counter()
+        try:
+            for i, (t, items, pd) in enumerate(trace):
+                while time.perf_counter() - t0 < t * time_scale:
+                    time.sleep(0.0001)
+                pairs = [(tables[tb], pools[tb][pi]) for tb, pi in items]
+                pdarg = None
+                if pd is not None:
+                    tb, pi = pd
+                    mx = sel.max_rows(tables[tb].nrows, 0.05)
+                    out = torch.full((max(1, mx),), -1, dtype=torch.int32, device="cuda")
+                    outs[i] = out
+                    pdarg = (tables[tb], pools[tb][pi], mx, out)
+                tickets[i] = srv.submit(pairs, pdarg)
+        except Exception as e:  # surfaced by the main thread
+            err.append(e)
+
+    th = threading.Thread(target=client)
+    th.start()
+    results = []
+    for i in range(len(trace)):
+        while tickets[i] is None and not err:
+            time.sleep(0.0001)
+        if err:
+            break
+        counts, st, pdc, lat = srv.wait(tickets[i])
+        results.append((counts, st, pdc, lat, outs[i]))
+    th.join()
+    if err:
+        raise err[0]
+    return results
+
+
+def test_mix_equals_alone(sel, ctx, world):
+    trace = datagen.serving_trace(seed=5, rate=4000.0, duration=0.1,
+                                  pool_sizes=(16, 16, 16, 16, 8))
+    say(f"serve: {len(trace)} requests")
+    srv = ctx.server(chunk_rows=1 << 18, hbm_budget_bytes=1 << 30)
+    res = run_trace(sel, ctx, world, trace, srv)
+    stats = srv.stats()
+    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    for (t, items, pd), (counts, st, pdc, lat, out) in zip(trace, res):
+        assert counts == [alone[tb][pi] for tb, pi in items]
+        if pd is not None:
+            tb, pi = pd
+            mx = sel.max_rows(tables[tb].nrows, 0.05)
+            want = torch.full((max(1, mx),), -1, dtype=torch.int32, device="cuda")
+            wst, wcnt = ctx.pushdown_rowids(tables[tb], pools[tb][pi], mx, want)
+            assert (st, pdc) == (wst, wcnt)
+            assert torch.equal(out, want)     # ids, or untouched when over the limit
+    assert stats["completed"] == len(trace)
+    # work of different requests overlapped: shared scans, several admitted
+    assert stats["shared_rounds"] > 0 and stats["max_admitted"] > 1
+    say(f"serve stats: {stats}")
+    srv.destroy()
+
+
+def test_single_request_alone(sel, ctx, world):
+    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    srv = ctx.server()
+    for tb in range(5):
+        tk = srv.submit([(tables[tb], pools[tb][1])])
+        counts, st, pdc, lat = srv.wait(tk)
+        assert counts == [alone[tb][1]] and st == sel.SEL_OK and lat > 0
+    # a push-down only request
+    mx = sel.max_rows(tables[3].nrows, 0.5)
+    out = torch.empty(mx, dtype=torch.int32, device="cuda")
+    tk = srv.submit([], (tables[3], pools[3][0], mx, out))
+    counts, st, pdc, lat = srv.wait(tk)
+    assert counts == [] and pdc == alone[3][0]
+    srv.destroy()
+
+
+def test_admission_by_footprint(sel, ctx, world):
+    """A tiny budget: a request larger than the budget is rejected; requests
+    that fit alone but not together wait for each other; all finish."""
+    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    srv = ctx.server(hbm_budget_bytes=12_000, chunk_rows=1 << 18)
+    out = torch.empty(1000, dtype=torch.int32, device="cuda")
+    with pytest.raises(sel.SelError) as ei:
+        srv.submit([], (tables[3], pools[3][0], 1000, out))   # mask alone > budget
+    assert ei.value.status == sel.SEL_E_BUSY
+    rng = np.random.default_rng(1)
+    reqs = []
+    for _ in range(40):
+        items = [(int(rng.integers(0, 5)), int(rng.integers(0, 8))) for _ in range(8)]
+        reqs.append(items)
+    tks = [srv.submit([(tables[tb], pools[tb][pi]) for tb, pi in it]) for it in reqs]
+    for it, tk in zip(reqs, tks):
+        counts, st, pdc, lat = srv.wait(tk)
+        assert counts == [alone[tb][pi] for tb, pi in it]
+    stats = srv.stats()
+    assert stats["rejected"] == 1
+    assert stats["max_admitted"] < 40          # the budget held requests back
+    srv.destroy()
+
+
+def test_chunk_sizes_agree(sel, ctx, world):
+    """The same requests with one chunk per table and with many chunks."""
+    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    trace = datagen.serving_trace(seed=8, rate=2000.0, duration=0.03,
+                                  pool_sizes=(16, 16, 16, 16, 8), pushdown_rate=0.0)
+    for chunk in (1 << 32, 1 << 16, 2048):
+        srv = ctx.server(chunk_rows=chunk, rounds_in_flight=3)
+        res = run_trace(sel, ctx, world, trace, srv, time_scale=0.0)
+        for (t, items, pd), (counts, *_rest) in zip(trace, res):
+            assert counts == [alone[tb][pi] for tb, pi in items], chunk
+        srv.destroy()
