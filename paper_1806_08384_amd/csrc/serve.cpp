@@ -132,6 +132,13 @@ uint64_t footprint_of(const sel_server* s, const Request& r) {
   return f;
 }
 
+// Record the first worker error and wake everyone waiting on the server.
+void set_error_locked(sel_server* s, const std::string& msg) {
+  if (s->error.empty()) s->error = msg;
+  s->cv_done.notify_all();
+  s->cv_work.notify_all();
+}
+
 void finish_request_locked(sel_server* s, Request* r) {
   r->done = true;
   r->t_done = Clock::now();
@@ -174,7 +181,10 @@ void admit_locked(sel_server* s) {
       s->lines_used += 1;
       it->second.progs.push_back(Active{r, i, line, (uint32_t)it->second.nchunks});
     }
-    if (r->has_pd) s->pd_queue.push_back(r);
+    if (r->has_pd) {
+      s->pd_queue.push_back(r);
+      s->cv_work.notify_all();   // wake the push-down worker
+    }
     if (r->remaining == 0 && r->pd_done) finish_request_locked(s, r);
   }
 }
@@ -199,7 +209,7 @@ bool wait_oldest(sel_server* s) {
   s->inflight.pop_front();
   if (hipEventSynchronize(s->slots[k].done_ev) != hipSuccess) {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->error.empty()) s->error = "round failed on the device";
+    set_error_locked(s, "round failed on the device");
     return false;
   }
   retire_round(s, s->slots[k]);
@@ -280,7 +290,7 @@ bool launch_round(sel_server* s) {
     if (hipMalloc(&rs.dev, want) != hipSuccess || hipHostMalloc((void**)&rs.host, want, 0) != hipSuccess ||
         hipHostMalloc((void**)&rs.h_out, want, 0) != hipSuccess) {
       std::lock_guard<std::mutex> lk(s->mu);
-      s->error = "out of memory for round descriptors";
+      set_error_locked(s, "out of memory for round descriptors");
       return false;
     }
     rs.dev_bytes = want;
@@ -309,7 +319,7 @@ bool launch_round(sel_server* s) {
   ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
   if (!ok) {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->error.empty()) s->error = "round launch failed";
+    set_error_locked(s, "round launch failed");
     return false;
   }
   rs.busy = true;
@@ -373,7 +383,7 @@ void pd_worker_main(sel_server* s) {
     r->pd_status = st;
     r->pd_count = cnt;
     r->pd_done = true;
-    if (st < 0 && s->error.empty()) s->error = sel_last_error(s->pd_ctx);
+    if (st == SEL_E_DEVICE || st == SEL_E_NOMEM) set_error_locked(s, sel_last_error(s->pd_ctx));
     if (r->remaining == 0) finish_request_locked(s, r);
   }
 }
