@@ -311,6 +311,8 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
  * device footprint (accumulators, program code, and for a push-down the
  * result mask, tile counts and its id capacity) fits the budget beside the
  * admitted ones; push-downs run on their own stream, overlapping the rounds.
+ * Identical programs (the same sel_program) attached by different requests
+ * are evaluated once per chunk and their chunk count is handed to each.
  * Counts are exact: a request's results do not depend on what else runs. */
 typedef struct sel_server sel_server;
 

@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t W = (uint64_t)gridDim.x * nw;
-  for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x) acc[p] = 0;
+  for (uint32_t p = threadIdx.x; p < (uint32_t)kBatchMaxProgs; p += blockDim.x) acc[p] = 0;
   __syncthreads();
   const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
   const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
@@ -534,11 +534,18 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
       const uint32_t T = full ? eval_tile<true>(code, nins, tb, lane, nrows)
                               : eval_tile<false>(code, nins, tb, lane, nrows) & inr;
       const uint32_t c = wave_sum(__builtin_popcount(T));
-      if (lane == 0 && c) atomicAdd(&acc[pb + k], c);
+      if (lane == 0 && c) {
+        if (pb + k < (uint32_t)kBatchMaxProgs) {
+          atomicAdd(&acc[pb + k], c);
+        } else {  // beyond the LDS table: straight to the accumulator line
+          atomicAdd(&a.acc[(uint64_t)progs[pb + k].acc_index * kBatchAccStride], (unsigned long long)c);
+        }
+      }
     }
   }
   __syncthreads();
-  for (uint32_t p = threadIdx.x; p < a.nprogs; p += blockDim.x)
+  const uint32_t nlds = a.nprogs < (uint32_t)kBatchMaxProgs ? a.nprogs : (uint32_t)kBatchMaxProgs;
+  for (uint32_t p = threadIdx.x; p < nlds; p += blockDim.x)
     if (acc[p]) atomicAdd(&a.acc[(uint64_t)progs[p].acc_index * kBatchAccStride], (unsigned long long)acc[p]);
   __threadfence();
   __syncthreads();

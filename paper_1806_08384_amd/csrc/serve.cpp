@@ -57,8 +57,13 @@ struct Request {
 struct Active {                             // one attached program
   Request* req;
   uint32_t index;                           // program index in the request
-  uint32_t line;                            // accumulator line
   uint32_t chunks_left;
+};
+
+struct Member {                             // an attached program in a round
+  Active a;
+  uint32_t group;                           // its distinct program's line
+  bool last;                                // this round finishes it
 };
 
 struct TableState {
@@ -75,7 +80,8 @@ struct RoundSlot {                          // per in-flight round
   unsigned long long* h_out = nullptr;      // pinned, finished counts
   hipEvent_t done_ev = nullptr;
   DevSlot* slot = nullptr;                  // ticket of this slot's launches
-  std::vector<Active> finishing;            // programs finished by this round
+  std::vector<Member> members;              // programs this round counts for
+  uint32_t ngroups = 0;                     // distinct programs (lines) in it
   bool busy = false;
 };
 
@@ -86,8 +92,7 @@ struct sel_server {
   sel_server_config cfg{};
   sel_ctx* pd_ctx = nullptr;                // own stream and scratch for push-downs
   hipStream_t stream = nullptr;             // rounds
-  unsigned long long* d_acc = nullptr;      // kMaxLines lines
-  std::vector<uint32_t> free_lines;
+  unsigned long long* d_acc = nullptr;      // kMaxLines lines, one per distinct program of a round
   std::vector<RoundSlot> slots;
   std::deque<uint32_t> inflight;            // slot indices, oldest first
   uint32_t next_slot = 0;
@@ -176,10 +181,8 @@ void admit_locked(sel_server* s) {
         ts.nchunks = std::max<uint64_t>(1, (r->tables[i]->nrows + chunk_rows_of(s) - 1) / chunk_rows_of(s));
         it = s->tables.emplace(r->tables[i], ts).first;
       }
-      const uint32_t line = s->free_lines.back();
-      s->free_lines.pop_back();
       s->lines_used += 1;
-      it->second.progs.push_back(Active{r, i, line, (uint32_t)it->second.nchunks});
+      it->second.progs.push_back(Active{r, i, (uint32_t)it->second.nchunks});
     }
     if (r->has_pd) {
       s->pd_queue.push_back(r);
@@ -189,18 +192,20 @@ void admit_locked(sel_server* s) {
   }
 }
 
-// Host side of a finished round: hand out the counts it finished.
+// Host side of a finished round: add each distinct program's chunk count to
+// every request program attached to it (rounds retire in launch order, so a
+// program's last round retires after all its earlier ones).
 void retire_round(sel_server* s, RoundSlot& rs) {
   std::lock_guard<std::mutex> lk(s->mu);
-  for (size_t k = 0; k < rs.finishing.size(); ++k) {
-    const Active& a = rs.finishing[k];
-    a.req->counts[a.index] = rs.h_out[k];
-    a.req->remaining -= 1;
-    s->free_lines.push_back(a.line);
-    s->lines_used -= 1;
-    if (a.req->remaining == 0 && a.req->pd_done) finish_request_locked(s, a.req);
+  for (const Member& m : rs.members) {
+    m.a.req->counts[m.a.index] += rs.h_out[m.group];
+    if (m.last) {
+      m.a.req->remaining -= 1;
+      s->lines_used -= 1;
+      if (m.a.req->remaining == 0 && m.a.req->pd_done) finish_request_locked(s, m.a.req);
+    }
   }
-  rs.finishing.clear();
+  rs.members.clear();
   rs.busy = false;
 }
 
@@ -217,11 +222,13 @@ bool wait_oldest(sel_server* s) {
 }
 
 // Build and launch one round; returns false if there was nothing to do.
+// Identical programs (the same compiled program on the same table) attached
+// by different requests are evaluated once per chunk; their chunk count is
+// handed to each of them.
 bool launch_round(sel_server* s) {
   RoundSlot& rs = s->slots[s->next_slot];
   std::vector<BatchTable> dt;
   std::vector<BatchProg> dp;
-  std::vector<uint32_t> done;
   uint64_t tile = 0;
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -236,49 +243,47 @@ bool launch_round(sel_server* s) {
       d.tile_begin = tile;
       d.row_begin = row_begin;
       d.prog_begin = (uint32_t)dp.size();
+      std::unordered_map<const sel_program*, uint32_t> group;
       const Request* first = nullptr;
       bool shared = false;
       for (Active& a : ts.progs) {
-        BatchProg p{};
-        p.code = a.req->progs[a.index]->dcode;
-        p.nins = a.req->progs[a.index]->nins;
-        p.acc_index = a.line;
-        dp.push_back(p);
+        const sel_program* p = a.req->progs[a.index];
+        auto g = group.find(p);
+        if (g == group.end()) {
+          BatchProg bp{};
+          bp.code = p->dcode;
+          bp.nins = p->nins;
+          bp.acc_index = (uint32_t)dp.size();
+          g = group.emplace(p, (uint32_t)dp.size()).first;
+          dp.push_back(bp);
+        }
         if (!first) first = a.req;
         else if (a.req != first) shared = true;
         a.chunks_left -= 1;
-        if (a.chunks_left == 0) {
-          done.push_back(a.line);
-          rs.finishing.push_back(a);
-        }
+        rs.members.push_back(Member{a, g->second, a.chunks_left == 0});
       }
       d.prog_count = (uint32_t)dp.size() - d.prog_begin;
       ts.progs.erase(std::remove_if(ts.progs.begin(), ts.progs.end(),
                                     [](const Active& a) { return a.chunks_left == 0; }),
                      ts.progs.end());
       ts.cur = (ts.cur + 1) % ts.nchunks;
-      if (row_end > row_begin) {
-        tile += (row_end - row_begin + kTileRows - 1) / kTileRows;
-        dt.push_back(d);
-      } else {
-        d.tile_begin = tile;
-        dt.push_back(d);   // an empty table: no tiles, its programs still finish
-      }
+      if (row_end > row_begin) tile += (row_end - row_begin + kTileRows - 1) / kTileRows;
+      dt.push_back(d);   // an empty table adds no tile; its programs still finish
       s->shared_rounds += shared ? 1 : 0;
     }
     if (dp.empty()) {
-      rs.finishing.clear();
+      rs.members.clear();
       return false;
     }
+    rs.ngroups = (uint32_t)dp.size();
     s->rounds += 1;
-    s->round_programs += dp.size();
+    s->round_programs += rs.members.size();
   }
   // descriptors: tables | progs | done list, staged through pinned memory
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t o_progs = up(dt.size() * sizeof(BatchTable));
-  const size_t o_done = up(o_progs + dp.size() * sizeof(BatchProg));
-  const size_t o_out = up(o_done + std::max<size_t>(1, done.size()) * 4);
-  const size_t need = o_out + std::max<size_t>(1, done.size()) * 8;
+  const size_t o_out = up(o_progs + dp.size() * sizeof(BatchProg));
+  const size_t need = o_out + dp.size() * 8;
   if (need > rs.dev_bytes) {
     if (rs.dev) (void)hipFree(rs.dev);
     if (rs.host) (void)hipHostFree(rs.host);
@@ -297,7 +302,6 @@ bool launch_round(sel_server* s) {
   }
   std::memcpy(rs.host, dt.data(), dt.size() * sizeof(BatchTable));
   std::memcpy(rs.host + o_progs, dp.data(), dp.size() * sizeof(BatchProg));
-  if (!done.empty()) std::memcpy(rs.host + o_done, done.data(), done.size() * 4);
   BatchArgs a{};
   a.tables = (const BatchTable*)rs.dev;
   a.progs = (const BatchProg*)((char*)rs.dev + o_progs);
@@ -305,8 +309,8 @@ bool launch_round(sel_server* s) {
   a.nprogs = (uint32_t)dp.size();
   a.total_tiles = tile;
   a.acc = s->d_acc;
-  a.done = (const uint32_t*)((char*)rs.dev + o_done);
-  a.ndone = (uint32_t)done.size();
+  a.done = nullptr;                  // every line of the round is read out and reset
+  a.ndone = (uint32_t)dp.size();
   a.out = (unsigned long long*)((char*)rs.dev + o_out);
   a.slot = rs.slot;
   const uint32_t block = 256;
@@ -314,8 +318,7 @@ bool launch_round(sel_server* s) {
       1, std::min<uint64_t>((uint64_t)4 * s->ctx->num_cus, (tile + 3) / 4));
   bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
   ok = ok && sel_launch_batch(a, grid, block, s->stream) == 0;
-  if (!done.empty())
-    ok = ok && hipMemcpyAsync(rs.h_out, a.out, done.size() * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(rs.h_out, a.out, dp.size() * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
   ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
   if (!ok) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -440,7 +443,6 @@ sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_ser
     release_server(s);
     return st;
   }
-  for (uint32_t l = 0; l < kMaxLines; ++l) s->free_lines.push_back(kMaxLines - 1 - l);
   s->worker = std::thread(worker_main, s);
   s->pd_worker = std::thread(pd_worker_main, s);
   *out = s;

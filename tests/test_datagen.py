@@ -44,3 +44,26 @@ def test_seed_changes_stream():
     b = datagen.uniform("i32", 2, 0, 0, 9999, 1000)
     c = datagen.uniform("i32", 1, 1, 0, 9999, 1000)
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_cfg3_programs_shape():
+    progs = datagen.cfg3_programs()
+    assert len(progs) == 64
+    assert [t for t, _ in progs] == [k // 16 for k in range(64)]
+    leaves = [datagen.tree_leaves(tree) for _, tree in progs]
+    assert min(leaves) >= 2 and max(leaves) <= 8
+    # same seed, same programs
+    again = datagen.cfg3_programs()
+    assert repr(again[:5]) == repr(progs[:5])
+
+
+def test_serving_trace_shape():
+    tr = datagen.serving_trace(seed=52, rate=2000.0, duration=2.0)
+    n = len(tr)
+    assert abs(n - 4000) < 5 * np.sqrt(4000)                 # Poisson count
+    assert all(a < b for a, b in zip([t for t, _, _ in tr], [t for t, _, _ in tr][1:]))
+    ks = [len(items) for _, items, _ in tr]
+    assert min(ks) == 1 and max(ks) == 12
+    frac = sum(1 for *_, pd in tr if pd) / n
+    assert abs(frac - 0.1) < 0.03
+    assert all(pd[0] != 4 for *_, pd in tr if pd)             # no push-down on the star table
