@@ -131,8 +131,13 @@ typedef struct sel_program sel_program;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
  * (for instance torch.cuda.current_stream().cuda_stream) on which every call
- * enqueues its work; NULL makes the context create its own stream.
+ * enqueues its work, so the calls are ordered after earlier work on that
+ * stream that produced their inputs.  NULL is the device's null stream (the
+ * handle torch reports for its default stream); SEL_STREAM_OWN makes the
+ * context create a non-blocking stream of its own, and the caller then
+ * synchronises its inputs before each call.
  * Errors: SEL_E_INVALID (bad device / out NULL), SEL_E_DEVICE, SEL_E_NOMEM. */
+#define SEL_STREAM_OWN ((void*)(intptr_t)-1)
 sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out);
 void sel_ctx_destroy(sel_ctx* ctx);
 
@@ -357,8 +362,12 @@ typedef struct sel_server_stats {
 sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_server** out);
 
 /* Queue a request; *ticket names it.  The arrays are copied; tables,
- * programs and pd_out must stay valid until the request completes.
- * Errors: SEL_E_INVALID (bad entries), SEL_E_BUSY (the request alone needs
+ * programs and pd_out must stay valid until the request completes.  The
+ * request's device work runs on the server's streams after whatever was
+ * enqueued on the context's stream before this call (an event recorded at
+ * submission), so inputs produced there need no host synchronisation.
+ * Errors: SEL_E_INVALID (bad entries, or a program with more than 64 leaf
+ * and validity words to batch), SEL_E_BUSY (the request alone needs
  * more than the budget: it is rejected, never queued), SEL_E_DEVICE (a
  * worker failed). */
 sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ticket);

@@ -239,7 +239,7 @@ void release_ctx(sel_ctx* ctx) {
   if (ctx->slot) (void)hipFree(ctx->slot);
   if (ctx->hout) (void)hipHostFree(ctx->hout);
   if (ctx->hstage) (void)hipHostFree(ctx->hstage);
-  if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
 }  // namespace
@@ -260,8 +260,8 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) { where = "hipGetDeviceProperties"; break; }
     ctx->num_cus = (uint32_t)prop.multiProcessorCount;
-    if (hip_stream) {
-      ctx->stream = (hipStream_t)hip_stream;
+    if (hip_stream != SEL_STREAM_OWN) {
+      ctx->stream = (hipStream_t)hip_stream;   // NULL: the null stream
     } else {
       if ((e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking)) != hipSuccess) { where = "hipStreamCreate"; break; }
       ctx->own_stream = true;

@@ -22,11 +22,11 @@ struct Candidate {
   uint32_t block, grid;
 };
 
-std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, bool batch) {
+std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, bool batch, uint32_t batch_slots) {
   std::vector<Candidate> c;
   for (uint32_t block : {64u, 128u, 256u}) {
     int occ = 0;
-    const int e = batch ? sel_batch_occupancy(block, &occ) : sel_scan_occupancy(occ_mode, block, &occ);
+    const int e = batch ? sel_batch_occupancy(block, batch_slots * 256u * (block / kWave), &occ) : sel_scan_occupancy(occ_mode, block, &occ);
     if (e != 0 || occ < 1) occ = 1;
     const int max_waves = occ * (int)(block / kWave);
     for (int waves : {4, 8, 12, 16, 20, 24, 32}) {
@@ -108,7 +108,7 @@ sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program*
   Candidate b{256, 0};
   double ms = 0;
   const uint64_t need_waves = std::max<uint64_t>(1, ntiles);
-  sel_status st = time_candidates(ctx, candidates(ctx, mode, false), reps, [&](const Candidate& c) {
+  sel_status st = time_candidates(ctx, candidates(ctx, mode, false, 0), reps, [&](const Candidate& c) {
     const uint64_t need = (need_waves + c.block / kWave - 1) / (c.block / kWave);
     return sel_launch_scan(mode, a, (uint32_t)std::min<uint64_t>(c.grid, need), c.block, ctx->stream);
   }, b, ms);
@@ -128,19 +128,14 @@ sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* 
   const sel_launch saved = ctx->launch;
   const bool saved_fixed = ctx->launch_fixed;
   std::vector<uint64_t> out(n ? n : 1);
-  uint64_t total_tiles = 0;
-  std::vector<const sel_table*> seen;
-  for (uint32_t i = 0; i < n && tables; ++i) {
-    if (!tables[i]) return set_err(ctx, SEL_E_INVALID, "NULL table");
-    if (std::find(seen.begin(), seen.end(), tables[i]) == seen.end()) {
-      seen.push_back(tables[i]);
-      total_tiles += ntiles_of(tables[i]->nrows);
-    }
-  }
+  BatchPlan bp;
+  sel_status pst = plan_batch(ctx, n, tables, progs, bp);
+  if (pst != SEL_OK) return pst;
+  const uint64_t total_tiles = bp.total_tiles;
   DeviceGuard g(ctx->device);
   Candidate b{256, 0};
   double ms = 0;
-  sel_status st = time_candidates(ctx, candidates(ctx, 0, true), reps, [&](const Candidate& c) {
+  sel_status st = time_candidates(ctx, candidates(ctx, 0, true, bp.max_slots), reps, [&](const Candidate& c) {
     ctx->launch = sel_launch{c.block, c.grid};
     ctx->launch_fixed = true;
     return (int)sel_count_batch(ctx, n, tables, progs, out.data()) == SEL_OK ? 0 : 1;

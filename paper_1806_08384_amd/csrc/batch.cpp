@@ -18,15 +18,11 @@ using namespace selrt;
 struct sel_batch {
   sel_ctx* ctx = nullptr;
   uint32_t n = 0;
-  std::vector<const sel_table*> tables;       // distinct, in first-use order
+  std::vector<const sel_table*> tabs;         // per caller index
   std::vector<const sel_program*> slot_prog;  // per caller index
-  std::vector<uint32_t> slot_to_flat;         // caller index -> BatchProg index
-  std::vector<BatchTable> dt;
-  std::vector<BatchProg> dp;
-  uint64_t total_tiles = 0;
-  void* dev = nullptr;                        // tables | progs | acc | out | slot
-  BatchTable* d_tables = nullptr;
-  BatchProg* d_progs = nullptr;
+  BatchPlan plan;
+  void* dev = nullptr;                        // descriptors | acc | out | slot
+  size_t desc_cap = 0;
   unsigned long long* d_acc = nullptr;
   unsigned long long* d_out = nullptr;
   DevSlot* d_slot = nullptr;
@@ -35,61 +31,53 @@ struct sel_batch {
   hipEvent_t ready = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  uint32_t grid = 0, block = 256;
+  BatchArgs args{};                           // as captured
+  uint32_t grid = 0, block = 256, lds = 0;
 };
 
-namespace {
+namespace selrt {
 
-// Group the (table, program) pairs by table and fill the descriptors.
-sel_status plan(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
-                const sel_program* const* progs, sel_batch& b) {
+// Validate the (table, program) pairs and plan one pass list per distinct
+// table (first-use order); accumulator line i belongs to pair i.
+sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                const sel_program* const* progs, BatchPlan& bp) {
   if (n == 0 || n > (uint32_t)kBatchMaxProgs)
     return set_err(ctx, SEL_E_INVALID, "batch size must be 1..1024");
   if (!tables || !progs) return set_err(ctx, SEL_E_INVALID, "NULL argument");
-  b.n = n;
-  b.slot_prog.assign(progs, progs + n);
+  std::vector<const sel_table*> distinct;
   for (uint32_t i = 0; i < n; ++i) {
     if (!tables[i] || !progs[i]) return set_err(ctx, SEL_E_INVALID, "NULL table or program");
     if (progs[i]->table != tables[i])
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " is bound to another table");
-    if (std::find(b.tables.begin(), b.tables.end(), tables[i]) == b.tables.end())
-      b.tables.push_back(tables[i]);
+    if (batch_slots_alone(progs[i]) > kBatchSlots)
+      return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " has too many leaves to batch");
+    if (std::find(distinct.begin(), distinct.end(), tables[i]) == distinct.end())
+      distinct.push_back(tables[i]);
   }
-  b.slot_to_flat.assign(n, 0);
-  b.dt.clear();
-  b.dp.clear();
-  uint64_t tile = 0;
-  for (const sel_table* t : b.tables) {
-    BatchTable d{};
-    d.nrows = t->nrows;
-    d.tile_begin = tile;
-    d.row_begin = 0;
-    d.prog_begin = (uint32_t)b.dp.size();
+  bp.clear();
+  std::vector<const sel_program*> ps;
+  std::vector<uint32_t> acc;
+  for (const sel_table* t : distinct) {
+    ps.clear();
+    acc.clear();
     for (uint32_t i = 0; i < n; ++i) {
       if (tables[i] != t) continue;
-      b.slot_to_flat[i] = (uint32_t)b.dp.size();
-      BatchProg p{};
-      p.code = progs[i]->dcode;
-      p.nins = progs[i]->nins;
-      p.acc_index = (uint32_t)b.dp.size();
-      b.dp.push_back(p);
+      ps.push_back(progs[i]);
+      acc.push_back(i);
     }
-    d.prog_count = (uint32_t)b.dp.size() - d.prog_begin;
-    tile += ntiles_of(t->nrows);
-    if (ntiles_of(t->nrows) == 0) continue;   // an empty table contributes no tile
-    b.dt.push_back(d);
+    bp.add(t, 0, t->nrows, ps.data(), acc.data(), (uint32_t)ps.size());
   }
-  if (b.dt.empty()) {   // every table empty: keep one zero-row entry
-    BatchTable d{};
-    b.dt.push_back(d);
-  }
-  b.total_tiles = tile;
   return SEL_OK;
 }
 
+}  // namespace selrt
+
+namespace {
+
 // Launch shape of a batch: fixed by the caller, else tuned for this
-// (program count, size) class, else 4 workgroups of 256 per CU.
-void batch_shape(sel_ctx* ctx, uint32_t nprogs, uint64_t total_tiles, uint32_t& grid,
+// (program count, size) class, else as many workgroups of 256 as fit a CU
+// (registers and the plan's LDS slots), at most 16 waves per CU.
+void batch_shape(sel_ctx* ctx, uint32_t nprogs, const BatchPlan& bp, uint32_t& grid,
                  uint32_t& block) {
   block = 256;
   uint64_t g = 0;
@@ -97,7 +85,7 @@ void batch_shape(sel_ctx* ctx, uint32_t nprogs, uint64_t total_tiles, uint32_t& 
     block = ctx->launch.block;
     g = ctx->launch.grid;
   } else {
-    auto it = ctx->tune.find(tune_key(TK_BATCH, batch_class(nprogs), total_tiles));
+    auto it = ctx->tune.find(tune_key(TK_BATCH, batch_class(nprogs), bp.total_tiles));
     if (it != ctx->tune.end()) {
       block = it->second.block;
       g = it->second.grid;
@@ -105,43 +93,32 @@ void batch_shape(sel_ctx* ctx, uint32_t nprogs, uint64_t total_tiles, uint32_t& 
   }
   if (g == 0) {
     int occ = 1;
-    if (sel_batch_occupancy(block, &occ) != 0 || occ < 1) occ = 1;
+    if (sel_batch_occupancy(block, bp.lds_bytes(block), &occ) != 0 || occ < 1) occ = 1;
     g = (uint64_t)std::min(occ, (int)(16 * 64 / block)) * ctx->num_cus;
   }
-  const uint64_t need = std::max<uint64_t>(1, (total_tiles + block / 64 - 1) / (block / 64));
+  const uint64_t need = std::max<uint64_t>(1, (bp.total_tiles + block / 64 - 1) / (block / 64));
   grid = (uint32_t)std::min(g, need);
 }
 
-size_t layout(uint32_t n, size_t ntables, size_t& off_progs, size_t& off_acc, size_t& off_out,
-              size_t& off_slot) {
-  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  off_progs = up(ntables * sizeof(BatchTable));
-  off_acc = up(off_progs + n * sizeof(BatchProg));
-  off_out = up(off_acc + (size_t)n * kBatchAccStride * 8);
-  off_slot = up(off_out + (size_t)n * 8);
-  return off_slot + 256;
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Workspace after the descriptors: accumulator lines, counts, slot.
+size_t tail_bytes(uint32_t n) {
+  return up256((size_t)n * kBatchAccStride * 8) + up256((size_t)n * 8) + 256;
 }
 
-sel_status upload_descriptors(sel_ctx* ctx, sel_batch& b) {
-  std::vector<uint8_t> host((char*)b.d_acc - (char*)b.dev);
-  std::memcpy(host.data(), b.dt.data(), b.dt.size() * sizeof(BatchTable));
-  std::memcpy(host.data() + ((char*)b.d_progs - (char*)b.dev), b.dp.data(), b.dp.size() * sizeof(BatchProg));
-  return stage_copy(ctx, b.dev, host.data(), host.size());
+void place_tail(char* base, size_t desc_cap, uint32_t n, unsigned long long*& acc,
+                unsigned long long*& out, DevSlot*& slot) {
+  acc = (unsigned long long*)(base + desc_cap);
+  out = (unsigned long long*)(base + desc_cap + up256((size_t)n * kBatchAccStride * 8));
+  slot = (DevSlot*)((char*)out + up256((size_t)n * 8));
 }
 
-BatchArgs args_of(const sel_batch& b) {
-  BatchArgs a{};
-  a.tables = b.d_tables;
-  a.progs = b.d_progs;
-  a.ntables = (uint32_t)b.dt.size();
-  a.nprogs = (uint32_t)b.dp.size();
-  a.total_tiles = b.total_tiles;
-  a.acc = b.d_acc;
-  a.done = nullptr;
-  a.ndone = (uint32_t)b.dp.size();
-  a.out = b.d_out;
-  a.slot = b.d_slot;
-  return a;
+// Writes the plan's descriptors to `dev` in stream order and fills `a`.
+sel_status upload_plan(sel_ctx* ctx, const BatchPlan& bp, char* dev, BatchArgs& a) {
+  std::vector<uint8_t> host(bp.bytes());
+  bp.write(host.data(), dev, a);
+  return stage_copy(ctx, dev, host.data(), host.size());
 }
 
 void release(sel_batch* b) {
@@ -154,6 +131,74 @@ void release(sel_batch* b) {
   delete b;
 }
 
+// Captures the persistent kernel, then the copy of the counts to pinned host
+// memory; no memset node (the kernel leaves its accumulators zero).
+sel_status capture(sel_batch* b) {
+  sel_ctx* ctx = b->ctx;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  hipError_t e;
+  const char* where = "";
+  do {
+    if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) { where = "hipStreamBeginCapture"; break; }
+    int le = sel_launch_batch(b->args, b->grid, b->block, b->lds, b->stream);
+    hipError_t ce = hipMemcpyAsync(b->h_out, b->d_out, (size_t)b->n * 8, hipMemcpyDeviceToHost, b->stream);
+    e = hipStreamEndCapture(b->stream, &b->graph);
+    if (le) { e = (hipError_t)le; where = "batch launch (capture)"; break; }
+    if (ce != hipSuccess) { e = ce; where = "hipMemcpyAsync (capture)"; break; }
+    if (e != hipSuccess) { where = "hipStreamEndCapture"; break; }
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) { where = "hipGraphInstantiate"; break; }
+  } while (0);
+  if (e != hipSuccess) return hip_err(ctx, e, where);
+  return SEL_OK;
+}
+
+// Plans, uploads and (re)captures a batch from its current pairs.  The
+// graph is captured again only when the launch arguments change; otherwise
+// rewriting the descriptors in place refreshes it.
+sel_status rebuild(sel_batch* b) {
+  sel_ctx* ctx = b->ctx;
+  sel_status st = plan_batch(ctx, b->n, b->tabs.data(), b->slot_prog.data(), b->plan);
+  if (st != SEL_OK) return st;
+  const size_t need = up256(b->plan.bytes());
+  if (need > b->desc_cap) {
+    if (b->dev) {
+      (void)hipStreamSynchronize(b->stream);
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(b->dev);
+      b->dev = nullptr;
+    }
+    const size_t cap = up256(need * 2);
+    HIP_TRY(ctx, hipMalloc(&b->dev, cap + tail_bytes(b->n)), "hipMalloc(batch)");
+    HIP_TRY(ctx, hipMemsetAsync(b->dev, 0, cap + tail_bytes(b->n), ctx->stream), "hipMemsetAsync(batch)");
+    b->desc_cap = cap;
+    place_tail((char*)b->dev, cap, b->n, b->d_acc, b->d_out, b->d_slot);
+  }
+  BatchArgs a{};
+  st = upload_plan(ctx, b->plan, (char*)b->dev, a);
+  if (st != SEL_OK) return st;
+  a.acc = b->d_acc;
+  a.done = nullptr;
+  a.ndone = b->n;
+  a.out = b->d_out;
+  a.slot = b->d_slot;
+  uint32_t grid, block;
+  batch_shape(ctx, b->n, b->plan, grid, block);
+  const uint32_t lds = b->plan.lds_bytes(block);
+  if (b->exec && std::memcmp(&a, &b->args, sizeof a) == 0 && grid == b->grid && block == b->block &&
+      lds == b->lds)
+    return SEL_OK;
+  b->args = a;
+  b->grid = grid;
+  b->block = block;
+  b->lds = lds;
+  // the capture stream must see the uploads before its first replay
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  return capture(b);
+}
+
 }  // namespace
 
 extern "C" {
@@ -161,14 +206,14 @@ extern "C" {
 sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
                            const sel_program* const* progs, uint64_t* out_counts) {
   if (!ctx || !out_counts) return set_err(ctx, SEL_E_INVALID, "NULL argument");
-  sel_batch b;
-  sel_status st = plan(ctx, n, tables, progs, b);
+  BatchPlan bp;
+  sel_status st = plan_batch(ctx, n, tables, progs, bp);
   if (st != SEL_OK) return st;
   DeviceGuard g(ctx->device);
-  // workspace at the start of the context's batch area: descriptors, then
-  // accumulators (zeroed once when the area is created), then counts
-  size_t op, oa, oo, os;
-  const size_t bytes = layout(n, b.dt.size(), op, oa, oo, os);
+  // workspace in the context's batch area: descriptors, then accumulators,
+  // counts and the slot
+  const size_t desc = up256(bp.bytes());
+  const size_t bytes = desc + tail_bytes(n);
   if (bytes > ctx->batch_bytes) {
     if (ctx->batch_mem) {
       (void)hipStreamSynchronize(ctx->stream);
@@ -176,41 +221,38 @@ sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tab
       ctx->batch_mem = nullptr;
       ctx->batch_bytes = 0;
     }
-    // accumulators sit at a fixed offset for the largest layout: zero all
     const size_t want = std::max(bytes, size_t(1) << 20);
     HIP_TRY(ctx, hipMalloc(&ctx->batch_mem, want), "hipMalloc(batch)");
-    HIP_TRY(ctx, hipMemsetAsync(ctx->batch_mem, 0, want, ctx->stream), "hipMemsetAsync(batch)");
     ctx->batch_bytes = want;
   }
-  b.dev = ctx->batch_mem;
-  b.d_tables = (BatchTable*)b.dev;
-  b.d_progs = (BatchProg*)((char*)b.dev + op);
-  b.d_acc = (unsigned long long*)((char*)b.dev + oa);
-  b.d_out = (unsigned long long*)((char*)b.dev + oo);
-  // the accumulators must be zero: earlier batches left them zero, but a
-  // layout with a different table count moves them, so clear this range
-  int e = sel_launch_fill((uint32_t*)b.d_acc, (size_t)n * kBatchAccStride * 2, 0u, ctx->stream);
+  char* base = (char*)ctx->batch_mem;
+  BatchArgs a{};
+  unsigned long long* acc;
+  unsigned long long* outp;
+  DevSlot* slot;
+  place_tail(base, desc, n, acc, outp, slot);
+  // the accumulators move with the descriptor size: clear this call's lines
+  int e = sel_launch_fill((uint32_t*)acc, (size_t)n * kBatchAccStride * 2, 0u, ctx->stream);
   if (e) return hip_err(ctx, (hipError_t)e, "accumulator clear");
-  st = upload_descriptors(ctx, b);
-  if (st != SEL_OK) {
-    b.dev = nullptr;
-    return st;
-  }
-  BatchArgs a = args_of(b);
+  st = upload_plan(ctx, bp, base, a);
+  if (st != SEL_OK) return st;
+  a.acc = acc;
+  a.done = nullptr;
+  a.ndone = n;
+  a.out = outp;
   a.slot = ctx->slot;
   uint32_t grid, block;
-  batch_shape(ctx, n, b.total_tiles, grid, block);
+  batch_shape(ctx, n, bp, grid, block);
   {
     TimedLaunch tl(ctx, SEL_K_BATCH);
-    e = sel_launch_batch(a, grid, block, ctx->stream);
+    e = sel_launch_batch(a, grid, block, bp.lds_bytes(block), ctx->stream);
     tl.done();
   }
-  b.dev = nullptr;  // borrowed from the context
   if (e) return hip_err(ctx, (hipError_t)e, "batch launch");
   HIP_TRY(ctx, hipMemcpyAsync(ctx->hbatch, a.out, n * 8, hipMemcpyDeviceToHost, ctx->stream),
           "hipMemcpyAsync(batch counts)");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-  for (uint32_t i = 0; i < n; ++i) out_counts[i] = ctx->hbatch[b.slot_to_flat[i]];
+  for (uint32_t i = 0; i < n; ++i) out_counts[i] = ctx->hbatch[i];
   return SEL_OK;
 }
 
@@ -218,59 +260,33 @@ sel_status sel_batch_create(sel_ctx* ctx, uint32_t n, const sel_table* const* ta
                             const sel_program* const* progs, sel_batch** out) {
   if (!ctx || !out) return set_err(ctx, SEL_E_INVALID, "NULL argument");
   *out = nullptr;
+  {
+    BatchPlan probe;   // validate before allocating anything
+    sel_status st = plan_batch(ctx, n, tables, progs, probe);
+    if (st != SEL_OK) return st;
+  }
   sel_batch* b = new (std::nothrow) sel_batch();
   if (!b) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
   b->ctx = ctx;
-  sel_status st = plan(ctx, n, tables, progs, *b);
-  if (st != SEL_OK) {
-    delete b;
-    return st;
-  }
+  b->n = n;
+  b->tabs.assign(tables, tables + n);
+  b->slot_prog.assign(progs, progs + n);
   DeviceGuard g(ctx->device);
-  size_t op, oa, oo, os;
-  const size_t bytes = layout(n, b->dt.size(), op, oa, oo, os);
   hipError_t e;
   const char* where = "";
   do {
-    if ((e = hipMalloc(&b->dev, bytes)) != hipSuccess) { where = "hipMalloc(batch)"; break; }
-    if ((e = hipMemset(b->dev, 0, bytes)) != hipSuccess) { where = "hipMemset(batch)"; break; }
     if ((e = hipHostMalloc((void**)&b->h_out, (size_t)n * 8, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
     if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) { where = "hipStreamCreate"; break; }
     if ((e = hipEventCreateWithFlags(&b->ready, hipEventDisableTiming)) != hipSuccess) { where = "hipEventCreate"; break; }
   } while (0);
   if (e != hipSuccess) {
-    st = hip_err(ctx, e, where);
+    sel_status st = hip_err(ctx, e, where);
     release(b);
     return st;
   }
-  b->d_tables = (BatchTable*)b->dev;
-  b->d_progs = (BatchProg*)((char*)b->dev + op);
-  b->d_acc = (unsigned long long*)((char*)b->dev + oa);
-  b->d_out = (unsigned long long*)((char*)b->dev + oo);
-  b->d_slot = (DevSlot*)((char*)b->dev + os);
-  st = upload_descriptors(ctx, *b);
-  if (st == SEL_OK && hipStreamSynchronize(ctx->stream) != hipSuccess)
-    st = set_err(ctx, SEL_E_DEVICE, "hipStreamSynchronize");
+  sel_status st = rebuild(b);
   if (st != SEL_OK) {
-    release(b);
-    return st;
-  }
-  // capture: the persistent kernel, then the copy of the counts to pinned
-  // host memory; no memset node (the kernel leaves its accumulators zero)
-  batch_shape(ctx, n, b->total_tiles, b->grid, b->block);
-  const BatchArgs a = args_of(*b);
-  do {
-    if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) { where = "hipStreamBeginCapture"; break; }
-    int le = sel_launch_batch(a, b->grid, b->block, b->stream);
-    hipError_t ce = hipMemcpyAsync(b->h_out, b->d_out, (size_t)b->dp.size() * 8, hipMemcpyDeviceToHost, b->stream);
-    e = hipStreamEndCapture(b->stream, &b->graph);
-    if (le) { e = (hipError_t)le; where = "batch launch (capture)"; break; }
-    if (ce != hipSuccess) { e = ce; where = "hipMemcpyAsync (capture)"; break; }
-    if (e != hipSuccess) { where = "hipStreamEndCapture"; break; }
-    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) { where = "hipGraphInstantiate"; break; }
-  } while (0);
-  if (e != hipSuccess) {
-    st = hip_err(ctx, e, where);
+    (void)hipStreamSynchronize(ctx->stream);
     release(b);
     return st;
   }
@@ -282,17 +298,13 @@ sel_status sel_batch_set_program(sel_batch* b, uint32_t i, const sel_program* pr
   if (!b) return SEL_E_INVALID;
   sel_ctx* ctx = b->ctx;
   if (!prog || i >= b->n) return set_err(ctx, SEL_E_INVALID, "bad index or NULL program");
-  if (prog->table != b->slot_prog[i]->table)
+  if (prog->table != b->tabs[i])
     return set_err(ctx, SEL_E_INVALID, "program is bound to a different table than the one it replaces");
   DeviceGuard g(ctx->device);
+  // a replay still in flight reads the descriptors being replaced
+  HIP_TRY(ctx, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
   b->slot_prog[i] = prog;
-  BatchProg& p = b->dp[b->slot_to_flat[i]];
-  p.code = prog->dcode;
-  p.nins = prog->nins;
-  // the descriptor is device memory the captured kernel reads through a
-  // pointer: rewriting it in stream order refreshes the graph without a
-  // new capture
-  return upload_descriptors(ctx, *b);
+  return rebuild(b);
 }
 
 sel_status sel_batch_run(sel_batch* b, uint64_t* out_counts) {
@@ -315,7 +327,7 @@ sel_status sel_batch_run(sel_batch* b, uint64_t* out_counts) {
     ctx->pending.push_back({SEL_K_BATCH, ev});
   }
   HIP_TRY(ctx, hipStreamSynchronize(b->stream), "hipStreamSynchronize");
-  for (uint32_t i = 0; i < b->n; ++i) out_counts[i] = b->h_out[b->slot_to_flat[i]];
+  for (uint32_t i = 0; i < b->n; ++i) out_counts[i] = b->h_out[i];
   return SEL_OK;
 }
 

@@ -1,0 +1,221 @@
+// batchplan.cpp -- descriptors of a leaf-major batched launch.
+//
+// Algorithm 1 asks for one exact count per candidate relation; a query's
+// candidates are predicates over the same few tables, so their leaf tests
+// overlap in the columns they read.  The plan regroups the leaves of all
+// programs of a table by column: k_batch then reads each column once per
+// pass and tile, tests every leaf on it from registers, and runs each
+// program's combinators over the resulting truth words held in LDS slots.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "runtime.h"
+
+using namespace sel;
+
+namespace selrt {
+
+namespace {
+
+// Leaves that test the same column with the same operation share one slot.
+using LeafKey = std::tuple<uint32_t, const void*, int64_t, uint64_t, const void*, uint32_t>;
+
+LeafKey key_of(const DevInstr& I) { return LeafKey{I.op, I.data, I.lo, I.span, I.aux, I.n}; }
+
+bool is_value_test(uint32_t op) { return op == D_RANGE || op == D_BITMAP || op == D_INLIST; }
+bool is_null_test(uint32_t op) { return op >= D_NN_TRUE && op <= D_NOTNULL; }
+
+struct PassCol {
+  const void* data = nullptr;
+  const uint32_t* valid = nullptr;
+  uint32_t type = 0;
+  uint32_t vslot = kNoSlot;
+  std::vector<DevInstr> leaves;
+};
+
+// One pass under construction.
+struct Pass {
+  std::vector<PassCol> cols;
+  std::map<LeafKey, uint32_t> leaf_slot;
+  std::map<const uint32_t*, uint32_t> valid_slot;
+  std::vector<std::pair<std::vector<uint32_t>, uint32_t>> progs;  // (ops, acc line)
+  uint32_t slots = 0;
+
+  // slots a program would add to this pass
+  uint32_t new_slots(const sel_program* p) const {
+    std::vector<LeafKey> nl;
+    std::vector<const uint32_t*> nv;
+    for (const DevInstr& I : p->host_code) {
+      if (is_value_test(I.op)) {
+        const LeafKey k = key_of(I);
+        if (!leaf_slot.count(k) && std::find(nl.begin(), nl.end(), k) == nl.end()) nl.push_back(k);
+      }
+      if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid && !valid_slot.count(I.valid) &&
+          std::find(nv.begin(), nv.end(), I.valid) == nv.end())
+        nv.push_back(I.valid);
+    }
+    return (uint32_t)(nl.size() + nv.size());
+  }
+  uint32_t vslot_of(const DevInstr& I) {
+    if (!I.valid) return kNoSlot;
+    auto it = valid_slot.find(I.valid);
+    if (it != valid_slot.end()) return it->second;
+    const uint32_t s = slots++;
+    valid_slot[I.valid] = s;
+    // the validity word is loaded with the column holding it (a column that
+    // only null tests read joins the list with no leaves)
+    PassCol* home = nullptr;
+    for (PassCol& c : cols)
+      if (c.valid == I.valid || (c.data == I.data && c.data != nullptr)) { home = &c; break; }
+    if (!home) {
+      cols.push_back(PassCol{});
+      home = &cols.back();
+      home->data = I.data;
+      home->type = I.type;
+    }
+    home->valid = I.valid;
+    home->vslot = s;
+    return s;
+  }
+  void add(const sel_program* p, uint32_t acc) {
+    std::vector<uint32_t> ops;
+    ops.reserve(p->host_code.size());
+    for (const DevInstr& I : p->host_code) {
+      const uint32_t op = I.op;
+      if (is_value_test(op)) {
+        const LeafKey k = key_of(I);
+        auto it = leaf_slot.find(k);
+        uint32_t s;
+        if (it != leaf_slot.end()) {
+          s = it->second;
+        } else {
+          s = slots++;
+          leaf_slot[k] = s;
+          PassCol* home = nullptr;
+          for (PassCol& c : cols)
+            if (c.data == I.data) { home = &c; break; }
+          if (!home) {
+            cols.push_back(PassCol{});
+            home = &cols.back();
+            home->data = I.data;
+            home->type = I.type;
+          }
+          DevInstr L = I;
+          L.flags = 0;
+          L.slot = s;
+          home->leaves.push_back(L);
+        }
+        ops.push_back(batch_op(D_RANGE, s, vslot_of(I)));
+      } else if (is_null_test(op)) {
+        ops.push_back(batch_op(op, 0, vslot_of(I)));
+      } else {
+        ops.push_back(batch_op(op, 0, 0));
+      }
+    }
+    progs.emplace_back(std::move(ops), acc);
+  }
+};
+
+}  // namespace
+
+uint32_t batch_slots_alone(const sel_program* p) { return Pass{}.new_slots(p); }
+
+void BatchPlan::clear() {
+  entries.clear();
+  cols.clear();
+  leaves.clear();
+  progs.clear();
+  ops.clear();
+  total_tiles = 0;
+  max_slots = 0;
+}
+
+void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
+                    const sel_program* const* prg, const uint32_t* acc, uint32_t n) {
+  if (row_end <= row_begin || n == 0) return;
+  const uint64_t tiles = (row_end - row_begin + kTileRows - 1) / kTileRows;
+  auto flush = [&](Pass& ps) {
+    if (ps.progs.empty()) return;
+    BatchTable e{};
+    e.nrows = t->nrows;
+    e.tile_begin = total_tiles;
+    e.row_begin = row_begin;
+    e.prog_begin = (uint32_t)progs.size();
+    e.prog_count = (uint32_t)ps.progs.size();
+    e.col_begin = (uint32_t)cols.size();
+    e.col_count = (uint32_t)ps.cols.size();
+    for (PassCol& c : ps.cols) {
+      BatchCol bc{};
+      bc.data = c.data;
+      bc.valid = c.valid;
+      bc.type = c.type;
+      bc.vslot = c.vslot;
+      bc.leaf_begin = (uint32_t)leaves.size();
+      bc.leaf_count = (uint32_t)c.leaves.size();
+      leaves.insert(leaves.end(), c.leaves.begin(), c.leaves.end());
+      cols.push_back(bc);
+    }
+    for (auto& pr : ps.progs) {
+      BatchProg bp{};
+      bp.ops = (const uint32_t*)(uintptr_t)ops.size();
+      bp.nops = (uint32_t)pr.first.size();
+      bp.acc_index = pr.second;
+      ops.insert(ops.end(), pr.first.begin(), pr.first.end());
+      progs.push_back(bp);
+    }
+    entries.push_back(e);
+    max_slots = std::max(max_slots, ps.slots);
+    total_tiles += tiles;
+  };
+  Pass ps;
+  for (uint32_t i = 0; i < n; ++i) {
+    // callers admit only programs that fit a pass of their own
+    if (!ps.progs.empty() && ps.slots + ps.new_slots(prg[i]) > kBatchSlots) {
+      flush(ps);
+      ps = Pass{};
+    }
+    ps.add(prg[i], acc[i]);
+  }
+  flush(ps);
+}
+
+namespace {
+size_t up(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
+size_t BatchPlan::bytes() const {
+  size_t o = up(entries.size() * sizeof(BatchTable));
+  o = up(o + cols.size() * sizeof(BatchCol));
+  o = up(o + leaves.size() * sizeof(DevInstr));
+  o = up(o + progs.size() * sizeof(BatchProg));
+  return up(o + ops.size() * sizeof(uint32_t));
+}
+
+void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
+  const size_t o_cols = up(entries.size() * sizeof(BatchTable));
+  const size_t o_leaves = up(o_cols + cols.size() * sizeof(BatchCol));
+  const size_t o_progs = up(o_leaves + leaves.size() * sizeof(DevInstr));
+  const size_t o_ops = up(o_progs + progs.size() * sizeof(BatchProg));
+  std::memset(host, 0, bytes());
+  if (!entries.empty()) std::memcpy(host, entries.data(), entries.size() * sizeof(BatchTable));
+  if (!cols.empty()) std::memcpy(host + o_cols, cols.data(), cols.size() * sizeof(BatchCol));
+  if (!leaves.empty()) std::memcpy(host + o_leaves, leaves.data(), leaves.size() * sizeof(DevInstr));
+  BatchProg* hp = (BatchProg*)(host + o_progs);
+  for (size_t k = 0; k < progs.size(); ++k) {
+    hp[k] = progs[k];
+    hp[k].ops = (const uint32_t*)(dev + o_ops + sizeof(uint32_t) * (uintptr_t)progs[k].ops);
+  }
+  if (!ops.empty()) std::memcpy(host + o_ops, ops.data(), ops.size() * sizeof(uint32_t));
+  a.tables = (const BatchTable*)dev;
+  a.cols = (const BatchCol*)(dev + o_cols);
+  a.leaves = (const DevInstr*)(dev + o_leaves);
+  a.progs = (const BatchProg*)(dev + o_progs);
+  a.ntables = (uint32_t)entries.size();
+  a.nprogs = (uint32_t)progs.size();
+  a.total_tiles = total_tiles;
+  a.slot_words = max_slots * (uint32_t)kWave;
+}
+
+}  // namespace selrt

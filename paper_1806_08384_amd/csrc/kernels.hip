@@ -500,45 +500,199 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
   }
 }
 
-// Batched count.  Per workgroup, per-program counts accumulate in LDS; at
-// the end each workgroup adds them to per-program accumulator lines (128
-// bytes each, so atomics on different programs do not contend), and the last
-// workgroup by ticket moves the finished lines out and zeroes them.  Entries
-// may be chunks of tables (row_begin), and lines not finished by this launch
-// keep accumulating: a cooperative scan adds one chunk per launch.
+// --------------------------------------------------------- batched count --
+// Value tests of one leaf over values already in registers (a full tile):
+// bits [b0, b0 + nb) of the lane's word, highest first.  No guard: batched
+// evaluation tests every row (a guard only saves lookups).
+template <int TY>
+__device__ __forceinline__ uint32_t raw_leaf(const Raw<TY>& r, uint32_t op, CInstr I, int h) {
+  constexpr int nb = TY == T_I64 ? 16 : 32;
+  const int64_t lo = I->lo;
+  const uint64_t span = I->span;
+  uint32_t P = 0;
+  if (op == D_RANGE) {
+    if constexpr (TY == T_I64) {
+#pragma unroll
+      for (int b = nb - 1; b >= 0; --b)
+        P = (P << 1) + (uint32_t)((uint64_t)get<TY>(r, b) - (uint64_t)lo <= span);
+    } else {
+      const uint32_t lo32 = (uint32_t)lo, span32 = (uint32_t)span;
+#pragma unroll
+      for (int b = nb - 1; b >= 0; --b)
+        P = (P << 1) + (uint32_t)((uint32_t)get<TY>(r, b) - lo32 <= span32);
+    }
+  } else {  // D_BITMAP
+    const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
+#pragma unroll
+    for (int b = nb - 1; b >= 0; --b) {
+      uint64_t d;
+      if constexpr (TY == T_I64) d = (uint64_t)get<TY>(r, b) - (uint64_t)lo;
+      else d = (uint64_t)((int64_t)get<TY>(r, b) - lo);
+      const bool ok = d < span;
+      const uint32_t k = ok ? (uint32_t)d : 0u;
+      P = (P << 1) + (ok & ((bits[k >> 5] >> (k & 31)) & 1u));
+    }
+  }
+  (void)h;
+  return P;
+}
+
+// All leaf tests of one column on one tile; each truth word goes to the
+// wave's LDS slot named by the leaf.
+template <int TY, bool FULL>
+__device__ __forceinline__ void column_leaves(const CONSTANT BatchCol* C, CInstr leaves,
+                                              uint64_t tb, uint32_t lane, uint64_t nrows,
+                                              uint32_t* wl) {
+  const void* data = C->data;
+  const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
+  if constexpr (!FULL) {
+    for (uint32_t k = 0; k < ln; ++k) {
+      CInstr I = leaves + lb + k;
+      wl[I->slot * kWave + lane] = leaf_pred<TY, false>(I->op, I, tb, lane, nrows, ~0u);
+    }
+  } else if constexpr (TY == T_I64) {
+#pragma unroll
+    for (int h = 1; h >= 0; --h) {
+      Raw<TY> r;
+      load_half64(r, data, tb, lane, h);
+      for (uint32_t k = 0; k < ln; ++k) {
+        CInstr I = leaves + lb + k;
+        const uint32_t op = I->op;
+        uint32_t* w = wl + I->slot * kWave + lane;
+        if (op == D_INLIST) {
+          if (h == 0) *w = leaf_pred<TY, false>(op, I, tb, lane, nrows, ~0u);
+          continue;
+        }
+        const uint32_t P = raw_leaf<TY>(r, op, I, h);
+        if (h == 1) *w = P;
+        else *w = (*w << 16) | P;
+      }
+    }
+  } else {
+    Raw<TY> r;
+    load_full<TY>(r, data, tb, lane);
+    for (uint32_t k = 0; k < ln; ++k) {
+      CInstr I = leaves + lb + k;
+      const uint32_t op = I->op;
+      wl[I->slot * kWave + lane] = op == D_INLIST ? leaf_pred<TY, false>(op, I, tb, lane, nrows, ~0u)
+                                                  : raw_leaf<TY>(r, op, I, 0);
+    }
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void entry_leaves(const CONSTANT BatchTable* E, const CONSTANT BatchCol* cols,
+                                             CInstr leaves, uint64_t tb, uint32_t lane,
+                                             uint64_t nrows, uint32_t* wl) {
+  const uint32_t cb = E->col_begin, cn = E->col_count;
+  for (uint32_t c = 0; c < cn; ++c) {
+    const CONSTANT BatchCol* C = cols + cb + c;
+    if (C->leaf_count) {
+      switch (C->type) {
+        case T_I8: column_leaves<T_I8, FULL>(C, leaves, tb, lane, nrows, wl); break;
+        case T_I16: column_leaves<T_I16, FULL>(C, leaves, tb, lane, nrows, wl); break;
+        case T_I32: column_leaves<T_I32, FULL>(C, leaves, tb, lane, nrows, wl); break;
+        default: column_leaves<T_I64, FULL>(C, leaves, tb, lane, nrows, wl); break;
+      }
+    }
+    const uint32_t vs = C->vslot;
+    if (vs != kNoSlot) wl[vs * kWave + lane] = valid_bits<FULL>(C->valid, tb, lane, nrows);
+  }
+}
+
+// TRUE bits of the lane's rows for one batched program: its postfix
+// combinators over the leaf and validity words in the wave's slots.
+__device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32_t nops,
+                                            const uint32_t* wl, uint32_t lane) {
+  uint32_t st[kMaxDepth], sf[kMaxDepth];
+  uint32_t tt = 0, tf = 0;
+  int d = 0;
+  for (uint32_t pc = 0; pc < nops; ++pc) {
+    const uint32_t w = ops[pc];
+    const uint32_t op = w & 0xFFu;
+    if (op < D_AND || op == D_TRUE || op == D_FALSE) {
+      uint32_t t, f;
+      const uint32_t vs = w >> 20;
+      const uint32_t V = (vs == kNoSlot || op >= D_TRUE) ? ~0u : wl[vs * kWave + lane];
+      switch (op) {
+        case D_RANGE: {
+          const uint32_t P = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+          t = P & V; f = ~P & V;
+          break;
+        }
+        case D_NN_TRUE: t = V; f = 0; break;
+        case D_NN_FALSE: t = 0; f = V; break;
+        case D_ISNULL: t = ~V; f = V; break;
+        case D_NOTNULL: t = V; f = ~V; break;
+        case D_TRUE: t = ~0u; f = 0; break;
+        default: t = 0; f = ~0u; break;  // D_FALSE
+      }
+      spill(st, sf, d - 1, tt, tf);
+      tt = t; tf = f;
+      ++d;
+    } else if (op == D_NOT) {
+      const uint32_t x = tt; tt = tf; tf = x;
+    } else if (op == D_ISUNK) {
+      const uint32_t k = tt | tf; tt = ~k; tf = k;
+    } else {
+      uint32_t at, af;
+      fill(st, sf, d - 2, at, af);
+      if (op == D_AND) { tt &= at; tf |= af; }
+      else { tt |= at; tf &= af; }
+      --d;
+    }
+  }
+  return tt;
+}
+
+// Per workgroup, per-program counts accumulate in LDS; at the end each
+// workgroup adds them to per-program accumulator lines (128 bytes each, so
+// atomics on different programs do not contend), and the last workgroup by
+// ticket moves the finished lines out and zeroes them.  Entries may be
+// chunks of tables (row_begin), and lines not finished by this launch keep
+// accumulating: a cooperative scan adds one chunk per launch.
 __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   __shared__ uint32_t acc[kBatchMaxProgs];
+  extern __shared__ uint32_t slots[];
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t W = (uint64_t)gridDim.x * nw;
+  uint32_t* wl = slots + (threadIdx.x >> 6) * a.slot_words;
   for (uint32_t p = threadIdx.x; p < (uint32_t)kBatchMaxProgs; p += blockDim.x) acc[p] = 0;
   __syncthreads();
   const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
+  const CONSTANT BatchCol* cols = (const CONSTANT BatchCol*)a.cols;
+  CInstr leaves = (CInstr)a.leaves;
   const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
   for (uint64_t flat = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); flat < a.total_tiles;
        flat += W) {
-    // table holding this tile: last t with tile_begin <= flat (uniform search)
+    // entry holding this tile: last e with tile_begin <= flat (uniform search)
     uint32_t lo = 0, hi = a.ntables;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (tables[mid].tile_begin <= flat) lo = mid; else hi = mid;
     }
-    const uint64_t nrows = tables[lo].nrows;
-    const uint64_t tb = tables[lo].row_begin + (flat - tables[lo].tile_begin) * kTileRows;
-    const uint32_t pb = tables[lo].prog_begin, pn = tables[lo].prog_count;
+    const CONSTANT BatchTable* E = tables + lo;
+    const uint64_t nrows = E->nrows;
+    const uint64_t tb = E->row_begin + (flat - E->tile_begin) * kTileRows;
+    const uint32_t pb = E->prog_begin, pn = E->prog_count;
     const bool full = tb + kTileRows <= nrows;
-    const uint32_t inr = full ? ~0u : inrange_bits(tb, lane, nrows);
+    uint32_t inr = ~0u;
+    if (full) {
+      entry_leaves<true>(E, cols, leaves, tb, lane, nrows, wl);
+    } else {
+      entry_leaves<false>(E, cols, leaves, tb, lane, nrows, wl);
+      inr = inrange_bits(tb, lane, nrows);
+    }
     for (uint32_t k = 0; k < pn; ++k) {
-      const CInstr code = (CInstr)progs[pb + k].code;
-      const uint32_t nins = progs[pb + k].nins;
-      const uint32_t T = full ? eval_tile<true>(code, nins, tb, lane, nrows)
-                              : eval_tile<false>(code, nins, tb, lane, nrows) & inr;
+      const CONSTANT BatchProg* P = progs + pb + k;
+      const uint32_t T = run_ops((const CONSTANT uint32_t*)P->ops, P->nops, wl, lane) & inr;
       const uint32_t c = wave_sum(__builtin_popcount(T));
       if (lane == 0 && c) {
         if (pb + k < (uint32_t)kBatchMaxProgs) {
           atomicAdd(&acc[pb + k], c);
         } else {  // beyond the LDS table: straight to the accumulator line
-          atomicAdd(&a.acc[(uint64_t)progs[pb + k].acc_index * kBatchAccStride], (unsigned long long)c);
+          atomicAdd(&a.acc[(uint64_t)P->acc_index * kBatchAccStride], (unsigned long long)c);
         }
       }
     }
@@ -619,11 +773,12 @@ int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu) {
   return (int)e;
 }
 
-int sel_launch_batch(const BatchArgs& a, uint32_t grid, uint32_t block, void* stream) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+int sel_launch_batch(const BatchArgs& a, uint32_t grid, uint32_t block, uint32_t lds_bytes,
+                     void* stream) {
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), lds_bytes, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 
-int sel_batch_occupancy(uint32_t block, int* blocks_per_cu) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, block, 0);
+int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, block, lds_bytes);
 }

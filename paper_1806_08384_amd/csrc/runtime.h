@@ -173,6 +173,36 @@ void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t&
                 uint32_t& block);
 sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int kind);
 
+// Descriptors of one leaf-major batched launch (k_batch).  add() appends
+// passes over rows [row_begin, row_end) of a table for a list of programs;
+// a pass holds as many programs as fit kBatchSlots LDS slots (deduplicated
+// leaf words plus validity words), so each pass reads its columns once.
+struct BatchPlan {
+  std::vector<sel::BatchTable> entries;
+  std::vector<sel::BatchCol> cols;
+  std::vector<DevInstr> leaves;
+  std::vector<sel::BatchProg> progs;   // ops holds an index into `ops` until written
+  std::vector<uint32_t> ops;
+  uint64_t total_tiles = 0;
+  uint32_t max_slots = 0;
+  void clear();
+  // acc[k]: accumulator line of progs[k].  Programs of an empty range add
+  // nothing (their lines stay zero).
+  void add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
+           const sel_program* const* progs, const uint32_t* acc, uint32_t n);
+  size_t bytes() const;
+  // Image of the descriptors for device address `dev` into `host` (bytes()
+  // long); sets the descriptor pointers and counts of `a`.
+  void write(uint8_t* host, char* dev, sel::BatchArgs& a) const;
+  uint32_t lds_bytes(uint32_t block) const { return max_slots * 256u * (block / 64); }
+};
+
+// LDS slots a program needs in a pass of its own (distinct leaves plus
+// validity words); batching requires at most kBatchSlots.
+uint32_t batch_slots_alone(const sel_program* p);
+sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
+                      const sel_program* const* progs, BatchPlan& bp);
+
 // Brackets one kernel launch with events when timing is on.
 struct TimedLaunch {
   sel_ctx* ctx;

@@ -55,7 +55,8 @@ struct DevInstr {          // 64 bytes, read with scalar loads
   int64_t lo;              // D_RANGE lower bound / D_BITMAP base
   uint64_t span;           // D_RANGE: hi - lo (unsigned) / D_BITMAP: nbits
   const void* aux;         // D_BITMAP words / D_INLIST values
-  uint64_t pad;
+  uint32_t slot;           // batched evaluation: LDS slot of the leaf's word
+  uint32_t reserved;
 };
 static_assert(sizeof(DevInstr) == 64, "DevInstr layout");
 
@@ -98,21 +99,49 @@ struct CompactArgs {
   uint64_t cap;
 };
 
-// Batched count (many programs over several tables in one launch).  Tiles
-// of all tables form one flat index space; a wave takes a tile and runs every
-// program bound to that tile's table on it, so programs sharing a table read
-// its columns from HBM once and from cache afterwards.
-struct BatchTable {            // 32 bytes: one table, or one chunk of a table
+// Batched count (many programs over several tables in one launch),
+// evaluated leaf-major.  Tiles of all entries form one flat index space.  For
+// its tile a wave loads each column the entry's programs read once, runs
+// every leaf test on that column while the values sit in registers, and
+// parks each leaf's truth word (and each nullable column's validity word) in
+// an LDS slot of its own; then each program's combinators run over the
+// slots.  A column is thus read from HBM once per entry, however many
+// programs and leaves use it.
+constexpr uint32_t kBatchSlots = 64;      // LDS slots per wave (256 B each)
+constexpr uint32_t kNoSlot = 0xFFFu;
+
+// Combinator op of a batched program: op | p_slot << 8 | v_slot << 20.
+//   D_RANGE    leaf with predicate word in p_slot (any value test)
+//   D_NN_TRUE .. D_NOTNULL   null tests on the validity word in v_slot
+//   D_TRUE, D_FALSE, D_AND, D_OR, D_NOT, D_ISUNK as in programs
+// v_slot == kNoSlot: the column has no NULLs (validity all ones).
+inline constexpr uint32_t batch_op(uint32_t op, uint32_t p, uint32_t v) {
+  return op | (p << 8) | (v << 20);
+}
+
+struct BatchTable {            // 48 bytes: one pass over a table or a chunk
   uint64_t nrows;              // rows of the whole table
   uint64_t tile_begin;         // first flat tile index of this entry
+  uint64_t row_begin;          // first row of the entry (a multiple of kTileRows)
   uint32_t prog_begin;         // into the BatchProg array
   uint32_t prog_count;
-  uint64_t row_begin;          // first row of the entry (a multiple of kTileRows)
+  uint32_t col_begin;          // into the BatchCol array
+  uint32_t col_count;
+  uint32_t pad[2];
+};
+
+struct BatchCol {              // 32 bytes: a column one entry reads
+  const void* data;
+  const uint32_t* valid;       // nullptr: no NULLs
+  uint32_t type;               // DevType
+  uint32_t vslot;              // slot of the validity word, or kNoSlot
+  uint32_t leaf_begin;         // its leaf tests: DevInstr array, slot field set
+  uint32_t leaf_count;
 };
 
 struct BatchProg {             // 16 bytes
-  const DevInstr* code;
-  uint32_t nins;
+  const uint32_t* ops;         // batch_op words, postfix
+  uint32_t nops;
   uint32_t acc_index;          // accumulator line this program adds into
 };
 
@@ -121,6 +150,8 @@ constexpr int kBatchAccStride = 16;   // u64 per accumulator: one 128-byte line 
 
 struct BatchArgs {
   const BatchTable* tables;
+  const BatchCol* cols;
+  const DevInstr* leaves;
   const BatchProg* progs;
   uint32_t ntables;
   uint32_t nprogs;
@@ -131,7 +162,7 @@ struct BatchArgs {
   // Lines not listed keep accumulating across launches.
   const uint32_t* done;
   uint32_t ndone;
-  uint32_t pad;
+  uint32_t slot_words;         // LDS words per wave: slots * 64
   unsigned long long* out;
   DevSlot* slot;
 };
@@ -146,6 +177,7 @@ int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* c
 int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
 int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);
-int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, void* stream);
-int sel_batch_occupancy(uint32_t block, int* blocks_per_cu);
+int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, uint32_t lds_bytes,
+                     void* stream);
+int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 }

@@ -52,6 +52,7 @@ struct Request {
   sel_status pd_status = SEL_OK;
   uint64_t footprint = 0;
   bool done = false;
+  hipEvent_t ready = nullptr;               // the caller's stream at submission
 };
 
 struct Active {                             // one attached program
@@ -74,9 +75,10 @@ struct TableState {
 };
 
 struct RoundSlot {                          // per in-flight round
-  void* dev = nullptr;                      // descriptors | done list | out
+  void* dev = nullptr;                      // descriptors | out
   size_t dev_bytes = 0;
-  char* host = nullptr;                     // pinned staging for descriptors
+  uint8_t* host = nullptr;                  // pinned staging for descriptors
+  selrt::BatchPlan plan;                    // this round's descriptors
   unsigned long long* h_out = nullptr;      // pinned, finished counts
   hipEvent_t done_ev = nullptr;
   DevSlot* slot = nullptr;                  // ticket of this slot's launches
@@ -101,6 +103,8 @@ struct sel_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> incoming;            // submitted, not admitted (FIFO)
   std::deque<Request*> pd_queue;            // admitted push-downs
+  std::vector<hipEvent_t> round_waits;      // ready events of newly admitted requests
+  std::vector<hipEvent_t> free_events;
   std::unordered_map<uint64_t, Request*> by_ticket;
   std::map<const sel_table*, TableState> tables;
   uint64_t next_ticket = 1;
@@ -145,6 +149,9 @@ void set_error_locked(sel_server* s, const std::string& msg) {
 }
 
 void finish_request_locked(sel_server* s, Request* r) {
+  // every wait on the ready event is enqueued by now: recycle it
+  if (r->ready) s->free_events.push_back(r->ready);
+  r->ready = nullptr;
   r->done = true;
   r->t_done = Clock::now();
   s->in_use -= r->footprint;
@@ -184,6 +191,8 @@ void admit_locked(sel_server* s) {
       s->lines_used += 1;
       it->second.progs.push_back(Active{r, i, (uint32_t)it->second.nchunks});
     }
+    // the rounds that scan for it start after the caller's earlier work
+    if (!r->progs.empty()) s->round_waits.push_back(r->ready);
     if (r->has_pd) {
       s->pd_queue.push_back(r);
       s->cv_work.notify_all();   // wake the push-down worker
@@ -227,63 +236,61 @@ bool wait_oldest(sel_server* s) {
 // handed to each of them.
 bool launch_round(sel_server* s) {
   RoundSlot& rs = s->slots[s->next_slot];
-  std::vector<BatchTable> dt;
-  std::vector<BatchProg> dp;
-  uint64_t tile = 0;
+  BatchPlan& bp = rs.plan;
+  bp.clear();
+  uint32_t ngroups = 0;
+  std::vector<hipEvent_t> waits;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     const uint64_t crow = chunk_rows_of(s);
+    std::vector<const sel_program*> gp;
+    std::vector<uint32_t> gacc;
     for (auto& kv : s->tables) {
       TableState& ts = kv.second;
       if (ts.progs.empty()) continue;
       const uint64_t row_begin = ts.cur * crow;
       const uint64_t row_end = std::min(ts.table->nrows, row_begin + crow);
-      BatchTable d{};
-      d.nrows = ts.table->nrows;
-      d.tile_begin = tile;
-      d.row_begin = row_begin;
-      d.prog_begin = (uint32_t)dp.size();
+      // identical programs of different requests are evaluated once
       std::unordered_map<const sel_program*, uint32_t> group;
+      gp.clear();
+      gacc.clear();
       const Request* first = nullptr;
       bool shared = false;
       for (Active& a : ts.progs) {
         const sel_program* p = a.req->progs[a.index];
         auto g = group.find(p);
         if (g == group.end()) {
-          BatchProg bp{};
-          bp.code = p->dcode;
-          bp.nins = p->nins;
-          bp.acc_index = (uint32_t)dp.size();
-          g = group.emplace(p, (uint32_t)dp.size()).first;
-          dp.push_back(bp);
+          g = group.emplace(p, ngroups).first;
+          gp.push_back(p);
+          gacc.push_back(ngroups);
+          ++ngroups;
         }
         if (!first) first = a.req;
         else if (a.req != first) shared = true;
         a.chunks_left -= 1;
         rs.members.push_back(Member{a, g->second, a.chunks_left == 0});
       }
-      d.prog_count = (uint32_t)dp.size() - d.prog_begin;
+      // an empty chunk adds no tile; its programs still finish (count 0)
+      bp.add(ts.table, row_begin, row_end, gp.data(), gacc.data(), (uint32_t)gp.size());
       ts.progs.erase(std::remove_if(ts.progs.begin(), ts.progs.end(),
                                     [](const Active& a) { return a.chunks_left == 0; }),
                      ts.progs.end());
       ts.cur = (ts.cur + 1) % ts.nchunks;
-      if (row_end > row_begin) tile += (row_end - row_begin + kTileRows - 1) / kTileRows;
-      dt.push_back(d);   // an empty table adds no tile; its programs still finish
       s->shared_rounds += shared ? 1 : 0;
     }
-    if (dp.empty()) {
+    if (ngroups == 0) {
       rs.members.clear();
       return false;
     }
-    rs.ngroups = (uint32_t)dp.size();
+    rs.ngroups = ngroups;
     s->rounds += 1;
     s->round_programs += rs.members.size();
+    waits.swap(s->round_waits);
   }
-  // descriptors: tables | progs | done list, staged through pinned memory
-  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
-  const size_t o_progs = up(dt.size() * sizeof(BatchTable));
-  const size_t o_out = up(o_progs + dp.size() * sizeof(BatchProg));
-  const size_t need = o_out + dp.size() * 8;
+  for (hipEvent_t ev : waits) (void)hipStreamWaitEvent(s->stream, ev, 0);
+  // descriptors, then the counts, staged through pinned memory
+  const size_t o_out = (bp.bytes() + 255) & ~size_t(255);
+  const size_t need = o_out + (size_t)ngroups * 8;
   if (need > rs.dev_bytes) {
     if (rs.dev) (void)hipFree(rs.dev);
     if (rs.host) (void)hipHostFree(rs.host);
@@ -300,25 +307,22 @@ bool launch_round(sel_server* s) {
     }
     rs.dev_bytes = want;
   }
-  std::memcpy(rs.host, dt.data(), dt.size() * sizeof(BatchTable));
-  std::memcpy(rs.host + o_progs, dp.data(), dp.size() * sizeof(BatchProg));
   BatchArgs a{};
-  a.tables = (const BatchTable*)rs.dev;
-  a.progs = (const BatchProg*)((char*)rs.dev + o_progs);
-  a.ntables = (uint32_t)dt.size();
-  a.nprogs = (uint32_t)dp.size();
-  a.total_tiles = tile;
+  bp.write(rs.host, (char*)rs.dev, a);
   a.acc = s->d_acc;
   a.done = nullptr;                  // every line of the round is read out and reset
-  a.ndone = (uint32_t)dp.size();
+  a.ndone = ngroups;
   a.out = (unsigned long long*)((char*)rs.dev + o_out);
   a.slot = rs.slot;
   const uint32_t block = 256;
+  const uint32_t lds = bp.lds_bytes(block);
+  int occ = 1;
+  if (sel_batch_occupancy(block, lds, &occ) != 0 || occ < 1) occ = 1;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>((uint64_t)4 * s->ctx->num_cus, (tile + 3) / 4));
+      1, std::min<uint64_t>((uint64_t)std::min(occ, 4) * s->ctx->num_cus, (bp.total_tiles + 3) / 4));
   bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
-  ok = ok && sel_launch_batch(a, grid, block, s->stream) == 0;
-  ok = ok && hipMemcpyAsync(rs.h_out, a.out, dp.size() * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
+  ok = ok && sel_launch_batch(a, grid, block, lds, s->stream) == 0;
+  ok = ok && hipMemcpyAsync(rs.h_out, a.out, (size_t)ngroups * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
   ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
   if (!ok) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -380,6 +384,7 @@ void pd_worker_main(sel_server* s) {
       s->pd_queue.pop_front();
     }
     uint64_t cnt = 0;
+    (void)hipStreamWaitEvent(s->pd_ctx->stream, r->ready, 0);
     sel_status st = sel_pushdown_rowids(s->pd_ctx, r->pd_table, r->pd_prog, r->pd_max_rows, r->pd_out,
                                         r->pd_cap, &cnt);
     std::lock_guard<std::mutex> lk(s->mu);
@@ -401,7 +406,11 @@ void release_server(sel_server* s) {
   if (s->d_acc) (void)hipFree(s->d_acc);
   if (s->stream) (void)hipStreamDestroy(s->stream);
   if (s->pd_ctx) sel_ctx_destroy(s->pd_ctx);
-  for (auto& kv : s->by_ticket) delete kv.second;
+  for (auto& kv : s->by_ticket) {
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
+    delete kv.second;
+  }
+  for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
   delete s;
 }
 
@@ -437,7 +446,7 @@ sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_ser
     release_server(s);
     return st;
   }
-  sel_status st = sel_ctx_create(ctx->device, nullptr, &s->pd_ctx);
+  sel_status st = sel_ctx_create(ctx->device, SEL_STREAM_OWN, &s->pd_ctx);
   if (st != SEL_OK) {
     set_err(ctx, st, "push-down context");
     release_server(s);
@@ -461,6 +470,10 @@ sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ti
     if (!req->tables[i] || !req->progs[i] || req->progs[i]->table != req->tables[i]) {
       delete r;
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " missing or bound to another table");
+    }
+    if (batch_slots_alone(req->progs[i]) > kBatchSlots) {
+      delete r;
+      return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " has too many leaves to batch");
     }
     r->tables.push_back(req->tables[i]);
     r->progs.push_back(req->progs[i]);
@@ -492,6 +505,21 @@ sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ti
     s->rejected += 1;
     delete r;
     return set_err(ctx, SEL_E_BUSY, "request needs more device memory than the server's budget");
+  }
+  if (!s->free_events.empty()) {
+    r->ready = s->free_events.back();
+    s->free_events.pop_back();
+  } else if (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess) {
+    delete r;
+    return set_err(ctx, SEL_E_DEVICE, "hipEventCreate");
+  }
+  {
+    DeviceGuard g(ctx->device);
+    if (hipEventRecord(r->ready, ctx->stream) != hipSuccess) {
+      s->free_events.push_back(r->ready);
+      delete r;
+      return set_err(ctx, SEL_E_DEVICE, "hipEventRecord");
+    }
   }
   r->ticket = s->next_ticket++;
   s->by_ticket[r->ticket] = r;

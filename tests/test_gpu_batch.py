@@ -5,6 +5,7 @@ import pytest
 
 import datagen
 import oracle
+from tests import sqlite_ref
 from tests.gpu_common import say
 
 pytestmark = pytest.mark.gpu
@@ -142,3 +143,31 @@ def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
     c2.tune_load(path)
     assert c2.tune_entries == ctx.tune_entries
     c2.close()
+
+
+@pytest.mark.parametrize("n", [1, 2049, 100_003])
+def test_batch_random_programs(sel, ctx, n):
+    """Random programs (every operator, NULLs, value lists, code sets) on two
+    random tables of ragged size, batched together: enough programs that the
+    batch splits into several passes per table.  Each count equals the plain
+    count and the oracle."""
+    say(f"batch random n={n}")
+    rng = np.random.default_rng(20_000 + n)
+    ts = [datagen.random_table(rng, n, grid=True, null_rate=0.3),
+          datagen.random_table(rng, n + 4097, grid=False, null_rate=0.1)]
+    dts = [sel.device_table(ctx, t) for t in ts]
+    orcs = [oracle.Oracle(t) for t in ts]
+    trees = []
+    for k in range(90):
+        ti = k % 2
+        trees.append((ti, sqlite_ref.clamp_literals(datagen.random_tree(rng, ts[ti]))))
+    pairs = [(dts[ti], ctx.program(dts[ti], tree)) for ti, tree in trees]
+    want = [orcs[ti].count(tree) for ti, tree in trees]
+    assert ctx.count_batch(pairs) == want
+    assert [ctx.count(*p) for p in pairs[:10]] == want[:10]
+    # the same program several times, and a replayed graph of the set
+    assert ctx.count_batch([pairs[3]] * 5 + pairs[:4]) == [want[3]] * 5 + want[:4]
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
