@@ -49,7 +49,7 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
     if (!tables[i] || !progs[i]) return set_err(ctx, SEL_E_INVALID, "NULL table or program");
     if (progs[i]->table != tables[i])
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " is bound to another table");
-    if (batch_slots_alone(progs[i]) > kBatchSlots)
+    if (batch_slots_alone(progs[i]) > kBatchMaxSlots)
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " has too many leaves to batch");
     if (std::find(distinct.begin(), distinct.end(), tables[i]) == distinct.end())
       distinct.push_back(tables[i]);

@@ -7,6 +7,7 @@
 // pass and tile, tests every leaf on it from registers, and runs each
 // program's combinators over the resulting truth words held in LDS slots.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -33,7 +34,37 @@ struct PassCol {
   uint32_t type = 0;
   uint32_t vslot = kNoSlot;
   std::vector<DevInstr> leaves;
+  uint32_t tab_word = kNoLds, tab_count = 0, tab_n = 0;
+  int32_t tab_lo = 0;
 };
+
+void type_range(uint32_t t, int64_t& lo, int64_t& hi) {
+  switch (t) {
+    case T_I8: lo = INT8_MIN; hi = INT8_MAX; break;
+    case T_I16: lo = INT16_MIN; hi = INT16_MAX; break;
+    case T_I32: lo = INT32_MIN; hi = INT32_MAX; break;
+    default: lo = INT64_MIN; hi = INT64_MAX; break;
+  }
+}
+
+// Values [lo, hi] a table leaf can be TRUE on (within the column's type).
+bool leaf_window(const DevInstr& L, int64_t& lo, int64_t& hi) {
+  int64_t tmin, tmax;
+  type_range(L.type, tmin, tmax);
+  if (L.op == D_RANGE) {
+    lo = L.lo;
+    hi = (int64_t)((uint64_t)L.lo + L.span);
+  } else if (L.op == D_BITMAP && L.span > 0) {
+    lo = L.lo;
+    if (L.lo > tmax) return false;
+    hi = L.span - 1 > (uint64_t)(tmax - L.lo) ? tmax : L.lo + (int64_t)(L.span - 1);
+  } else {
+    return false;
+  }
+  lo = std::max(lo, tmin);
+  hi = std::min(hi, tmax);
+  return lo <= hi;
+}
 
 // One pass under construction.
 struct Pass {
@@ -42,6 +73,78 @@ struct Pass {
   std::map<const uint32_t*, uint32_t> valid_slot;
   std::vector<std::pair<std::vector<uint32_t>, uint32_t>> progs;  // (ops, acc line)
   uint32_t slots = 0;
+  std::vector<BatchBitmap> bms;             // staged in LDS
+  std::map<const void*, uint32_t> bm_at;    // source -> its BatchBitmap
+  uint32_t bm_words = 0;
+
+  // Lookup tables and staged bitmaps, within kBatchBmWords words: first a
+  // table for each narrow column with at least two value-test leaves
+  // (bitmaps and ranges, at most 32), most leaves first; then the bitmaps of
+  // the remaining leaves.  Table leaves move to the front of their column.
+  void finalize() {
+    std::vector<PassCol*> order;
+    for (PassCol& c : cols) order.push_back(&c);
+    std::stable_sort(order.begin(), order.end(),
+                     [](const PassCol* a, const PassCol* b) { return a->leaves.size() > b->leaves.size(); });
+    for (PassCol* c : order) {
+      if (c->type == T_I64) continue;
+      std::vector<DevInstr> tab, rest;
+      int64_t lo = INT64_MAX, hi = INT64_MIN;
+      for (const DevInstr& L : c->leaves) {
+        int64_t a, b;
+        if (tab.size() < 32 && (L.op == D_RANGE || L.op == D_BITMAP)) {
+          if (leaf_window(L, a, b)) {
+            lo = std::min(lo, a);
+            hi = std::max(hi, b);
+          }
+          tab.push_back(L);
+        } else {
+          rest.push_back(L);
+        }
+      }
+      if (tab.size() < 2) continue;
+      if (lo > hi) { lo = 0; hi = 0; }   // every leaf empty: one all-zero entry
+      const uint64_t n = (uint64_t)(hi - lo) + 1;
+      if (n + 1 > kBatchBmWords - bm_words) continue;
+      c->tab_word = bm_words;
+      c->tab_count = (uint32_t)tab.size();
+      c->tab_lo = (int32_t)lo;
+      c->tab_n = (uint32_t)n;
+      bm_words += (uint32_t)n + 1;
+      c->leaves = tab;
+      c->leaves.insert(c->leaves.end(), rest.begin(), rest.end());
+    }
+    for (PassCol& c : cols) {
+      const size_t first = c.tab_word != kNoLds ? c.tab_count : 0;
+      for (size_t k = first; k < c.leaves.size(); ++k) stage(c.leaves[k]);
+    }
+  }
+
+  // Stage a bitmap leaf in LDS if it fits the budget and (for narrow
+  // columns) its window [lo, lo + nbits) lies inside int32.
+  void stage(DevInstr& L) {
+    L.lds_word = kNoLds;
+    const uint64_t nbits = L.span;
+    if (L.op != D_BITMAP || nbits == 0) return;
+    if (L.type != T_I64 &&
+        (L.lo < INT32_MIN || L.lo > INT32_MAX || nbits - 1 > (uint64_t)(INT32_MAX - L.lo)))
+      return;
+    const uint64_t words = (nbits + 31) / 32;
+    auto it = bm_at.find(L.aux);
+    if (it == bm_at.end() || bms[it->second].words != words) {
+      if (bm_words + words + 1 > kBatchBmWords) return;
+      BatchBitmap b{};
+      b.src = (const uint32_t*)L.aux;
+      b.words = (uint32_t)words;
+      b.last_mask = nbits % 32 ? (1u << (nbits % 32)) - 1u : ~0u;
+      b.lds_word = bm_words;
+      bm_words += (uint32_t)words + 1;
+      bms.push_back(b);
+      it = bm_at.insert_or_assign(L.aux, (uint32_t)bms.size() - 1).first;
+    }
+    L.lds_word = bms[it->second].lds_word;
+    L.n = (uint32_t)words * 32;   // index of a zero bit past the copy
+  }
 
   // slots a program would add to this pass
   uint32_t new_slots(const sel_program* p) const {
@@ -105,6 +208,7 @@ struct Pass {
           DevInstr L = I;
           L.flags = 0;
           L.slot = s;
+          L.lds_word = kNoLds;
           home->leaves.push_back(L);
         }
         ops.push_back(batch_op(D_RANGE, s, vslot_of(I)));
@@ -114,7 +218,20 @@ struct Pass {
         ops.push_back(batch_op(op, 0, 0));
       }
     }
-    progs.emplace_back(std::move(ops), acc);
+    // a value-test leaf that is the right operand of the AND / OR right
+    // after it combines with the top of the stack directly
+    std::vector<uint32_t> fused;
+    fused.reserve(ops.size());
+    for (size_t k = 0; k < ops.size(); ++k) {
+      const uint32_t op = ops[k] & 0xFFu, next = k + 1 < ops.size() ? ops[k + 1] & 0xFFu : 0u;
+      if (op == D_RANGE && (next == D_AND || next == D_OR)) {
+        fused.push_back((ops[k] & ~0xFFu) | (next == D_AND ? B_AND_LEAF : B_OR_LEAF));
+        ++k;
+      } else {
+        fused.push_back(ops[k]);
+      }
+    }
+    progs.emplace_back(std::move(fused), acc);
   }
 };
 
@@ -128,8 +245,10 @@ void BatchPlan::clear() {
   leaves.clear();
   progs.clear();
   ops.clear();
+  bms.clear();
   total_tiles = 0;
   max_slots = 0;
+  max_bm_words = 0;
 }
 
 void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
@@ -138,6 +257,7 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
   const uint64_t tiles = (row_end - row_begin + kTileRows - 1) / kTileRows;
   auto flush = [&](Pass& ps) {
     if (ps.progs.empty()) return;
+    ps.finalize();
     BatchTable e{};
     e.nrows = t->nrows;
     e.tile_begin = total_tiles;
@@ -146,6 +266,10 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     e.prog_count = (uint32_t)ps.progs.size();
     e.col_begin = (uint32_t)cols.size();
     e.col_count = (uint32_t)ps.cols.size();
+    e.ntiles = tiles;
+    e.bm_begin = (uint32_t)bms.size();
+    e.bm_count = (uint32_t)ps.bms.size();
+    bms.insert(bms.end(), ps.bms.begin(), ps.bms.end());
     for (PassCol& c : ps.cols) {
       BatchCol bc{};
       bc.data = c.data;
@@ -154,6 +278,11 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
       bc.vslot = c.vslot;
       bc.leaf_begin = (uint32_t)leaves.size();
       bc.leaf_count = (uint32_t)c.leaves.size();
+      bc.tab_word = c.tab_word;
+      bc.tab_count = c.tab_count;
+      bc.tab_lo = c.tab_lo;
+      bc.tab_n = c.tab_n;
+      e.ntab += c.tab_word != kNoLds ? 1u : 0u;
       leaves.insert(leaves.end(), c.leaves.begin(), c.leaves.end());
       cols.push_back(bc);
     }
@@ -167,7 +296,8 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     }
     entries.push_back(e);
     max_slots = std::max(max_slots, ps.slots);
-    total_tiles += tiles;
+    max_bm_words = std::max(max_bm_words, ps.bm_words);
+    total_tiles += (tiles + kBatchTileAlign - 1) / kBatchTileAlign * kBatchTileAlign;
   };
   Pass ps;
   for (uint32_t i = 0; i < n; ++i) {
@@ -190,7 +320,8 @@ size_t BatchPlan::bytes() const {
   o = up(o + cols.size() * sizeof(BatchCol));
   o = up(o + leaves.size() * sizeof(DevInstr));
   o = up(o + progs.size() * sizeof(BatchProg));
-  return up(o + ops.size() * sizeof(uint32_t));
+  o = up(o + ops.size() * sizeof(uint32_t));
+  return up(o + bms.size() * sizeof(BatchBitmap));
 }
 
 void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
@@ -198,6 +329,7 @@ void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
   const size_t o_leaves = up(o_cols + cols.size() * sizeof(BatchCol));
   const size_t o_progs = up(o_leaves + leaves.size() * sizeof(DevInstr));
   const size_t o_ops = up(o_progs + progs.size() * sizeof(BatchProg));
+  const size_t o_bms = up(o_ops + ops.size() * sizeof(uint32_t));
   std::memset(host, 0, bytes());
   if (!entries.empty()) std::memcpy(host, entries.data(), entries.size() * sizeof(BatchTable));
   if (!cols.empty()) std::memcpy(host + o_cols, cols.data(), cols.size() * sizeof(BatchCol));
@@ -208,14 +340,17 @@ void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
     hp[k].ops = (const uint32_t*)(dev + o_ops + sizeof(uint32_t) * (uintptr_t)progs[k].ops);
   }
   if (!ops.empty()) std::memcpy(host + o_ops, ops.data(), ops.size() * sizeof(uint32_t));
+  if (!bms.empty()) std::memcpy(host + o_bms, bms.data(), bms.size() * sizeof(BatchBitmap));
   a.tables = (const BatchTable*)dev;
   a.cols = (const BatchCol*)(dev + o_cols);
   a.leaves = (const DevInstr*)(dev + o_leaves);
   a.progs = (const BatchProg*)(dev + o_progs);
+  a.bms = (const BatchBitmap*)(dev + o_bms);
   a.ntables = (uint32_t)entries.size();
   a.nprogs = (uint32_t)progs.size();
   a.total_tiles = total_tiles;
   a.slot_words = max_slots * (uint32_t)kWave;
+  a.bm_words = max_bm_words;
 }
 
 }  // namespace selrt

@@ -501,102 +501,247 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
 }
 
 // --------------------------------------------------------- batched count --
-// Value tests of one leaf over values already in registers (a full tile):
-// bits [b0, b0 + nb) of the lane's word, highest first.  No guard: batched
-// evaluation tests every row (a guard only saves lookups).
+// Column values of one pipeline segment: a full tile of a narrow column or
+// half a tile of an int64 column, 128 B per lane at most.  Narrow types use
+// the leading components of each step's vector.
+struct Seg { v4i w[kSteps]; };
+
 template <int TY>
-__device__ __forceinline__ uint32_t raw_leaf(const Raw<TY>& r, uint32_t op, CInstr I, int h) {
+__device__ __forceinline__ auto seg_get(const Seg& r, int b) {
+  const int j = b >> 2, i = b & 3;
+  if constexpr (TY == T_I8) {
+    return (int32_t)(int8_t)((uint32_t)r.w[j][0] >> (8 * i));
+  } else if constexpr (TY == T_I16) {
+    return (int32_t)(int16_t)((uint32_t)r.w[j][i >> 1] >> (16 * (i & 1)));
+  } else if constexpr (TY == T_I32) {
+    return (int32_t)r.w[j][i];
+  } else {  // b indexes the loaded half: 0..15
+    const v4i& q = r.w[2 * j + (i >> 1)];
+    const int k = 2 * (i & 1);
+    return (int64_t)(((uint64_t)(uint32_t)q[k + 1] << 32) | (uint32_t)q[k]);
+  }
+}
+
+// Issue the loads of a segment (and, with a column's first segment, of its
+// validity word); nothing waits for them here.
+__device__ __forceinline__ void seg_issue(Seg& r, uint32_t& V, const CONSTANT BatchCol* C, int h,
+                                          uint64_t tb, uint32_t lane) {
+  const void* data = C->data;
+  switch (C->type) {
+    case T_I8: {
+      const GLOBAL uint32_t* p = gptr<uint32_t>((const int8_t*)data + tb) + lane;
+#pragma unroll
+      for (int j = 0; j < kSteps; ++j) r.w[j][0] = (int32_t)__builtin_nontemporal_load(p + 64 * j);
+      break;
+    }
+    case T_I16: {
+      const GLOBAL v2i* p = gptr<v2i>((const int16_t*)data + tb) + lane;
+#pragma unroll
+      for (int j = 0; j < kSteps; ++j) {
+        const v2i x = __builtin_nontemporal_load(p + 64 * j);
+        r.w[j][0] = x[0];
+        r.w[j][1] = x[1];
+      }
+      break;
+    }
+    case T_I32: {
+      const GLOBAL v4i* p = gptr<v4i>((const int32_t*)data + tb) + lane;
+#pragma unroll
+      for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+      break;
+    }
+    default: {  // int64: h = 0 loads steps 4..7 (bits 16..31), h = 1 steps 0..3
+      const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * 4 * (1 - h);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        r.w[2 * j] = __builtin_nontemporal_load(p + 128 * j);
+        r.w[2 * j + 1] = __builtin_nontemporal_load(p + 128 * j + 1);
+      }
+      break;
+    }
+  }
+  if (h == 0 && C->vslot != kNoSlot) V = valid_bits<true>(C->valid, tb, lane, tb + kTileRows);
+}
+
+// Value tests of one leaf on a segment: bits [0, nb) of the result, highest
+// row first.  No guard: batched evaluation tests every row (a guard only
+// saves lookups).
+template <int TY>
+__device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I,
+                                             const uint32_t* bmlds) {
   constexpr int nb = TY == T_I64 ? 16 : 32;
   const int64_t lo = I->lo;
   const uint64_t span = I->span;
   uint32_t P = 0;
-  if (op == D_RANGE) {
+  if (op == D_BITMAP && I->lds_word != kNoLds) {
+    // staged copy: an offset past the window is clamped to the zero bit z
+    // that follows the copied words, so no test or select is needed.  For
+    // narrow columns the window lies inside int32 (the host stages only
+    // such bitmaps), so 32-bit differences are exact.
+    const uint32_t* bm = bmlds + I->lds_word;
+    const uint32_t z = I->n;
+    if constexpr (TY == T_I64) {
+#pragma unroll
+      for (int b = nb - 1; b >= 0; --b) {
+        const uint64_t d = (uint64_t)seg_get<TY>(r, b) - (uint64_t)lo;
+        const uint32_t k = d < z ? (uint32_t)d : z;
+        P = (P << 1) + ((bm[k >> 5] >> (k & 31)) & 1u);
+      }
+    } else {
+      const uint32_t lo32 = (uint32_t)lo;
+#pragma unroll
+      for (int b = nb - 1; b >= 0; --b) {
+        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - lo32;
+        const uint32_t k = d < z ? d : z;
+        P = (P << 1) + ((bm[k >> 5] >> (k & 31)) & 1u);
+      }
+    }
+  } else if (op == D_RANGE) {
     if constexpr (TY == T_I64) {
 #pragma unroll
       for (int b = nb - 1; b >= 0; --b)
-        P = (P << 1) + (uint32_t)((uint64_t)get<TY>(r, b) - (uint64_t)lo <= span);
+        P = (P << 1) + (uint32_t)((uint64_t)seg_get<TY>(r, b) - (uint64_t)lo <= span);
     } else {
       const uint32_t lo32 = (uint32_t)lo, span32 = (uint32_t)span;
 #pragma unroll
       for (int b = nb - 1; b >= 0; --b)
-        P = (P << 1) + (uint32_t)((uint32_t)get<TY>(r, b) - lo32 <= span32);
+        P = (P << 1) + (uint32_t)((uint32_t)seg_get<TY>(r, b) - lo32 <= span32);
     }
-  } else {  // D_BITMAP
+  } else {  // D_BITMAP in global memory
     const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
 #pragma unroll
     for (int b = nb - 1; b >= 0; --b) {
       uint64_t d;
-      if constexpr (TY == T_I64) d = (uint64_t)get<TY>(r, b) - (uint64_t)lo;
-      else d = (uint64_t)((int64_t)get<TY>(r, b) - lo);
+      if constexpr (TY == T_I64) d = (uint64_t)seg_get<TY>(r, b) - (uint64_t)lo;
+      else d = (uint64_t)((int64_t)seg_get<TY>(r, b) - lo);
       const bool ok = d < span;
       const uint32_t k = ok ? (uint32_t)d : 0u;
       P = (P << 1) + (ok & ((bits[k >> 5] >> (k & 31)) & 1u));
     }
   }
-  (void)h;
   return P;
 }
 
-// All leaf tests of one column on one tile; each truth word goes to the
-// wave's LDS slot named by the leaf.
-template <int TY, bool FULL>
-__device__ __forceinline__ void column_leaves(const CONSTANT BatchCol* C, CInstr leaves,
-                                              uint64_t tb, uint32_t lane, uint64_t nrows,
-                                              uint32_t* wl) {
-  const void* data = C->data;
+// Every leaf of one segment; truth words go to the wave's slots.  An int64
+// column's upper half (h = 0) writes bits 16..31, its lower half completes
+// them.  Sparse value lists take the element path once, with the last
+// segment of their column.
+template <int TY>
+__device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol* C, int h,
+                                           CInstr leaves, uint64_t tb, uint32_t lane,
+                                           uint32_t* wl, const uint32_t* bmlds) {
   const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
-  if constexpr (!FULL) {
-    for (uint32_t k = 0; k < ln; ++k) {
-      CInstr I = leaves + lb + k;
-      wl[I->slot * kWave + lane] = leaf_pred<TY, false>(I->op, I, tb, lane, nrows, ~0u);
-    }
-  } else if constexpr (TY == T_I64) {
+  uint32_t k0 = 0;
+  if constexpr (TY != T_I64) {
+    const uint32_t tw = C->tab_word;
+    if (tw != kNoLds) {
+      // one table lookup per row serves every table leaf of the column;
+      // leaf i's word is bit i of the 32 looked-up entries
+      const uint32_t* tab = bmlds + tw;
+      const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n;
+      uint32_t T[32];
 #pragma unroll
-    for (int h = 1; h >= 0; --h) {
-      Raw<TY> r;
-      load_half64(r, data, tb, lane, h);
-      for (uint32_t k = 0; k < ln; ++k) {
-        CInstr I = leaves + lb + k;
-        const uint32_t op = I->op;
-        uint32_t* w = wl + I->slot * kWave + lane;
-        if (op == D_INLIST) {
-          if (h == 0) *w = leaf_pred<TY, false>(op, I, tb, lane, nrows, ~0u);
-          continue;
-        }
-        const uint32_t P = raw_leaf<TY>(r, op, I, h);
-        if (h == 1) *w = P;
-        else *w = (*w << 16) | P;
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+        T[b] = tab[d < n ? d : n];
       }
+      const uint32_t m = C->tab_count;
+      for (uint32_t i = 0; i < m; ++i) {
+        uint32_t P = 0;
+#pragma unroll
+        for (int b = 31; b >= 0; --b) P = (P << 1) + ((T[b] >> i) & 1u);
+        wl[leaves[lb + i].slot * kWave + lane] = P;
+      }
+      k0 = m;
     }
-  } else {
-    Raw<TY> r;
-    load_full<TY>(r, data, tb, lane);
-    for (uint32_t k = 0; k < ln; ++k) {
-      CInstr I = leaves + lb + k;
-      const uint32_t op = I->op;
-      wl[I->slot * kWave + lane] = op == D_INLIST ? leaf_pred<TY, false>(op, I, tb, lane, nrows, ~0u)
-                                                  : raw_leaf<TY>(r, op, I, 0);
+  }
+  for (uint32_t k = k0; k < ln; ++k) {
+    CInstr I = leaves + lb + k;
+    const uint32_t op = I->op;
+    uint32_t* w = wl + I->slot * kWave + lane;
+    if (op == D_INLIST) {
+      if (TY != T_I64 || h == 1) *w = leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u);
+      continue;
     }
+    const uint32_t P = seg_leaf<TY>(r, op, I, bmlds);
+    if (TY != T_I64 || h == 0) *w = P;
+    else *w = (*w << 16) | P;
   }
 }
 
-template <bool FULL>
-__device__ __forceinline__ void entry_leaves(const CONSTANT BatchTable* E, const CONSTANT BatchCol* cols,
-                                             CInstr leaves, uint64_t tb, uint32_t lane,
-                                             uint64_t nrows, uint32_t* wl) {
+// All leaf tests of an entry on a full tile, as a software pipeline over
+// the segments of the columns that have leaves: the loads of the next
+// segment are in flight while the leaves of the current one run.
+__device__ __forceinline__ void entry_leaves_full(const CONSTANT BatchTable* E,
+                                                  const CONSTANT BatchCol* cols, CInstr leaves,
+                                                  uint64_t tb, uint32_t lane, uint32_t* wl,
+                                                  const uint32_t* bmlds) {
+  const uint32_t cb = E->col_begin, cn = E->col_count;
+  // columns that only null tests read: validity alone
+  for (uint32_t c = 0; c < cn; ++c) {
+    const CONSTANT BatchCol* C = cols + cb + c;
+    if (!C->leaf_count && C->vslot != kNoSlot)
+      wl[C->vslot * kWave + lane] = valid_bits<true>(C->valid, tb, lane, tb + kTileRows);
+  }
+  uint32_t c = 0;
+  while (c < cn && !cols[cb + c].leaf_count) ++c;
+  if (c == cn) return;
+  Seg cur;
+  uint32_t curV = ~0u;
+  int h = 0;
+  seg_issue(cur, curV, cols + cb + c, h, tb, lane);
+  for (;;) {
+    const CONSTANT BatchCol* C = cols + cb + c;
+    const uint32_t ty = C->type;
+    uint32_t nc = c;
+    int nh = 0;
+    if (ty == T_I64 && h == 0) {
+      nh = 1;
+    } else {
+      ++nc;
+      while (nc < cn && !cols[cb + nc].leaf_count) ++nc;
+    }
+    const bool more = nc < cn;
+    Seg nxt;
+    uint32_t nxtV = ~0u;
+    if (more) seg_issue(nxt, nxtV, cols + cb + nc, nh, tb, lane);
+    if (h == 0 && C->vslot != kNoSlot) wl[C->vslot * kWave + lane] = curV;
+    switch (ty) {
+      case T_I8: seg_leaves<T_I8>(cur, C, h, leaves, tb, lane, wl, bmlds); break;
+      case T_I16: seg_leaves<T_I16>(cur, C, h, leaves, tb, lane, wl, bmlds); break;
+      case T_I32: seg_leaves<T_I32>(cur, C, h, leaves, tb, lane, wl, bmlds); break;
+      default: seg_leaves<T_I64>(cur, C, h, leaves, tb, lane, wl, bmlds); break;
+    }
+    if (!more) break;
+    cur = nxt;
+    curV = nxtV;
+    c = nc;
+    h = nh;
+  }
+}
+
+// All leaf tests of an entry on the partial last tile of its table.
+__device__ __forceinline__ void entry_leaves_partial(const CONSTANT BatchTable* E,
+                                                     const CONSTANT BatchCol* cols, CInstr leaves,
+                                                     uint64_t tb, uint32_t lane, uint64_t nrows,
+                                                     uint32_t* wl) {
   const uint32_t cb = E->col_begin, cn = E->col_count;
   for (uint32_t c = 0; c < cn; ++c) {
     const CONSTANT BatchCol* C = cols + cb + c;
-    if (C->leaf_count) {
+    const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
+    for (uint32_t k = 0; k < ln; ++k) {
+      CInstr I = leaves + lb + k;
+      uint32_t P;
       switch (C->type) {
-        case T_I8: column_leaves<T_I8, FULL>(C, leaves, tb, lane, nrows, wl); break;
-        case T_I16: column_leaves<T_I16, FULL>(C, leaves, tb, lane, nrows, wl); break;
-        case T_I32: column_leaves<T_I32, FULL>(C, leaves, tb, lane, nrows, wl); break;
-        default: column_leaves<T_I64, FULL>(C, leaves, tb, lane, nrows, wl); break;
+        case T_I8: P = leaf_pred<T_I8, false>(I->op, I, tb, lane, nrows, ~0u); break;
+        case T_I16: P = leaf_pred<T_I16, false>(I->op, I, tb, lane, nrows, ~0u); break;
+        case T_I32: P = leaf_pred<T_I32, false>(I->op, I, tb, lane, nrows, ~0u); break;
+        default: P = leaf_pred<T_I64, false>(I->op, I, tb, lane, nrows, ~0u); break;
       }
+      wl[I->slot * kWave + lane] = P;
     }
     const uint32_t vs = C->vslot;
-    if (vs != kNoSlot) wl[vs * kWave + lane] = valid_bits<FULL>(C->valid, tb, lane, nrows);
+    if (vs != kNoSlot) wl[vs * kWave + lane] = valid_bits<false>(C->valid, tb, lane, nrows);
   }
 }
 
@@ -610,7 +755,13 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
   for (uint32_t pc = 0; pc < nops; ++pc) {
     const uint32_t w = ops[pc];
     const uint32_t op = w & 0xFFu;
-    if (op < D_AND || op == D_TRUE || op == D_FALSE) {
+    if (op >= B_AND_LEAF) {
+      const uint32_t vs = w >> 20;
+      const uint32_t V = vs == kNoSlot ? ~0u : wl[vs * kWave + lane];
+      const uint32_t P = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+      if (op == B_AND_LEAF) { tt &= P & V; tf |= ~P & V; }
+      else { tt |= P & V; tf &= ~P & V; }
+    } else if (op < D_AND || op == D_TRUE || op == D_FALSE) {
       uint32_t t, f;
       const uint32_t vs = w >> 20;
       const uint32_t V = (vs == kNoSlot || op >= D_TRUE) ? ~0u : wl[vs * kWave + lane];
@@ -653,35 +804,87 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
 // accumulating: a cooperative scan adds one chunk per launch.
 __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
   __shared__ uint32_t acc[kBatchMaxProgs];
-  extern __shared__ uint32_t slots[];
-  const uint32_t lane = threadIdx.x & 63;
+  extern __shared__ uint32_t dyn[];   // staged bitmaps, then each wave's slots
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
-  const uint64_t W = (uint64_t)gridDim.x * nw;
-  uint32_t* wl = slots + (threadIdx.x >> 6) * a.slot_words;
+  uint32_t* bmlds = dyn;
+  uint32_t* wl = dyn + a.bm_words + wave * a.slot_words;
   for (uint32_t p = threadIdx.x; p < (uint32_t)kBatchMaxProgs; p += blockDim.x) acc[p] = 0;
   __syncthreads();
   const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
   const CONSTANT BatchCol* cols = (const CONSTANT BatchCol*)a.cols;
   CInstr leaves = (CInstr)a.leaves;
   const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
-  for (uint64_t flat = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); flat < a.total_tiles;
-       flat += W) {
+  const CONSTANT BatchBitmap* bms = (const CONSTANT BatchBitmap*)a.bms;
+  // the workgroup takes groups of nw consecutive tiles; entry ranges are
+  // padded to multiples of 4, so a group never straddles two entries and the
+  // loop below (with its barriers) is uniform over the workgroup
+  const uint64_t ngroups = a.total_tiles / nw;
+  uint32_t staged = 0xFFFFFFFFu;
+  for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const uint64_t flat = g * nw + wave;
     // entry holding this tile: last e with tile_begin <= flat (uniform search)
     uint32_t lo = 0, hi = a.ntables;
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) >> 1;
       if (tables[mid].tile_begin <= flat) lo = mid; else hi = mid;
     }
+    lo = uni(lo);
     const CONSTANT BatchTable* E = tables + lo;
+    if ((E->bm_count || E->ntab) && lo != staged) {
+      __syncthreads();   // every wave is done with the previous tables
+      for (uint32_t c = 0; c < E->col_count; ++c) {
+        const CONSTANT BatchCol* C = cols + E->col_begin + c;
+        if (C->tab_word == kNoLds) continue;
+        const uint32_t n = C->tab_n, m = C->tab_count;
+        const int64_t L = C->tab_lo;
+        CInstr tl = leaves + C->leaf_begin;
+        uint32_t* dst = bmlds + C->tab_word;
+        for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
+          uint32_t w = 0;
+          if (i < n) {
+            const int64_t x = L + (int64_t)i;
+            for (uint32_t k = 0; k < m; ++k) {
+              CInstr I = tl + k;
+              const uint64_t d = (uint64_t)x - (uint64_t)I->lo;
+              uint32_t bit;
+              if (I->op == D_RANGE) {
+                bit = d <= I->span;
+              } else {  // D_BITMAP
+                const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
+                bit = d < I->span ? (bits[d >> 5] >> (d & 31)) & 1u : 0u;
+              }
+              w |= bit << k;
+            }
+          }
+          dst[i] = w;
+        }
+      }
+      for (uint32_t k = 0; k < E->bm_count; ++k) {
+        const CONSTANT BatchBitmap* B = bms + E->bm_begin + k;
+        const uint32_t n = B->words, last = B->last_mask;
+        const GLOBAL uint32_t* src = gptr<uint32_t>(B->src);
+        uint32_t* dst = bmlds + B->lds_word;
+        for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
+          uint32_t w = 0;
+          if (i < n) w = i + 1 == n ? src[i] & last : src[i];
+          dst[i] = w;
+        }
+      }
+      __syncthreads();
+      staged = lo;
+    }
+    const uint64_t local = flat - E->tile_begin;
+    if (local >= E->ntiles) continue;   // padding
     const uint64_t nrows = E->nrows;
-    const uint64_t tb = E->row_begin + (flat - E->tile_begin) * kTileRows;
+    const uint64_t tb = E->row_begin + local * kTileRows;
     const uint32_t pb = E->prog_begin, pn = E->prog_count;
     const bool full = tb + kTileRows <= nrows;
     uint32_t inr = ~0u;
     if (full) {
-      entry_leaves<true>(E, cols, leaves, tb, lane, nrows, wl);
+      entry_leaves_full(E, cols, leaves, tb, lane, wl, bmlds);
     } else {
-      entry_leaves<false>(E, cols, leaves, tb, lane, nrows, wl);
+      entry_leaves_partial(E, cols, leaves, tb, lane, nrows, wl);
       inr = inrange_bits(tb, lane, nrows);
     }
     for (uint32_t k = 0; k < pn; ++k) {

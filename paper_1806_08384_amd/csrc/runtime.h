@@ -176,15 +176,18 @@ sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int 
 // Descriptors of one leaf-major batched launch (k_batch).  add() appends
 // passes over rows [row_begin, row_end) of a table for a list of programs;
 // a pass holds as many programs as fit kBatchSlots LDS slots (deduplicated
-// leaf words plus validity words), so each pass reads its columns once.
+// leaf words plus validity words; a single larger program gets a pass of its
+// own), so each pass reads its columns once.
 struct BatchPlan {
   std::vector<sel::BatchTable> entries;
   std::vector<sel::BatchCol> cols;
   std::vector<DevInstr> leaves;
   std::vector<sel::BatchProg> progs;   // ops holds an index into `ops` until written
   std::vector<uint32_t> ops;
+  std::vector<sel::BatchBitmap> bms;
   uint64_t total_tiles = 0;
   uint32_t max_slots = 0;
+  uint32_t max_bm_words = 0;
   void clear();
   // acc[k]: accumulator line of progs[k].  Programs of an empty range add
   // nothing (their lines stay zero).
@@ -194,11 +197,13 @@ struct BatchPlan {
   // Image of the descriptors for device address `dev` into `host` (bytes()
   // long); sets the descriptor pointers and counts of `a`.
   void write(uint8_t* host, char* dev, sel::BatchArgs& a) const;
-  uint32_t lds_bytes(uint32_t block) const { return max_slots * 256u * (block / 64); }
+  uint32_t lds_bytes(uint32_t block) const {
+    return 4u * max_bm_words + max_slots * 256u * (block / 64);
+  }
 };
 
 // LDS slots a program needs in a pass of its own (distinct leaves plus
-// validity words); batching requires at most kBatchSlots.
+// validity words); batching requires at most kBatchMaxSlots.
 uint32_t batch_slots_alone(const sel_program* p);
 sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
                       const sel_program* const* progs, BatchPlan& bp);

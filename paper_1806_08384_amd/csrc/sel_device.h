@@ -56,7 +56,8 @@ struct DevInstr {          // 64 bytes, read with scalar loads
   uint64_t span;           // D_RANGE: hi - lo (unsigned) / D_BITMAP: nbits
   const void* aux;         // D_BITMAP words / D_INLIST values
   uint32_t slot;           // batched evaluation: LDS slot of the leaf's word
-  uint32_t reserved;
+  uint32_t lds_word;       // batched D_BITMAP: offset of its staged copy in
+                           // LDS (n = index of a zero bit past it), or kNoLds
 };
 static_assert(sizeof(DevInstr) == 64, "DevInstr layout");
 
@@ -107,36 +108,72 @@ struct CompactArgs {
 // an LDS slot of its own; then each program's combinators run over the
 // slots.  A column is thus read from HBM once per entry, however many
 // programs and leaves use it.
-constexpr uint32_t kBatchSlots = 64;      // LDS slots per wave (256 B each)
+constexpr uint32_t kBatchSlots = 32;      // LDS slots per wave (256 B each) that
+                                          // passes are packed to; 3 workgroups per CU
+constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
+                                          // and 32 validity words
 constexpr uint32_t kNoSlot = 0xFFFu;
+// When a pass starts on a workgroup it builds, in LDS, a lookup table for
+// each narrow column with several leaves (entry x - lo holds one bit per
+// leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
+// most this many words per workgroup in all.
+constexpr uint32_t kBatchBmWords = 4096;
+constexpr uint32_t kNoLds = 0xFFFFFFFFu;
+// Entry tile ranges are padded to a multiple of this, so that the waves of
+// one workgroup (1, 2 or 4) always work on the same entry.
+constexpr uint32_t kBatchTileAlign = 4;
 
 // Combinator op of a batched program: op | p_slot << 8 | v_slot << 20.
 //   D_RANGE    leaf with predicate word in p_slot (any value test)
 //   D_NN_TRUE .. D_NOTNULL   null tests on the validity word in v_slot
 //   D_TRUE, D_FALSE, D_AND, D_OR, D_NOT, D_ISUNK as in programs
+//   B_AND_LEAF, B_OR_LEAF    a value-test leaf fused with the AND / OR that
+//                            consumes it: top = top AND/OR leaf
 // v_slot == kNoSlot: the column has no NULLs (validity all ones).
+constexpr uint32_t B_AND_LEAF = 24;
+constexpr uint32_t B_OR_LEAF = 25;
 inline constexpr uint32_t batch_op(uint32_t op, uint32_t p, uint32_t v) {
   return op | (p << 8) | (v << 20);
 }
 
-struct BatchTable {            // 48 bytes: one pass over a table or a chunk
+struct BatchTable {            // 64 bytes: one pass over a table or a chunk
   uint64_t nrows;              // rows of the whole table
   uint64_t tile_begin;         // first flat tile index of this entry
   uint64_t row_begin;          // first row of the entry (a multiple of kTileRows)
+  uint64_t ntiles;             // tiles of the entry (its flat range is padded
+                               // to a multiple of kBatchTileAlign)
   uint32_t prog_begin;         // into the BatchProg array
   uint32_t prog_count;
   uint32_t col_begin;          // into the BatchCol array
   uint32_t col_count;
-  uint32_t pad[2];
+  uint32_t bm_begin;           // into the BatchBitmap array
+  uint32_t bm_count;
+  uint32_t ntab;               // columns with a lookup table
+  uint32_t pad;
 };
 
-struct BatchCol {              // 32 bytes: a column one entry reads
+struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS
+  const uint32_t* src;
+  uint32_t words;              // words copied; a zero word follows them
+  uint32_t last_mask;          // bits of the last word below nbits
+  uint32_t lds_word;           // offset in the workgroup's bitmap area
+  uint32_t pad;
+};
+
+struct BatchCol {              // 48 bytes: a column one entry reads
   const void* data;
   const uint32_t* valid;       // nullptr: no NULLs
   uint32_t type;               // DevType
   uint32_t vslot;              // slot of the validity word, or kNoSlot
   uint32_t leaf_begin;         // its leaf tests: DevInstr array, slot field set
   uint32_t leaf_count;
+  // Lookup table (narrow columns): its first tab_count leaves are bits
+  // 0 .. tab_count-1 of word min(x - tab_lo, tab_n) at LDS offset tab_word;
+  // word tab_n is zero.  tab_word == kNoLds: no table.
+  uint32_t tab_word;
+  uint32_t tab_count;
+  int32_t tab_lo;
+  uint32_t tab_n;
 };
 
 struct BatchProg {             // 16 bytes
@@ -153,9 +190,10 @@ struct BatchArgs {
   const BatchCol* cols;
   const DevInstr* leaves;
   const BatchProg* progs;
+  const BatchBitmap* bms;
   uint32_t ntables;
   uint32_t nprogs;
-  uint64_t total_tiles;
+  uint64_t total_tiles;        // a multiple of kBatchTileAlign
   unsigned long long* acc;     // accumulator lines (kBatchAccStride u64 each)
   // After the launch, the last workgroup moves accumulator done[k] to out[k]
   // and zeroes it (k < ndone); done == nullptr means lines 0 .. ndone-1.
@@ -163,6 +201,8 @@ struct BatchArgs {
   const uint32_t* done;
   uint32_t ndone;
   uint32_t slot_words;         // LDS words per wave: slots * 64
+  uint32_t bm_words;           // LDS words of staged bitmaps per workgroup
+  uint32_t pad;
   unsigned long long* out;
   DevSlot* slot;
 };

@@ -471,7 +471,7 @@ sel_status sel_server_submit(sel_server* s, const sel_request* req, uint64_t* ti
       delete r;
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " missing or bound to another table");
     }
-    if (batch_slots_alone(req->progs[i]) > kBatchSlots) {
+    if (batch_slots_alone(req->progs[i]) > kBatchMaxSlots) {
       delete r;
       return set_err(ctx, SEL_E_INVALID, "program " + std::to_string(i) + " has too many leaves to batch");
     }
