@@ -78,9 +78,10 @@ struct Pass {
   uint32_t bm_words = 0;
 
   // Lookup tables and staged bitmaps, within kBatchBmWords words: first a
-  // table for each narrow column with at least two value-test leaves
-  // (bitmaps and ranges, at most 32), most leaves first; then the bitmaps of
-  // the remaining leaves.  Table leaves move to the front of their column.
+  // table for each narrow column whose value-test leaves (bitmaps and
+  // ranges, at most 32) cost more per row than a lookup, most leaves first;
+  // then the bitmaps of the remaining leaves.  Table leaves move to the
+  // front of their column.
   void finalize() {
     std::vector<PassCol*> order;
     for (PassCol& c : cols) order.push_back(&c);
@@ -102,7 +103,12 @@ struct Pass {
           rest.push_back(L);
         }
       }
-      if (tab.size() < 2) continue;
+      // per row: a table costs a lookup and a 32 x 32 bit transpose (about
+      // 13 vector ops for all its leaves); a direct range test about 3, a
+      // bitmap lookup about 7 per leaf
+      uint32_t direct = 0;
+      for (const DevInstr& L : tab) direct += L.op == D_RANGE ? 3u : 7u;
+      if (direct <= 13) continue;
       if (lo > hi) { lo = 0; hi = 0; }   // every leaf empty: one all-zero entry
       const uint64_t n = (uint64_t)(hi - lo) + 1;
       if (n + 1 > kBatchBmWords - bm_words) continue;

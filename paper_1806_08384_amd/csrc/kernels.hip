@@ -598,9 +598,19 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
     }
   } else if (op == D_RANGE) {
     if constexpr (TY == T_I64) {
+      // one-sided ranges (x >= lo, x <= hi) need one compare per row
+      if ((uint64_t)lo + span == (uint64_t)INT64_MAX) {
 #pragma unroll
-      for (int b = nb - 1; b >= 0; --b)
-        P = (P << 1) + (uint32_t)((uint64_t)seg_get<TY>(r, b) - (uint64_t)lo <= span);
+        for (int b = nb - 1; b >= 0; --b) P = (P << 1) + (uint32_t)(seg_get<TY>(r, b) >= lo);
+      } else if (lo == INT64_MIN) {
+        const int64_t hi = (int64_t)((uint64_t)lo + span);
+#pragma unroll
+        for (int b = nb - 1; b >= 0; --b) P = (P << 1) + (uint32_t)(seg_get<TY>(r, b) <= hi);
+      } else {
+#pragma unroll
+        for (int b = nb - 1; b >= 0; --b)
+          P = (P << 1) + (uint32_t)((uint64_t)seg_get<TY>(r, b) - (uint64_t)lo <= span);
+      }
     } else {
       const uint32_t lo32 = (uint32_t)lo, span32 = (uint32_t)span;
 #pragma unroll
@@ -622,6 +632,30 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
   return P;
 }
 
+// In-register transpose of a 32 x 32 bit matrix: on return a[c] bit r is
+// what a[r] bit c was.  Each stage swaps, in every 2s x 2s block, the s x s
+// block above the diagonal with the one below it.
+template <int S>
+__device__ __forceinline__ void transpose_stage(uint32_t (&a)[32], uint32_t m) {
+#pragma unroll
+  for (int g = 0; g < 32; g += 2 * S) {
+#pragma unroll
+    for (int k = g; k < g + S; ++k) {
+      const uint32_t t = ((a[k] >> S) ^ a[k + S]) & m;
+      a[k + S] ^= t;
+      a[k] ^= t << S;
+    }
+  }
+}
+
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
+  transpose_stage<16>(a, 0x0000FFFFu);
+  transpose_stage<8>(a, 0x00FF00FFu);
+  transpose_stage<4>(a, 0x0F0F0F0Fu);
+  transpose_stage<2>(a, 0x33333333u);
+  transpose_stage<1>(a, 0x55555555u);
+}
+
 // Every leaf of one segment; truth words go to the wave's slots.  An int64
 // column's upper half (h = 0) writes bits 16..31, its lower half completes
 // them.  Sparse value lists take the element path once, with the last
@@ -631,31 +665,9 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
                                            CInstr leaves, uint64_t tb, uint32_t lane,
                                            uint32_t* wl, const uint32_t* bmlds) {
   const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
-  uint32_t k0 = 0;
-  if constexpr (TY != T_I64) {
-    const uint32_t tw = C->tab_word;
-    if (tw != kNoLds) {
-      // one table lookup per row serves every table leaf of the column;
-      // leaf i's word is bit i of the 32 looked-up entries
-      const uint32_t* tab = bmlds + tw;
-      const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n;
-      uint32_t T[32];
-#pragma unroll
-      for (int b = 0; b < 32; ++b) {
-        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
-        T[b] = tab[d < n ? d : n];
-      }
-      const uint32_t m = C->tab_count;
-      for (uint32_t i = 0; i < m; ++i) {
-        uint32_t P = 0;
-#pragma unroll
-        for (int b = 31; b >= 0; --b) P = (P << 1) + ((T[b] >> i) & 1u);
-        wl[leaves[lb + i].slot * kWave + lane] = P;
-      }
-      k0 = m;
-    }
-  }
-  for (uint32_t k = k0; k < ln; ++k) {
+  const uint32_t tw = TY != T_I64 ? C->tab_word : kNoLds;
+  // leaves outside the table first: the values die once the table is read
+  for (uint32_t k = tw != kNoLds ? C->tab_count : 0u; k < ln; ++k) {
     CInstr I = leaves + lb + k;
     const uint32_t op = I->op;
     uint32_t* w = wl + I->slot * kWave + lane;
@@ -666,6 +678,26 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
     const uint32_t P = seg_leaf<TY>(r, op, I, bmlds);
     if (TY != T_I64 || h == 0) *w = P;
     else *w = (*w << 16) | P;
+  }
+  if constexpr (TY != T_I64) {
+    if (tw != kNoLds) {
+      // one table lookup per row serves every table leaf of the column
+      const uint32_t* tab = bmlds + tw;
+      const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n;
+      uint32_t T[32];
+#pragma unroll
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+        T[b] = tab[d < n ? d : n];
+      }
+      // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf
+      // i's word (bit b = row b)
+      transpose32(T);
+      const uint32_t m = C->tab_count;
+#pragma unroll
+      for (int i = 0; i < 32; ++i)
+        if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+    }
   }
 }
 

@@ -108,16 +108,18 @@ struct CompactArgs {
 // an LDS slot of its own; then each program's combinators run over the
 // slots.  A column is thus read from HBM once per entry, however many
 // programs and leaves use it.
-constexpr uint32_t kBatchSlots = 32;      // LDS slots per wave (256 B each) that
-                                          // passes are packed to; 3 workgroups per CU
+constexpr uint32_t kBatchSlots = 48;      // LDS slots per wave (256 B each) that
+                                          // passes are packed to
 constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
                                           // and 32 validity words
 constexpr uint32_t kNoSlot = 0xFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
 // leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
-// most this many words per workgroup in all.
-constexpr uint32_t kBatchBmWords = 4096;
+// most this many words per workgroup in all.  With 48 slots per wave, a
+// 256-thread workgroup holds at most 48 + 32 + 4 (counters) KB of LDS: two
+// workgroups (eight waves, two per SIMD) share a CU.
+constexpr uint32_t kBatchBmWords = 8192;
 constexpr uint32_t kNoLds = 0xFFFFFFFFu;
 // Entry tile ranges are padded to a multiple of this, so that the waves of
 // one workgroup (1, 2 or 4) always work on the same entry.
