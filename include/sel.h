@@ -308,9 +308,10 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
  * count per (table, program), Ch.3 sec.3.1) and optionally one push-down
  * with materialisation (Algorithm 1's Execute: count, limit check, ascending
  * row ids).  Count queries are served by cooperative scans: each table with
- * pending programs is cut into chunks of chunk_rows rows, and a round is one
- * batched launch over the current chunk of every such table for every
- * program attached to it.  A program attaches at the next round and is done
+ * pending programs is cut into rounds_per_cycle chunks (fewer if a chunk
+ * would exceed chunk_rows rows), and a round is one batched launch over the
+ * current chunk of every such table for every program attached to it, so
+ * every table completes a cycle in the same number of rounds.  A program attaches at the next round and is done
  * after one revolution over its table, so requests arriving while others are
  * on the GPU share their scans.  A request is admitted (FIFO) when its
  * device footprint (accumulators, program code, and for a push-down the
@@ -323,9 +324,11 @@ typedef struct sel_server sel_server;
 
 typedef struct sel_server_config {
   uint64_t hbm_budget_bytes;   /* device bytes admitted requests may hold (0 = 1 GiB) */
-  uint64_t chunk_rows;         /* rows per cooperative-scan chunk (0 = 2^26) */
+  uint64_t chunk_rows;         /* most rows per cooperative-scan chunk (0 = no cap) */
   uint32_t max_programs;       /* programs in flight (<= 4096; 0 = 4096) */
   uint32_t rounds_in_flight;   /* rounds queued on the device (1..4; 0 = 2) */
+  uint32_t rounds_per_cycle;   /* chunks per table (0 = 8) */
+  uint32_t pad;
 } sel_server_config;
 
 typedef struct sel_request {

@@ -21,8 +21,12 @@ struct sel_batch {
   std::vector<const sel_table*> tabs;         // per caller index
   std::vector<const sel_program*> slot_prog;  // per caller index
   BatchPlan plan;
-  void* dev = nullptr;                        // descriptors | acc | out | slot
-  size_t desc_cap = 0;
+  void* dev = nullptr;                        // descriptors | acc | out | slot | tables
+  size_t desc_cap = 0, gtab_cap = 0;
+  uint32_t* d_gtab = nullptr;
+  const TableBuild* d_builds = nullptr;       // as captured
+  uint32_t nbuilds = 0;
+  uint64_t table_entries = 0;
   unsigned long long* d_acc = nullptr;
   unsigned long long* d_out = nullptr;
   DevSlot* d_slot = nullptr;
@@ -115,9 +119,10 @@ void place_tail(char* base, size_t desc_cap, uint32_t n, unsigned long long*& ac
 }
 
 // Writes the plan's descriptors to `dev` in stream order and fills `a`.
-sel_status upload_plan(sel_ctx* ctx, const BatchPlan& bp, char* dev, BatchArgs& a) {
+sel_status upload_plan(sel_ctx* ctx, const BatchPlan& bp, char* dev, uint32_t* gtab, BatchArgs& a,
+                       const TableBuild** d_builds) {
   std::vector<uint8_t> host(bp.bytes());
-  bp.write(host.data(), dev, a);
+  bp.write(host.data(), dev, gtab, a, d_builds);
   return stage_copy(ctx, dev, host.data(), host.size());
 }
 
@@ -143,7 +148,7 @@ sel_status capture(sel_batch* b) {
   const char* where = "";
   do {
     if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) { where = "hipStreamBeginCapture"; break; }
-    int le = sel_launch_batch(b->args, b->grid, b->block, b->lds, b->stream);
+    int le = b->plan.launch(b->args, b->d_builds, b->grid, b->block, b->stream);
     hipError_t ce = hipMemcpyAsync(b->h_out, b->d_out, (size_t)b->n * 8, hipMemcpyDeviceToHost, b->stream);
     e = hipStreamEndCapture(b->stream, &b->graph);
     if (le) { e = (hipError_t)le; where = "batch launch (capture)"; break; }
@@ -163,21 +168,26 @@ sel_status rebuild(sel_batch* b) {
   sel_status st = plan_batch(ctx, b->n, b->tabs.data(), b->slot_prog.data(), b->plan);
   if (st != SEL_OK) return st;
   const size_t need = up256(b->plan.bytes());
-  if (need > b->desc_cap) {
+  const size_t need_gtab = up256(b->plan.gtab_words * 4);
+  if (need > b->desc_cap || need_gtab > b->gtab_cap) {
     if (b->dev) {
       (void)hipStreamSynchronize(b->stream);
       (void)hipStreamSynchronize(ctx->stream);
       (void)hipFree(b->dev);
       b->dev = nullptr;
     }
-    const size_t cap = up256(need * 2);
-    HIP_TRY(ctx, hipMalloc(&b->dev, cap + tail_bytes(b->n)), "hipMalloc(batch)");
-    HIP_TRY(ctx, hipMemsetAsync(b->dev, 0, cap + tail_bytes(b->n), ctx->stream), "hipMemsetAsync(batch)");
+    const size_t cap = up256(need * 2), gcap = up256(need_gtab * 2);
+    const size_t total = cap + tail_bytes(b->n) + gcap;
+    HIP_TRY(ctx, hipMalloc(&b->dev, total), "hipMalloc(batch)");
+    HIP_TRY(ctx, hipMemsetAsync(b->dev, 0, total, ctx->stream), "hipMemsetAsync(batch)");
     b->desc_cap = cap;
+    b->gtab_cap = gcap;
     place_tail((char*)b->dev, cap, b->n, b->d_acc, b->d_out, b->d_slot);
+    b->d_gtab = (uint32_t*)((char*)b->dev + cap + tail_bytes(b->n));
   }
   BatchArgs a{};
-  st = upload_plan(ctx, b->plan, (char*)b->dev, a);
+  const TableBuild* d_builds = nullptr;
+  st = upload_plan(ctx, b->plan, (char*)b->dev, b->d_gtab, a, &d_builds);
   if (st != SEL_OK) return st;
   a.acc = b->d_acc;
   a.done = nullptr;
@@ -187,13 +197,18 @@ sel_status rebuild(sel_batch* b) {
   uint32_t grid, block;
   batch_shape(ctx, b->n, b->plan, grid, block);
   const uint32_t lds = b->plan.lds_bytes(block);
+  const uint32_t nbuilds = (uint32_t)b->plan.builds.size();
   if (b->exec && std::memcmp(&a, &b->args, sizeof a) == 0 && grid == b->grid && block == b->block &&
-      lds == b->lds)
+      lds == b->lds && d_builds == b->d_builds && nbuilds == b->nbuilds &&
+      b->plan.table_entries == b->table_entries)
     return SEL_OK;
   b->args = a;
   b->grid = grid;
   b->block = block;
   b->lds = lds;
+  b->d_builds = d_builds;
+  b->nbuilds = nbuilds;
+  b->table_entries = b->plan.table_entries;
   // the capture stream must see the uploads before its first replay
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
   return capture(b);
@@ -213,7 +228,7 @@ sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tab
   // workspace in the context's batch area: descriptors, then accumulators,
   // counts and the slot
   const size_t desc = up256(bp.bytes());
-  const size_t bytes = desc + tail_bytes(n);
+  const size_t bytes = desc + tail_bytes(n) + up256(bp.gtab_words * 4);
   if (bytes > ctx->batch_bytes) {
     if (ctx->batch_mem) {
       (void)hipStreamSynchronize(ctx->stream);
@@ -234,7 +249,8 @@ sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tab
   // the accumulators move with the descriptor size: clear this call's lines
   int e = sel_launch_fill((uint32_t*)acc, (size_t)n * kBatchAccStride * 2, 0u, ctx->stream);
   if (e) return hip_err(ctx, (hipError_t)e, "accumulator clear");
-  st = upload_plan(ctx, bp, base, a);
+  const TableBuild* d_builds = nullptr;
+  st = upload_plan(ctx, bp, base, (uint32_t*)(base + desc + tail_bytes(n)), a, &d_builds);
   if (st != SEL_OK) return st;
   a.acc = acc;
   a.done = nullptr;
@@ -245,7 +261,7 @@ sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tab
   batch_shape(ctx, n, bp, grid, block);
   {
     TimedLaunch tl(ctx, SEL_K_BATCH);
-    e = sel_launch_batch(a, grid, block, bp.lds_bytes(block), ctx->stream);
+    e = bp.launch(a, d_builds, grid, block, ctx->stream);
     tl.done();
   }
   if (e) return hip_err(ctx, (hipError_t)e, "batch launch");

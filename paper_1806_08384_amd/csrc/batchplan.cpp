@@ -36,7 +36,55 @@ struct PassCol {
   std::vector<DevInstr> leaves;
   uint32_t tab_word = kNoLds, tab_count = 0, tab_n = 0;
   int32_t tab_lo = 0;
+  bool gtab = false;                 // table in device memory instead of LDS
+  bool tab_guarded = false;          // ... read only where a leaf's guard holds
 };
+
+// A device-memory table pays when it stays in L2 (4 MB per XCD): past this
+// many entries, random lookups into it miss and each costs an HBM burst,
+// while separate (guarded) bitmaps of the same leaves are 32 times smaller.
+constexpr uint64_t kMaxDeviceTable = 1ull << 19;   // entries (2 MB)
+// A table read only where guards hold may be larger: few rows reach it.
+constexpr uint64_t kMaxGuardedDeviceTable = 1ull << 23;   // entries (32 MB)
+
+// Instruction indices of the value-test leaves on columns without NULLs that
+// are top-level factors of the program's conjunction (the program is
+// FALSE wherever one of them is).
+std::vector<size_t> and_factor_leaves(const std::vector<DevInstr>& code) {
+  struct Node { uint32_t op; size_t idx; int a, b; };
+  std::vector<Node> nodes;
+  std::vector<int> st;
+  for (size_t k = 0; k < code.size(); ++k) {
+    const uint32_t op = code[k].op;
+    if (op == D_AND || op == D_OR) {
+      if (st.size() < 2) return {};
+      const int b = st.back(); st.pop_back();
+      const int a = st.back(); st.pop_back();
+      nodes.push_back(Node{op, k, a, b});
+    } else if (op == D_NOT || op == D_ISUNK) {
+      if (st.empty()) return {};
+      const int a = st.back(); st.pop_back();
+      nodes.push_back(Node{op, k, a, -1});
+    } else {
+      nodes.push_back(Node{op, k, -1, -1});
+    }
+    st.push_back((int)nodes.size() - 1);
+  }
+  std::vector<size_t> out;
+  if (st.size() != 1) return out;
+  std::vector<int> todo{st.back()};
+  while (!todo.empty()) {
+    const Node& n = nodes[todo.back()];
+    todo.pop_back();
+    if (n.op == D_AND) {
+      todo.push_back(n.a);
+      todo.push_back(n.b);
+    } else if (is_value_test(n.op) && code[n.idx].valid == nullptr) {
+      out.push_back(n.idx);
+    }
+  }
+  return out;
+}
 
 void type_range(uint32_t t, int64_t& lo, int64_t& hi) {
   switch (t) {
@@ -73,6 +121,8 @@ struct Pass {
   std::map<const uint32_t*, uint32_t> valid_slot;
   std::vector<std::pair<std::vector<uint32_t>, uint32_t>> progs;  // (ops, acc line)
   uint32_t slots = 0;
+  std::vector<std::vector<uint32_t>> factors;   // per program: slots of its AND factors
+  std::map<uint32_t, uint32_t> slot_uses;       // leaf slot -> references
   std::vector<BatchBitmap> bms;             // staged in LDS
   std::map<const void*, uint32_t> bm_at;    // source -> its BatchBitmap
   uint32_t bm_words = 0;
@@ -83,12 +133,17 @@ struct Pass {
   // then the bitmaps of the remaining leaves.  Table leaves move to the
   // front of their column.
   void finalize() {
+    set_guards();
     std::vector<PassCol*> order;
     for (PassCol& c : cols) order.push_back(&c);
     std::stable_sort(order.begin(), order.end(),
                      [](const PassCol* a, const PassCol* b) { return a->leaves.size() > b->leaves.size(); });
+    // two rounds: LDS tables within the budget, then device-memory tables
+    // for the columns left (one lookup served from L2 instead of one per
+    // leaf: for dimension bitmaps too large for LDS)
+    for (int round = 0; round < 2; ++round)
     for (PassCol* c : order) {
-      if (c->type == T_I64) continue;
+      if (c->type == T_I64 || c->tab_word != kNoLds || c->gtab) continue;
       std::vector<DevInstr> tab, rest;
       int64_t lo = INT64_MAX, hi = INT64_MIN;
       for (const DevInstr& L : c->leaves) {
@@ -111,17 +166,27 @@ struct Pass {
       if (direct <= 13) continue;
       if (lo > hi) { lo = 0; hi = 0; }   // every leaf empty: one all-zero entry
       const uint64_t n = (uint64_t)(hi - lo) + 1;
-      if (n + 1 > kBatchBmWords - bm_words) continue;
-      c->tab_word = bm_words;
+      // a device table whose every leaf is guarded is read only on rows some
+      // leaf needs; the other rows all read its zero entry
+      bool guarded = true;
+      for (const DevInstr& L : tab) guarded &= L.flags != kNoGuard;
+      if (round == 0) {
+        if (n + 1 > kBatchBmWords - bm_words) continue;
+        c->tab_word = bm_words;
+        bm_words += (uint32_t)n + 1;
+      } else {
+        if (n > (guarded ? kMaxGuardedDeviceTable : kMaxDeviceTable)) continue;
+        c->gtab = true;
+        c->tab_guarded = guarded;
+      }
       c->tab_count = (uint32_t)tab.size();
       c->tab_lo = (int32_t)lo;
       c->tab_n = (uint32_t)n;
-      bm_words += (uint32_t)n + 1;
       c->leaves = tab;
       c->leaves.insert(c->leaves.end(), rest.begin(), rest.end());
     }
     for (PassCol& c : cols) {
-      const size_t first = c.tab_word != kNoLds ? c.tab_count : 0;
+      const size_t first = c.tab_word != kNoLds || c.gtab ? c.tab_count : 0;
       for (size_t k = first; k < c.leaves.size(); ++k) stage(c.leaves[k]);
     }
   }
@@ -191,7 +256,10 @@ struct Pass {
   void add(const sel_program* p, uint32_t acc) {
     std::vector<uint32_t> ops;
     ops.reserve(p->host_code.size());
-    for (const DevInstr& I : p->host_code) {
+    const std::vector<size_t> fidx = and_factor_leaves(p->host_code);
+    std::vector<uint32_t> fslots;
+    for (size_t pc = 0; pc < p->host_code.size(); ++pc) {
+      const DevInstr& I = p->host_code[pc];
       const uint32_t op = I.op;
       if (is_value_test(op)) {
         const LeafKey k = key_of(I);
@@ -212,11 +280,13 @@ struct Pass {
             home->type = I.type;
           }
           DevInstr L = I;
-          L.flags = 0;
+          L.flags = kNoGuard;
           L.slot = s;
           L.lds_word = kNoLds;
           home->leaves.push_back(L);
         }
+        slot_uses[s] += 1;
+        if (std::find(fidx.begin(), fidx.end(), pc) != fidx.end()) fslots.push_back(s);
         ops.push_back(batch_op(D_RANGE, s, vslot_of(I)));
       } else if (is_null_test(op)) {
         ops.push_back(batch_op(op, 0, vslot_of(I)));
@@ -238,6 +308,33 @@ struct Pass {
       }
     }
     progs.emplace_back(std::move(fused), acc);
+    factors.push_back(std::move(fslots));
+  }
+
+  // Guards: a bitmap leaf that only one program uses, as a factor of its
+  // conjunction, need not look up rows where a factor on an earlier column
+  // is already FALSE (the program is FALSE there whatever the leaf says);
+  // those rows read word 0 instead, so the gather collapses.
+  void set_guards() {
+    std::map<uint32_t, std::pair<size_t, size_t>> where;   // slot -> (column, leaf)
+    for (size_t c = 0; c < cols.size(); ++c)
+      for (size_t k = 0; k < cols[c].leaves.size(); ++k) where[cols[c].leaves[k].slot] = {c, k};
+    for (const std::vector<uint32_t>& f : factors) {
+      for (uint32_t s : f) {
+        if (slot_uses[s] != 1) continue;
+        const auto ws = where.at(s);
+        DevInstr& L = cols[ws.first].leaves[ws.second];
+        if (L.op != D_BITMAP) continue;
+        uint32_t g = kNoGuard;
+        int n = 0;
+        for (uint32_t t : f) {
+          if (t == s || n == 4 || where.at(t).first >= ws.first) continue;
+          g = (g & ~(0xFFu << (8 * n))) | (t << (8 * n));
+          ++n;
+        }
+        L.flags = g;
+      }
+    }
   }
 };
 
@@ -252,6 +349,10 @@ void BatchPlan::clear() {
   progs.clear();
   ops.clear();
   bms.clear();
+  col_gtab.clear();
+  builds.clear();
+  gtab_words = 0;
+  table_entries = 0;
   total_tiles = 0;
   max_slots = 0;
   max_bm_words = 0;
@@ -288,6 +389,21 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
       bc.tab_count = c.tab_count;
       bc.tab_lo = c.tab_lo;
       bc.tab_n = c.tab_n;
+      bc.tab_guarded = c.tab_guarded ? 1u : 0u;
+      col_gtab.push_back(~0ull);
+      if (c.gtab) {
+        TableBuild tbd{};
+        tbd.dst = (uint32_t*)(uintptr_t)gtab_words;          // offset until written
+        tbd.leaves = (const DevInstr*)(uintptr_t)bc.leaf_begin;  // index until written
+        tbd.lo = c.tab_lo;
+        tbd.n = c.tab_n;
+        tbd.entry_begin = table_entries;
+        tbd.m = c.tab_count;
+        builds.push_back(tbd);
+        col_gtab.back() = gtab_words;
+        table_entries += (uint64_t)c.tab_n + 1;
+        gtab_words += ((uint64_t)c.tab_n + 1 + 63) & ~63ull;   // 256-byte aligned tables
+      }
       e.ntab += c.tab_word != kNoLds ? 1u : 0u;
       leaves.insert(leaves.end(), c.leaves.begin(), c.leaves.end());
       cols.push_back(bc);
@@ -327,18 +443,32 @@ size_t BatchPlan::bytes() const {
   o = up(o + leaves.size() * sizeof(DevInstr));
   o = up(o + progs.size() * sizeof(BatchProg));
   o = up(o + ops.size() * sizeof(uint32_t));
-  return up(o + bms.size() * sizeof(BatchBitmap));
+  o = up(o + bms.size() * sizeof(BatchBitmap));
+  return up(o + builds.size() * sizeof(TableBuild));
 }
 
-void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
+void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a,
+                      const TableBuild** d_builds) const {
   const size_t o_cols = up(entries.size() * sizeof(BatchTable));
   const size_t o_leaves = up(o_cols + cols.size() * sizeof(BatchCol));
   const size_t o_progs = up(o_leaves + leaves.size() * sizeof(DevInstr));
   const size_t o_ops = up(o_progs + progs.size() * sizeof(BatchProg));
   const size_t o_bms = up(o_ops + ops.size() * sizeof(uint32_t));
+  const size_t o_builds = up(o_bms + bms.size() * sizeof(BatchBitmap));
   std::memset(host, 0, bytes());
   if (!entries.empty()) std::memcpy(host, entries.data(), entries.size() * sizeof(BatchTable));
-  if (!cols.empty()) std::memcpy(host + o_cols, cols.data(), cols.size() * sizeof(BatchCol));
+  BatchCol* hc = (BatchCol*)(host + o_cols);
+  for (size_t k = 0; k < cols.size(); ++k) {
+    hc[k] = cols[k];
+    hc[k].gtab = col_gtab[k] == ~0ull ? nullptr : gtab_dev + col_gtab[k];
+  }
+  TableBuild* hb = (TableBuild*)(host + o_builds);
+  for (size_t k = 0; k < builds.size(); ++k) {
+    hb[k] = builds[k];
+    hb[k].dst = gtab_dev + (uintptr_t)builds[k].dst;
+    hb[k].leaves = (const DevInstr*)(dev + o_leaves) + (uintptr_t)builds[k].leaves;
+  }
+  if (d_builds) *d_builds = (const TableBuild*)(dev + o_builds);
   if (!leaves.empty()) std::memcpy(host + o_leaves, leaves.data(), leaves.size() * sizeof(DevInstr));
   BatchProg* hp = (BatchProg*)(host + o_progs);
   for (size_t k = 0; k < progs.size(); ++k) {
@@ -357,6 +487,16 @@ void BatchPlan::write(uint8_t* host, char* dev, BatchArgs& a) const {
   a.total_tiles = total_tiles;
   a.slot_words = max_slots * (uint32_t)kWave;
   a.bm_words = max_bm_words;
+  a.acc_words = acc_words();
+}
+
+int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t grid, uint32_t block,
+                      void* stream) const {
+  if (!builds.empty()) {
+    const int e = sel_launch_tables(d_builds, (uint32_t)builds.size(), table_entries, stream);
+    if (e) return e;
+  }
+  return sel_launch_batch(a, grid, block, lds_bytes(block), stream);
 }
 
 }  // namespace selrt

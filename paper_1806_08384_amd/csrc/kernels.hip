@@ -358,6 +358,13 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t W = (uint64_t)gridDim.x * nw;
   uint32_t cnt = 0, oor = 0;
+  // M_MASK: result words of the last 8 tiles, written together with
+  // nontemporal stores (fewer, fuller store bursts interleaved with the loads)
+  uint32_t pend[8];
+  uint64_t ptile[8];
+  int np = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) { pend[k] = 0; ptile[k] = 0; }
   for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
     const uint64_t tb = tile * kTileRows;
     uint32_t T;
@@ -368,7 +375,15 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
     }
     cnt += __builtin_popcount(T);
     if constexpr (MODE == M_MASK) {
-      a.mask[tile * kWave + lane] = T;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (k == np) { pend[k] = T; ptile[k] = tile; }
+      ++np;
+      if (np == 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(pend[k], &a.mask[ptile[k] * kWave + lane]);
+        np = 0;
+      }
       const uint32_t tc = wave_sum(__builtin_popcount(T));
       if (lane == 0) a.tile_counts[tile] = tc;
     } else if constexpr (MODE == M_KEYBITMAP) {
@@ -384,6 +399,11 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
         else ++oor;
       }
     }
+  }
+  if constexpr (MODE == M_MASK) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < np) __builtin_nontemporal_store(pend[k], &a.mask[ptile[k] * kWave + lane]);
   }
   finish(a.slot, a.out, cnt, oor, MODE == M_KEYBITMAP);
 }
@@ -564,11 +584,14 @@ __device__ __forceinline__ void seg_issue(Seg& r, uint32_t& V, const CONSTANT Ba
 }
 
 // Value tests of one leaf on a segment: bits [0, nb) of the result, highest
-// row first.  No guard: batched evaluation tests every row (a guard only
-// saves lookups).
+// row first.  A bitmap leaf in global memory may carry a guard (slots of
+// factors on earlier columns): rows outside it read word 0 and test FALSE.
+// `gshift` places the segment's rows in the guard word (16 for the upper
+// half of an int64 column).
 template <int TY>
 __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I,
-                                             const uint32_t* bmlds) {
+                                             const uint32_t* bmlds, const uint32_t* wl,
+                                             uint32_t lane, int gshift) {
   constexpr int nb = TY == T_I64 ? 16 : 32;
   const int64_t lo = I->lo;
   const uint64_t span = I->span;
@@ -619,12 +642,22 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
     }
   } else {  // D_BITMAP in global memory
     const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
+    uint32_t need = ~0u;
+    const uint32_t gd = I->flags;
+    if (gd != kNoGuard) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t gs = (gd >> (8 * k)) & 0xFFu;
+        if (gs != 0xFFu) need &= wl[gs * kWave + lane];
+      }
+      need >>= gshift;
+    }
 #pragma unroll
     for (int b = nb - 1; b >= 0; --b) {
       uint64_t d;
       if constexpr (TY == T_I64) d = (uint64_t)seg_get<TY>(r, b) - (uint64_t)lo;
       else d = (uint64_t)((int64_t)seg_get<TY>(r, b) - lo);
-      const bool ok = d < span;
+      const bool ok = d < span && ((need >> b) & 1u);
       const uint32_t k = ok ? (uint32_t)d : 0u;
       P = (P << 1) + (ok & ((bits[k >> 5] >> (k & 31)) & 1u));
     }
@@ -666,8 +699,9 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
                                            uint32_t* wl, const uint32_t* bmlds) {
   const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
   const uint32_t tw = TY != T_I64 ? C->tab_word : kNoLds;
+  const bool tabled = TY != T_I64 && (tw != kNoLds || C->gtab != nullptr);
   // leaves outside the table first: the values die once the table is read
-  for (uint32_t k = tw != kNoLds ? C->tab_count : 0u; k < ln; ++k) {
+  for (uint32_t k = tabled ? C->tab_count : 0u; k < ln; ++k) {
     CInstr I = leaves + lb + k;
     const uint32_t op = I->op;
     uint32_t* w = wl + I->slot * kWave + lane;
@@ -675,20 +709,45 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
       if (TY != T_I64 || h == 1) *w = leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u);
       continue;
     }
-    const uint32_t P = seg_leaf<TY>(r, op, I, bmlds);
+    const uint32_t P = seg_leaf<TY>(r, op, I, bmlds, wl, lane, TY == T_I64 && h == 0 ? 16 : 0);
     if (TY != T_I64 || h == 0) *w = P;
     else *w = (*w << 16) | P;
   }
   if constexpr (TY != T_I64) {
-    if (tw != kNoLds) {
+    const GLOBAL uint32_t* gtab = gptr<uint32_t>(C->gtab);
+    if (tw != kNoLds || gtab != nullptr) {
       // one table lookup per row serves every table leaf of the column
-      const uint32_t* tab = bmlds + tw;
       const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n;
       uint32_t T[32];
+      if (tw != kNoLds) {
+        const uint32_t* tab = bmlds + tw;
 #pragma unroll
-      for (int b = 0; b < 32; ++b) {
-        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
-        T[b] = tab[d < n ? d : n];
+        for (int b = 0; b < 32; ++b) {
+          const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+          T[b] = tab[d < n ? d : n];
+        }
+      } else {
+        uint32_t need = ~0u;
+        if (C->tab_guarded) {
+          // rows some table leaf needs: the union of the leaves' guards
+          need = 0;
+          const uint32_t m = C->tab_count;
+          for (uint32_t i = 0; i < m; ++i) {
+            const uint32_t gd = leaves[lb + i].flags;
+            uint32_t g = ~0u;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const uint32_t gs = (gd >> (8 * k)) & 0xFFu;
+              if (gs != 0xFFu) g &= wl[gs * kWave + lane];
+            }
+            need |= g;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < 32; ++b) {
+          const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+          T[b] = gtab[d < n && ((need >> b) & 1u) ? d : n];
+        }
       }
       // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf
       // i's word (bit b = row b)
@@ -835,13 +894,15 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
 // chunks of tables (row_begin), and lines not finished by this launch keep
 // accumulating: a cooperative scan adds one chunk per launch.
 __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
-  __shared__ uint32_t acc[kBatchMaxProgs];
-  extern __shared__ uint32_t dyn[];   // staged bitmaps, then each wave's slots
+  // LDS: per-program counters, tables and staged bitmaps, each wave's slots
+  extern __shared__ uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
-  uint32_t* bmlds = dyn;
-  uint32_t* wl = dyn + a.bm_words + wave * a.slot_words;
-  for (uint32_t p = threadIdx.x; p < (uint32_t)kBatchMaxProgs; p += blockDim.x) acc[p] = 0;
+  const uint32_t nacc = a.acc_words;   // min(nprogs, kBatchMaxProgs)
+  uint32_t* acc = dyn;
+  uint32_t* bmlds = dyn + nacc;
+  uint32_t* wl = bmlds + a.bm_words + wave * a.slot_words;
+  for (uint32_t p = threadIdx.x; p < nacc; p += blockDim.x) acc[p] = 0;
   __syncthreads();
   const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
   const CONSTANT BatchCol* cols = (const CONSTANT BatchCol*)a.cols;
@@ -924,7 +985,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
       const uint32_t T = run_ops((const CONSTANT uint32_t*)P->ops, P->nops, wl, lane) & inr;
       const uint32_t c = wave_sum(__builtin_popcount(T));
       if (lane == 0 && c) {
-        if (pb + k < (uint32_t)kBatchMaxProgs) {
+        if (pb + k < nacc) {
           atomicAdd(&acc[pb + k], c);
         } else {  // beyond the LDS table: straight to the accumulator line
           atomicAdd(&a.acc[(uint64_t)P->acc_index * kBatchAccStride], (unsigned long long)c);
@@ -933,8 +994,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
     }
   }
   __syncthreads();
-  const uint32_t nlds = a.nprogs < (uint32_t)kBatchMaxProgs ? a.nprogs : (uint32_t)kBatchMaxProgs;
-  for (uint32_t p = threadIdx.x; p < nlds; p += blockDim.x)
+  for (uint32_t p = threadIdx.x; p < nacc; p += blockDim.x)
     if (acc[p]) atomicAdd(&a.acc[(uint64_t)progs[p].acc_index * kBatchAccStride], (unsigned long long)acc[p]);
   __threadfence();
   __syncthreads();
@@ -953,6 +1013,39 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) atomicExch(&a.slot->ticket, 0u);
+  }
+}
+
+// Device-memory lookup tables of a batch (one thread per entry; the bitmap
+// words of neighbouring entries are shared, so the reads coalesce).
+__global__ void __launch_bounds__(256) k_tables(const TableBuild* __restrict__ tb, uint32_t nb,
+                                                uint64_t nentries) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nentries; e += stride) {
+    uint32_t lo = 0, hi = nb;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tb[mid].entry_begin <= e) lo = mid; else hi = mid;
+    }
+    const TableBuild& B = tb[lo];
+    const uint64_t i = e - B.entry_begin;
+    uint32_t w = 0;
+    if (i < B.n) {
+      const int64_t x = B.lo + (int64_t)i;
+      for (uint32_t k = 0; k < B.m; ++k) {
+        const DevInstr& I = B.leaves[k];
+        const uint64_t d = (uint64_t)x - (uint64_t)I.lo;
+        uint32_t bit;
+        if (I.op == D_RANGE) {
+          bit = d <= I.span;
+        } else {  // D_BITMAP
+          const uint32_t* bits = (const uint32_t*)I.aux;
+          bit = d < I.span ? (bits[d >> 5] >> (d & 31)) & 1u : 0u;
+        }
+        w |= bit << k;
+      }
+    }
+    B.dst[i] = w;
   }
 }
 
@@ -987,6 +1080,15 @@ int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* c
 
 int sel_launch_compact(const CompactArgs& a, uint32_t grid, uint32_t block, void* stream) {
   hipLaunchKernelGGL(k_compact, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int sel_launch_tables(const TableBuild* d_builds, uint32_t nbuilds, uint64_t nentries, void* stream) {
+  if (nbuilds == 0 || nentries == 0) return 0;
+  uint64_t blocks = (nentries + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_tables, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, d_builds,
+                     nbuilds, nentries);
   return (int)hipGetLastError();
 }
 

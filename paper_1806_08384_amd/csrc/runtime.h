@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -185,6 +186,10 @@ struct BatchPlan {
   std::vector<sel::BatchProg> progs;   // ops holds an index into `ops` until written
   std::vector<uint32_t> ops;
   std::vector<sel::BatchBitmap> bms;
+  std::vector<uint64_t> col_gtab;        // per column: word offset of its device table, or ~0
+  std::vector<sel::TableBuild> builds;   // dst / leaves hold offsets until written
+  uint64_t gtab_words = 0;               // device-memory tables, in words
+  uint64_t table_entries = 0;            // entries k_tables writes
   uint64_t total_tiles = 0;
   uint32_t max_slots = 0;
   uint32_t max_bm_words = 0;
@@ -195,10 +200,19 @@ struct BatchPlan {
            const sel_program* const* progs, const uint32_t* acc, uint32_t n);
   size_t bytes() const;
   // Image of the descriptors for device address `dev` into `host` (bytes()
-  // long); sets the descriptor pointers and counts of `a`.
-  void write(uint8_t* host, char* dev, sel::BatchArgs& a) const;
+  // long), with the device tables at gtab_dev (gtab_words words); sets the
+  // descriptor pointers and counts of `a` and the device address of the
+  // table builds.
+  void write(uint8_t* host, char* dev, uint32_t* gtab_dev, sel::BatchArgs& a,
+             const sel::TableBuild** d_builds) const;
+  // Enqueue the table builds (if any) and the batch kernel.
+  int launch(const sel::BatchArgs& a, const sel::TableBuild* d_builds, uint32_t grid,
+             uint32_t block, void* stream) const;
+  uint32_t acc_words() const {
+    return (uint32_t)std::min<size_t>(progs.size(), (size_t)sel::kBatchMaxProgs);
+  }
   uint32_t lds_bytes(uint32_t block) const {
-    return 4u * max_bm_words + max_slots * 256u * (block / 64);
+    return 4u * (acc_words() + max_bm_words) + max_slots * 256u * (block / 64);
   }
 };
 

@@ -113,13 +113,17 @@ constexpr uint32_t kBatchSlots = 48;      // LDS slots per wave (256 B each) tha
 constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
                                           // and 32 validity words
 constexpr uint32_t kNoSlot = 0xFFFu;
+// Batched leaves reuse DevInstr::flags as a guard: up to four slots, one
+// per byte (0xFF = none), whose words AND to the rows that need a lookup.
+constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
 // leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
 // most this many words per workgroup in all.  With 48 slots per wave, a
-// 256-thread workgroup holds at most 48 + 32 + 4 (counters) KB of LDS: two
-// workgroups (eight waves, two per SIMD) share a CU.
-constexpr uint32_t kBatchBmWords = 8192;
+// 256-thread workgroup of a batch of up to 256 programs holds at most
+// 48 + 31 + 1 (counters) = 80 KB of LDS: two workgroups (eight waves, two
+// per SIMD) share a CU.
+constexpr uint32_t kBatchBmWords = 7936;
 constexpr uint32_t kNoLds = 0xFFFFFFFFu;
 // Entry tile ranges are padded to a multiple of this, so that the waves of
 // one workgroup (1, 2 or 4) always work on the same entry.
@@ -162,7 +166,7 @@ struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS
   uint32_t pad;
 };
 
-struct BatchCol {              // 48 bytes: a column one entry reads
+struct BatchCol {              // 64 bytes: a column one entry reads
   const void* data;
   const uint32_t* valid;       // nullptr: no NULLs
   uint32_t type;               // DevType
@@ -170,12 +174,30 @@ struct BatchCol {              // 48 bytes: a column one entry reads
   uint32_t leaf_begin;         // its leaf tests: DevInstr array, slot field set
   uint32_t leaf_count;
   // Lookup table (narrow columns): its first tab_count leaves are bits
-  // 0 .. tab_count-1 of word min(x - tab_lo, tab_n) at LDS offset tab_word;
-  // word tab_n is zero.  tab_word == kNoLds: no table.
+  // 0 .. tab_count-1 of word min(x - tab_lo, tab_n), at LDS offset tab_word
+  // or, for a table too large for LDS, in device memory at gtab; word tab_n
+  // is zero.  tab_word == kNoLds and gtab == nullptr: no table.
   uint32_t tab_word;
   uint32_t tab_count;
   int32_t tab_lo;
   uint32_t tab_n;
+  const uint32_t* gtab;
+  uint32_t tab_guarded;        // every table leaf has a guard: rows outside
+                               // all guards read entry tab_n
+  uint32_t pad;
+};
+
+// A lookup table in device memory, built by k_tables before the batch
+// launch: entry i (i < n) holds bit k = leaf k's test of value lo + i, for
+// the m leaves at `leaves`; entry n is zero.
+struct TableBuild {            // 48 bytes
+  uint32_t* dst;
+  const DevInstr* leaves;
+  int64_t lo;
+  uint64_t n;
+  uint64_t entry_begin;        // first entry of this table in the launch's flat range
+  uint32_t m;
+  uint32_t pad;
 };
 
 struct BatchProg {             // 16 bytes
@@ -204,7 +226,7 @@ struct BatchArgs {
   uint32_t ndone;
   uint32_t slot_words;         // LDS words per wave: slots * 64
   uint32_t bm_words;           // LDS words of staged bitmaps per workgroup
-  uint32_t pad;
+  uint32_t acc_words;          // LDS counters: min(nprogs, kBatchMaxProgs)
   unsigned long long* out;
   DevSlot* slot;
 };
@@ -218,6 +240,8 @@ int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* c
                           uint32_t* chunk_offs, uint64_t n, void* stream);
 int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
+int sel_launch_tables(const sel::TableBuild* d_builds, uint32_t nbuilds, uint64_t nentries,
+                      void* stream);
 int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);
 int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, uint32_t lds_bytes,
                      void* stream);

@@ -69,14 +69,15 @@ struct Member {                             // an attached program in a round
 
 struct TableState {
   const sel_table* table;
+  uint64_t chunk_rows;                      // a multiple of the tile
   uint64_t nchunks;
   uint64_t cur = 0;                         // chunk of the next round
   std::vector<Active> progs;
 };
 
 struct RoundSlot {                          // per in-flight round
-  void* dev = nullptr;                      // descriptors | out
-  size_t dev_bytes = 0;
+  void* dev = nullptr;                      // descriptors | out | device tables
+  size_t dev_bytes = 0, host_bytes = 0;
   uint8_t* host = nullptr;                  // pinned staging for descriptors
   selrt::BatchPlan plan;                    // this round's descriptors
   unsigned long long* h_out = nullptr;      // pinned, finished counts
@@ -126,8 +127,13 @@ struct sel_server {
 
 namespace {
 
-uint64_t chunk_rows_of(const sel_server* s) {
-  uint64_t c = s->cfg.chunk_rows ? s->cfg.chunk_rows : (1ull << 26);
+// Rows per chunk of a table: 1/rounds_per_cycle of it, capped by chunk_rows,
+// whole tiles.
+uint64_t chunk_rows_of(const sel_server* s, uint64_t nrows) {
+  const uint64_t r = s->cfg.rounds_per_cycle ? s->cfg.rounds_per_cycle : 8;
+  uint64_t c = (nrows + r - 1) / r;
+  if (s->cfg.chunk_rows) c = std::min<uint64_t>(c, s->cfg.chunk_rows);
+  c = std::max<uint64_t>(c, 1);
   return (c + kTileRows - 1) / kTileRows * kTileRows;
 }
 
@@ -185,7 +191,8 @@ void admit_locked(sel_server* s) {
       if (it == s->tables.end()) {
         TableState ts;
         ts.table = r->tables[i];
-        ts.nchunks = std::max<uint64_t>(1, (r->tables[i]->nrows + chunk_rows_of(s) - 1) / chunk_rows_of(s));
+        ts.chunk_rows = chunk_rows_of(s, r->tables[i]->nrows);
+        ts.nchunks = std::max<uint64_t>(1, (r->tables[i]->nrows + ts.chunk_rows - 1) / ts.chunk_rows);
         it = s->tables.emplace(r->tables[i], ts).first;
       }
       s->lines_used += 1;
@@ -242,14 +249,13 @@ bool launch_round(sel_server* s) {
   std::vector<hipEvent_t> waits;
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    const uint64_t crow = chunk_rows_of(s);
     std::vector<const sel_program*> gp;
     std::vector<uint32_t> gacc;
     for (auto& kv : s->tables) {
       TableState& ts = kv.second;
       if (ts.progs.empty()) continue;
-      const uint64_t row_begin = ts.cur * crow;
-      const uint64_t row_end = std::min(ts.table->nrows, row_begin + crow);
+      const uint64_t row_begin = ts.cur * ts.chunk_rows;
+      const uint64_t row_end = std::min(ts.table->nrows, row_begin + ts.chunk_rows);
       // identical programs of different requests are evaluated once
       std::unordered_map<const sel_program*, uint32_t> group;
       gp.clear();
@@ -288,27 +294,42 @@ bool launch_round(sel_server* s) {
     waits.swap(s->round_waits);
   }
   for (hipEvent_t ev : waits) (void)hipStreamWaitEvent(s->stream, ev, 0);
-  // descriptors, then the counts, staged through pinned memory
-  const size_t o_out = (bp.bytes() + 255) & ~size_t(255);
-  const size_t need = o_out + (size_t)ngroups * 8;
-  if (need > rs.dev_bytes) {
+  // device: descriptors, the counts, the device tables; the descriptors are
+  // staged through pinned memory
+  auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+  const size_t o_out = up(bp.bytes());
+  const size_t o_gtab = up(o_out + (size_t)ngroups * 8);
+  const size_t need_dev = o_gtab + bp.gtab_words * 4;
+  if (need_dev > rs.dev_bytes) {
     if (rs.dev) (void)hipFree(rs.dev);
-    if (rs.host) (void)hipHostFree(rs.host);
-    if (rs.h_out) (void)hipHostFree(rs.h_out);
     rs.dev = nullptr;
-    rs.host = nullptr;
-    rs.h_out = nullptr;
-    const size_t want = std::max(need * 2, size_t(1) << 16);
-    if (hipMalloc(&rs.dev, want) != hipSuccess || hipHostMalloc((void**)&rs.host, want, 0) != hipSuccess ||
-        hipHostMalloc((void**)&rs.h_out, want, 0) != hipSuccess) {
+    rs.dev_bytes = 0;
+    const size_t want = std::max(need_dev * 2, size_t(1) << 16);
+    if (hipMalloc(&rs.dev, want) != hipSuccess) {
       std::lock_guard<std::mutex> lk(s->mu);
       set_error_locked(s, "out of memory for round descriptors");
       return false;
     }
     rs.dev_bytes = want;
   }
+  if (o_gtab > rs.host_bytes) {
+    if (rs.host) (void)hipHostFree(rs.host);
+    if (rs.h_out) (void)hipHostFree(rs.h_out);
+    rs.host = nullptr;
+    rs.h_out = nullptr;
+    rs.host_bytes = 0;
+    const size_t want = std::max(o_gtab * 2, size_t(1) << 16);
+    if (hipHostMalloc((void**)&rs.host, want, 0) != hipSuccess ||
+        hipHostMalloc((void**)&rs.h_out, want, 0) != hipSuccess) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      set_error_locked(s, "out of memory for round descriptors");
+      return false;
+    }
+    rs.host_bytes = want;
+  }
   BatchArgs a{};
-  bp.write(rs.host, (char*)rs.dev, a);
+  const TableBuild* d_builds = nullptr;
+  bp.write(rs.host, (char*)rs.dev, (uint32_t*)((char*)rs.dev + o_gtab), a, &d_builds);
   a.acc = s->d_acc;
   a.done = nullptr;                  // every line of the round is read out and reset
   a.ndone = ngroups;
@@ -321,7 +342,7 @@ bool launch_round(sel_server* s) {
   const uint32_t grid = (uint32_t)std::max<uint64_t>(
       1, std::min<uint64_t>((uint64_t)std::min(occ, 4) * s->ctx->num_cus, (bp.total_tiles + 3) / 4));
   bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
-  ok = ok && sel_launch_batch(a, grid, block, lds, s->stream) == 0;
+  ok = ok && bp.launch(a, d_builds, grid, block, s->stream) == 0;
   ok = ok && hipMemcpyAsync(rs.h_out, a.out, (size_t)ngroups * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
   ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
   if (!ok) {

@@ -64,7 +64,8 @@ class sel_launch(ctypes.Structure):
 
 class sel_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_uint64),
-                ("max_programs", ctypes.c_uint32), ("rounds_in_flight", ctypes.c_uint32)]
+                ("max_programs", ctypes.c_uint32), ("rounds_in_flight", ctypes.c_uint32),
+                ("rounds_per_cycle", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class sel_request(ctypes.Structure):
@@ -445,9 +446,10 @@ class Server:
     own stream)."""
 
     def __init__(self, ctx: Context, hbm_budget_bytes=0, chunk_rows=0, max_programs=0,
-                 rounds_in_flight=0):
+                 rounds_in_flight=0, rounds_per_cycle=0):
         self.ctx = ctx
-        cfg = sel_server_config(hbm_budget_bytes, chunk_rows, max_programs, rounds_in_flight)
+        cfg = sel_server_config(hbm_budget_bytes, chunk_rows, max_programs, rounds_in_flight,
+                                rounds_per_cycle, 0)
         h = _vp()
         ctx.check(sel_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

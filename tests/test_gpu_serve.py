@@ -180,13 +180,14 @@ def test_admission_by_footprint(sel, ctx, world):
 
 
 def test_chunk_sizes_agree(sel, ctx, world):
-    """The same requests with one chunk per table and with many chunks."""
+    """The same requests with one chunk per table and with many chunks
+    (equal chunks per table, and chunks capped by a row count)."""
     tables, pools, alone = world["tables"], world["pools"], world["alone"]
     trace = datagen.serving_trace(seed=8, rate=2000.0, duration=0.03,
                                   pool_sizes=(16, 16, 16, 16, 8), pushdown_rate=0.0)
-    for chunk in (1 << 32, 1 << 16, 2048):
-        srv = ctx.server(chunk_rows=chunk, rounds_in_flight=3)
+    for cycle, chunk in ((1, 0), (8, 0), (3, 1 << 16), (1000, 2048)):
+        srv = ctx.server(chunk_rows=chunk, rounds_per_cycle=cycle, rounds_in_flight=3)
         res = run_trace(sel, ctx, world, trace, srv, time_scale=0.0)
         for (t, items, pd), (counts, *_rest) in zip(trace, res):
-            assert counts == [alone[tb][pi] for tb, pi in items], chunk
+            assert counts == [alone[tb][pi] for tb, pi in items], (cycle, chunk)
         srv.destroy()
