@@ -421,8 +421,23 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     max_bm_words = std::max(max_bm_words, ps.bm_words);
     total_tiles += (tiles + kBatchTileAlign - 1) / kBatchTileAlign * kBatchTileAlign;
   };
-  Pass ps;
+  // Pack programs that read the same wide columns into the same passes, so
+  // that a pass which needs no wide column does not read one: order them by
+  // their column sets, widest columns first.
+  std::vector<std::vector<std::pair<uint32_t, uintptr_t>>> key(n);
   for (uint32_t i = 0; i < n; ++i) {
+    for (const DevInstr& I : prg[i]->host_code) {
+      if (!is_value_test(I.op)) continue;
+      const std::pair<uint32_t, uintptr_t> c{8u - type_bytes(I.type), (uintptr_t)I.data};
+      if (std::find(key[i].begin(), key[i].end(), c) == key[i].end()) key[i].push_back(c);
+    }
+    std::sort(key[i].begin(), key[i].end());
+  }
+  std::vector<uint32_t> order(n);
+  for (uint32_t i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
+  Pass ps;
+  for (uint32_t i : order) {
     // callers admit only programs that fit a pass of their own
     if (!ps.progs.empty() && ps.slots + ps.new_slots(prg[i]) > kBatchSlots) {
       flush(ps);

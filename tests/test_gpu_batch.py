@@ -171,3 +171,47 @@ def test_batch_random_programs(sel, ctx, n):
     for _ in range(2):
         assert b.run() == want
     b.destroy()
+
+
+def test_batch_star_programs(sel, ctx):
+    """Star semi-join programs in one batch, over dimensions large enough
+    that the batch takes every lookup route: an LDS table (2556 keys),
+    device-memory tables (30k and 600k keys, read where the earlier probes
+    leave rows), and guarded bitmap probes (9M keys).  With fact-side
+    predicates, a plain fact program and a program used twice (no guard)."""
+    sizes = (2556, 30_000, 600_000, 9_000_000)
+    say("batch star: generating dimensions and fact")
+    dims = datagen.star_dims(seed=42, sizes=sizes)
+    fact = datagen.star_fact(1_000_003, dim_rows=sizes)
+    ddims = [sel.device_table(ctx, d) for d in dims]
+    dfact = sel.device_table(ctx, fact)
+    ofact = oracle.Oracle(fact)
+    fp = datagen.star_fact_predicate()
+    progs, want, keep = [], [], []
+    for k, combo in enumerate(datagen.star_dim_programs(7, 12, dims)):
+        bms_gpu, bms_cpu = [], []
+        for d, dt, p in zip(dims, ddims, combo):
+            bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+            st, _ = ctx.pushdown_keybitmap(dt, 0, 0, ctx.program(dt, p), bm, d.nrows)
+            assert st == sel.SEL_OK
+            ost, _, owords = oracle.Oracle(d).keybitmap(p, 0, 0, d.nrows)
+            assert ost == 0
+            bms_gpu.append(bm)
+            bms_cpu.append(owords)
+        keep.append(bms_gpu)
+        pred = ctx.program(dfact, fp) if k % 3 == 2 else None
+        progs.append(ctx.star_program(dfact, [0, 1, 2, 3], bms_gpu, list(sizes), pred))
+        want.append(ofact.star_count([0, 1, 2, 3], bms_cpu, list(sizes),
+                                     fp if pred is not None else None, threads=8))
+    progs.append(ctx.program(dfact, fp))
+    want.append(ofact.count(fp, threads=8))
+    progs.append(progs[0])
+    want.append(want[0])
+    pairs = [(dfact, p) for p in progs]
+    assert [ctx.count(*p) for p in pairs] == want
+    assert ctx.count_batch(pairs) == want
+    assert ctx.count_batch(pairs[:5]) == want[:5]
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
