@@ -412,6 +412,12 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
       BatchProg bp{};
       bp.ops = (const uint32_t*)(uintptr_t)ops.size();
       bp.nops = (uint32_t)pr.first.size();
+      bool two = true;   // every validity reference is kNoSlot
+      for (uint32_t w : pr.first) {
+        const uint32_t op = w & 0xFFu;
+        if ((op < D_AND || op >= B_AND_LEAF) && (w >> 20) != kNoSlot) two = false;
+      }
+      if (two) bp.nops |= kTwoValued;
       bp.acc_index = pr.second;
       ops.insert(ops.end(), pr.first.begin(), pr.first.end());
       progs.push_back(bp);

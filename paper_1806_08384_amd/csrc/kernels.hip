@@ -887,6 +887,47 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
   return tt;
 }
 
+// The same for a program none of whose columns has NULLs: no value is
+// UNKNOWN, so FALSE is the complement of TRUE and one word per stack entry
+// suffices.
+__device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint32_t nops,
+                                             const uint32_t* wl, uint32_t lane) {
+  uint32_t st[kMaxDepth];
+  uint32_t tt = 0;
+  int d = 0;
+  for (uint32_t pc = 0; pc < nops; ++pc) {
+    const uint32_t w = ops[pc];
+    const uint32_t op = w & 0xFFu;
+    if (op >= B_AND_LEAF) {
+      const uint32_t P = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+      if (op == B_AND_LEAF) tt &= P;
+      else tt |= P;
+    } else if (op < D_AND || op == D_TRUE || op == D_FALSE) {
+      uint32_t t;
+      if (op == D_RANGE) t = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+      else t = (op == D_NN_TRUE || op == D_NOTNULL || op == D_TRUE) ? ~0u : 0u;
+#pragma unroll
+      for (int k = 0; k < kMaxDepth; ++k)
+        if (k == d - 1) st[k] = tt;
+      tt = t;
+      ++d;
+    } else if (op == D_NOT) {
+      tt = ~tt;
+    } else if (op == D_ISUNK) {
+      tt = 0;
+    } else {
+      uint32_t at = 0;
+#pragma unroll
+      for (int k = 0; k < kMaxDepth; ++k)
+        if (k == d - 2) at = st[k];
+      if (op == D_AND) tt &= at;
+      else tt |= at;
+      --d;
+    }
+  }
+  return tt;
+}
+
 // Per workgroup, per-program counts accumulate in LDS; at the end each
 // workgroup adds them to per-program accumulator lines (128 bytes each, so
 // atomics on different programs do not contend), and the last workgroup by
@@ -982,7 +1023,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
     }
     for (uint32_t k = 0; k < pn; ++k) {
       const CONSTANT BatchProg* P = progs + pb + k;
-      const uint32_t T = run_ops((const CONSTANT uint32_t*)P->ops, P->nops, wl, lane) & inr;
+      const uint32_t nops = P->nops;
+      const uint32_t T = (nops & kTwoValued ? run_ops2((const CONSTANT uint32_t*)P->ops, nops & ~kTwoValued, wl, lane)
+                                            : run_ops((const CONSTANT uint32_t*)P->ops, nops, wl, lane)) & inr;
       const uint32_t c = wave_sum(__builtin_popcount(T));
       if (lane == 0 && c) {
         if (pb + k < nacc) {

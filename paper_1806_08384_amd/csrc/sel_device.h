@@ -202,10 +202,11 @@ struct TableBuild {            // 48 bytes
 
 struct BatchProg {             // 16 bytes
   const uint32_t* ops;         // batch_op words, postfix
-  uint32_t nops;
+  uint32_t nops;               // | kTwoValued: no column of the program has NULLs
   uint32_t acc_index;          // accumulator line this program adds into
 };
 
+constexpr uint32_t kTwoValued = 0x80000000u;
 constexpr int kBatchMaxProgs = 1024;
 constexpr int kBatchAccStride = 16;   // u64 per accumulator: one 128-byte line each
 
