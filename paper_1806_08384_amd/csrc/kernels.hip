@@ -1021,17 +1021,29 @@ __global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
       entry_leaves_partial(E, cols, leaves, tb, lane, nrows, wl);
       inr = inrange_bits(tb, lane, nrows);
     }
-    for (uint32_t k = 0; k < pn; ++k) {
-      const CONSTANT BatchProg* P = progs + pb + k;
-      const uint32_t nops = P->nops;
-      const uint32_t T = (nops & kTwoValued ? run_ops2((const CONSTANT uint32_t*)P->ops, nops & ~kTwoValued, wl, lane)
-                                            : run_ops((const CONSTANT uint32_t*)P->ops, nops, wl, lane)) & inr;
-      const uint32_t c = wave_sum(__builtin_popcount(T));
-      if (lane == 0 && c) {
-        if (pb + k < nacc) {
-          atomicAdd(&acc[pb + k], c);
-        } else {  // beyond the LDS table: straight to the accumulator line
-          atomicAdd(&a.acc[(uint64_t)P->acc_index * kBatchAccStride], (unsigned long long)c);
+    // programs in pairs: both popcounts (at most 2048 per wave each) share
+    // one wave reduction, 16 bits apart
+    for (uint32_t k = 0; k < pn; k += 2) {
+      uint32_t T[2] = {0u, 0u};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (k + q >= pn) break;
+        const CONSTANT BatchProg* P = progs + pb + k + q;
+        const uint32_t nops = P->nops;
+        T[q] = (nops & kTwoValued ? run_ops2((const CONSTANT uint32_t*)P->ops, nops & ~kTwoValued, wl, lane)
+                                  : run_ops((const CONSTANT uint32_t*)P->ops, nops, wl, lane)) & inr;
+      }
+      const uint32_t c2 = wave_sum(__builtin_popcount(T[0]) | (__builtin_popcount(T[1]) << 16));
+      if (lane == 0 && c2) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const uint32_t c = q ? c2 >> 16 : c2 & 0xFFFFu;
+          if (!c) continue;
+          if (pb + k + q < nacc) {
+            atomicAdd(&acc[pb + k + q], c);
+          } else {  // beyond the LDS table: straight to the accumulator line
+            atomicAdd(&a.acc[(uint64_t)progs[pb + k + q].acc_index * kBatchAccStride], (unsigned long long)c);
+          }
         }
       }
     }
