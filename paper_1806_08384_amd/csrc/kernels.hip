@@ -668,25 +668,31 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
 // In-register transpose of a 32 x 32 bit matrix: on return a[c] bit r is
 // what a[r] bit c was.  Each stage swaps, in every 2s x 2s block, the s x s
 // block above the diagonal with the one below it.
-template <int S>
+// Only words 0 .. NOUT-1 of the result are wanted: later stages mix words
+// within blocks of S, so a stage updates only the words below
+// ceil(NOUT / S) * S.
+template <int S, int NOUT>
 __device__ __forceinline__ void transpose_stage(uint32_t (&a)[32], uint32_t m) {
+  constexpr int R = (NOUT + S - 1) / S * S;
 #pragma unroll
   for (int g = 0; g < 32; g += 2 * S) {
 #pragma unroll
     for (int k = g; k < g + S; ++k) {
+      if (k >= R) continue;
       const uint32_t t = ((a[k] >> S) ^ a[k + S]) & m;
-      a[k + S] ^= t;
+      if (k + S < R) a[k + S] ^= t;
       a[k] ^= t << S;
     }
   }
 }
 
+template <int NOUT>
 __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
-  transpose_stage<16>(a, 0x0000FFFFu);
-  transpose_stage<8>(a, 0x00FF00FFu);
-  transpose_stage<4>(a, 0x0F0F0F0Fu);
-  transpose_stage<2>(a, 0x33333333u);
-  transpose_stage<1>(a, 0x55555555u);
+  transpose_stage<16, NOUT>(a, 0x0000FFFFu);
+  transpose_stage<8, NOUT>(a, 0x00FF00FFu);
+  transpose_stage<4, NOUT>(a, 0x0F0F0F0Fu);
+  transpose_stage<2, NOUT>(a, 0x33333333u);
+  transpose_stage<1, NOUT>(a, 0x55555555u);
 }
 
 // Every leaf of one segment; truth words go to the wave's slots.  An int64
@@ -751,11 +757,23 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
       }
       // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf
       // i's word (bit b = row b)
-      transpose32(T);
       const uint32_t m = C->tab_count;
+      if (m <= 8) {
+        transpose32<8>(T);
 #pragma unroll
-      for (int i = 0; i < 32; ++i)
-        if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+        for (int i = 0; i < 8; ++i)
+          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+      } else if (m <= 16) {
+        transpose32<16>(T);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+      } else {
+        transpose32<32>(T);
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+      }
     }
   }
 }
