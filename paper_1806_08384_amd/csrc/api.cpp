@@ -267,13 +267,14 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
       ctx->own_stream = true;
     }
     void* dmem = nullptr;
-    const size_t dbytes = 256 + 129 * sizeof(DevInstr);
+    const size_t dbytes = 256 + 129 * sizeof(DevInstr) + kMaxStage * sizeof(BatchBitmap);
     if ((e = hipMalloc(&dmem, dbytes)) != hipSuccess) { where = "hipMalloc(ctx)"; break; }
     ctx->slot = (DevSlot*)dmem;
     if ((e = hipMemset(dmem, 0, dbytes)) != hipSuccess) { where = "hipMemset(ctx)"; break; }
     ctx->dout = (unsigned long long*)((char*)dmem + 128);
     ctx->dstar = (DevInstr*)((char*)dmem + 256);
     ctx->dtrue = ctx->dstar + 128;
+    ctx->dstage = (BatchBitmap*)(ctx->dtrue + 1);
     if ((e = hipMalloc(&ctx->arena_mem, kArenaBytes)) != hipSuccess) { where = "hipMalloc(arena)"; break; }
     ctx->arena.init((char*)ctx->arena_mem, kArenaBytes);
     if ((e = hipHostMalloc((void**)&ctx->hout, 64, hipHostMallocDefault)) != hipSuccess) { where = "hipHostMalloc"; break; }
@@ -426,7 +427,13 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   p->depth = L.depth;
   p->text = L.text;
   const size_t code_bytes = L.code.size() * sizeof(DevInstr);
-  const size_t total = code_bytes + L.blob.size();
+  const size_t blob_bytes = (L.blob.size() + 7) & ~size_t(7);
+  // bitmaps a scan stages in LDS (their sources are blob offsets until the
+  // blob's device address is known)
+  std::vector<BatchBitmap> stage;
+  p->stage_words = plan_scan_stage(L.code, stage);
+  p->nstage = (uint32_t)stage.size();
+  const size_t total = code_bytes + blob_bytes + stage.size() * sizeof(BatchBitmap);
   p->dev = ctx->arena.alloc(total);
   if (!p->dev) {
     hipError_t he = hipMalloc(&p->dev, total);
@@ -440,9 +447,13 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   const uintptr_t blob_base = (uintptr_t)p->dev + code_bytes;
   for (size_t k = 0; k < L.code.size(); ++k)
     if (L.aux_is_offset[k]) L.code[k].aux = (const void*)(blob_base + (uintptr_t)L.code[k].aux);
-  std::vector<uint8_t> host(total);
+  for (BatchBitmap& b : stage) b.src = (const uint32_t*)(blob_base + (uintptr_t)b.src);
+  p->dstage = p->nstage ? (const BatchBitmap*)((char*)p->dev + code_bytes + blob_bytes) : nullptr;
+  std::vector<uint8_t> host(total, 0);
   std::memcpy(host.data(), L.code.data(), code_bytes);
   if (!L.blob.empty()) std::memcpy(host.data() + code_bytes, L.blob.data(), L.blob.size());
+  if (!stage.empty())
+    std::memcpy(host.data() + code_bytes + blob_bytes, stage.data(), stage.size() * sizeof(BatchBitmap));
   sel_status cst = stage_copy(ctx, p->dev, host.data(), total);
   if (cst != SEL_OK) {
     if (p->own_alloc) (void)hipFree(p->dev);
@@ -488,6 +499,7 @@ sel_status sel_count_async(sel_ctx* ctx, const sel_table* table, const sel_progr
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
+  set_stage(a, prog);
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = (unsigned long long*)d_count;
@@ -502,6 +514,7 @@ sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* pr
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
+  set_stage(a, prog);
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = ctx->dout;
@@ -545,6 +558,7 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
+  set_stage(a, prog);
   a.nrows = table->nrows;
   a.ntiles = ntiles;
   a.out = ctx->dout;
@@ -605,6 +619,7 @@ sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t k
   if (prog) {
     a.prog = prog->dcode;
     a.nins = prog->nins;
+    set_stage(a, prog);
   } else {
     a.prog = ctx->dtrue;
     a.nins = 1;
@@ -714,9 +729,18 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
   DeviceGuard g(ctx->device);
   st = stage_copy(ctx, ctx->dstar, code.data(), code.size() * sizeof(DevInstr));
   if (st != SEL_OK) return st;
+  std::vector<BatchBitmap> stage;
+  const uint32_t stage_words = plan_scan_stage(code, stage);
+  if (!stage.empty()) {
+    st = stage_copy(ctx, ctx->dstage, stage.data(), stage.size() * sizeof(BatchBitmap));
+    if (st != SEL_OK) return st;
+  }
   ScanArgs a{};
   a.prog = ctx->dstar;
   a.nins = (uint32_t)code.size();
+  a.stage = ctx->dstage;
+  a.nstage = (uint32_t)stage.size();
+  a.stage_words = stage_words;
   a.nrows = fact->nrows;
   a.ntiles = ntiles_of(fact->nrows);
   a.out = ctx->dout;
@@ -746,7 +770,11 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
   p->tune_class = tune_class_of(bpr, p->nins);
   p->host_code = code;
   p->text = "STAR\n";
-  const size_t bytes = code.size() * sizeof(DevInstr);
+  std::vector<BatchBitmap> stage;
+  p->stage_words = plan_scan_stage(code, stage);
+  p->nstage = (uint32_t)stage.size();
+  const size_t code_bytes = code.size() * sizeof(DevInstr);
+  const size_t bytes = code_bytes + stage.size() * sizeof(BatchBitmap);
   p->dev = ctx->arena.alloc(bytes);
   if (!p->dev) {
     hipError_t he = hipMalloc(&p->dev, bytes);
@@ -757,7 +785,11 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
     p->own_alloc = true;
   }
   p->dcode = (DevInstr*)p->dev;
-  st = stage_copy(ctx, p->dev, code.data(), bytes);
+  p->dstage = p->nstage ? (const BatchBitmap*)((char*)p->dev + code_bytes) : nullptr;
+  std::vector<uint8_t> image(bytes);
+  std::memcpy(image.data(), code.data(), code_bytes);
+  if (!stage.empty()) std::memcpy(image.data() + code_bytes, stage.data(), stage.size() * sizeof(BatchBitmap));
+  st = stage_copy(ctx, p->dev, image.data(), bytes);
   if (st != SEL_OK) {
     if (p->own_alloc) (void)hipFree(p->dev);
     else ctx->arena.release(p->dev);

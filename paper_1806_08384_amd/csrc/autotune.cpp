@@ -93,6 +93,7 @@ sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program*
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
+  set_stage(a, prog);
   a.nrows = table->nrows;
   a.ntiles = ntiles;
   a.out = ctx->dout;

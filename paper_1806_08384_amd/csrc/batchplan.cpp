@@ -520,4 +520,28 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
   return sel_launch_batch(a, grid, block, lds_bytes(block), stream);
 }
 
+uint32_t plan_scan_stage(const std::vector<DevInstr>& code, std::vector<BatchBitmap>& out) {
+  out.clear();
+  uint32_t words = 0;
+  for (const DevInstr& I : code) {
+    if (I.op != D_BITMAP || I.span == 0 || out.size() == kMaxStage) continue;
+    if (I.type != T_I64 &&
+        (I.lo < INT32_MIN || I.lo > INT32_MAX || I.span - 1 > (uint64_t)(INT32_MAX - I.lo)))
+      continue;
+    bool seen = false;
+    for (const BatchBitmap& b : out) seen |= b.src == (const uint32_t*)I.aux;
+    if (seen) continue;
+    const uint64_t w = (I.span + 31) / 32;
+    if (words + w + 1 > kScanStageWords) continue;
+    BatchBitmap b{};
+    b.src = (const uint32_t*)I.aux;
+    b.words = (uint32_t)w;
+    b.last_mask = I.span % 32 ? (1u << (I.span % 32)) - 1u : ~0u;
+    b.lds_word = words;
+    out.push_back(b);
+    words += (uint32_t)w + 1;
+  }
+  return words;
+}
+
 }  // namespace selrt

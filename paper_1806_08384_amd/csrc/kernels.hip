@@ -49,6 +49,14 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Bitmaps of the program staged in the workgroup's LDS: a leaf whose bitmap
+// address is listed reads the copy (followed by a zero word) instead.
+struct StageView {
+  const CONSTANT BatchBitmap* list;
+  uint32_t n;
+  const uint32_t* lds;
+};
+
 // ---------------------------------------------------------------- loads --
 // Raw storage of one lane's 32 rows of a column in a full tile.  All loads
 // of a column are issued before any is used, so each lane keeps 32 rows of
@@ -178,10 +186,40 @@ __device__ __forceinline__ uint32_t inrange_bits(uint64_t tb, uint32_t lane, uin
 // ---------------------------------------------------------------- leaves --
 template <int TY, bool FULL>
 __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
-                                              uint64_t nrows, uint32_t need) {
+                                              uint64_t nrows, uint32_t need, const StageView& sv) {
   const void* data = I->data;
   const int64_t lo = I->lo;
   const uint64_t span = I->span;
+  if (op == D_BITMAP && sv.n) {
+    uint32_t off = kNoLds, z = 0;
+    for (uint32_t k = 0; k < sv.n; ++k) {
+      if (sv.list[k].src == (const uint32_t*)I->aux) {
+        off = sv.list[k].lds_word;
+        z = sv.list[k].words * 32;
+        break;
+      }
+    }
+    if (off != kNoLds) {
+      // an offset outside the window, or a row the guard skips, reads the
+      // zero bit z after the copy; for narrow columns the window lies inside
+      // int32 (the host stages only such bitmaps)
+      const uint32_t* bm = sv.lds + off;
+      if constexpr (TY == T_I64) {
+        return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
+          const uint64_t d = (uint64_t)x - (uint64_t)lo;
+          const uint32_t k = ((need >> b) & 1u) && d < z ? (uint32_t)d : z;
+          return (bm[k >> 5] >> (k & 31)) & 1u;
+        });
+      } else {
+        const uint32_t lo32 = (uint32_t)lo;
+        return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
+          const uint32_t d = (uint32_t)x - lo32;
+          const uint32_t k = ((need >> b) & 1u) && d < z ? d : z;
+          return (bm[k >> 5] >> (k & 31)) & 1u;
+        });
+      }
+    }
+  }
   if (op == D_RANGE) {
     if constexpr (TY == T_I64) {
       return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int) {
@@ -234,7 +272,7 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
 template <bool FULL>
 __device__ __forceinline__ void eval_leaf(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
                                           uint64_t nrows, uint32_t tos_t, uint32_t tos_f,
-                                          uint32_t& t, uint32_t& f) {
+                                          uint32_t& t, uint32_t& f, const StageView& sv) {
   const uint32_t* valid = I->valid;
   const uint32_t V = valid_bits<FULL>(valid, tb, lane, nrows);
   if (op >= D_NN_TRUE) {
@@ -251,10 +289,10 @@ __device__ __forceinline__ void eval_leaf(uint32_t op, CInstr I, uint64_t tb, ui
   else if (flags & F_GUARD_OR) need = ~tos_t;
   uint32_t P;
   switch (I->type) {
-    case T_I8: P = leaf_pred<T_I8, FULL>(op, I, tb, lane, nrows, need); break;
-    case T_I16: P = leaf_pred<T_I16, FULL>(op, I, tb, lane, nrows, need); break;
-    case T_I32: P = leaf_pred<T_I32, FULL>(op, I, tb, lane, nrows, need); break;
-    default: P = leaf_pred<T_I64, FULL>(op, I, tb, lane, nrows, need); break;
+    case T_I8: P = leaf_pred<T_I8, FULL>(op, I, tb, lane, nrows, need, sv); break;
+    case T_I16: P = leaf_pred<T_I16, FULL>(op, I, tb, lane, nrows, need, sv); break;
+    case T_I32: P = leaf_pred<T_I32, FULL>(op, I, tb, lane, nrows, need, sv); break;
+    default: P = leaf_pred<T_I64, FULL>(op, I, tb, lane, nrows, need, sv); break;
   }
   t = P & V;
   f = ~P & V;
@@ -281,7 +319,7 @@ __device__ __forceinline__ void fill(const uint32_t (&st)[kMaxDepth], const uint
 // TRUE bits of the lane's 32 rows of the tile starting at row tb.
 template <bool FULL>
 __device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64_t tb,
-                                              uint32_t lane, uint64_t nrows) {
+                                              uint32_t lane, uint64_t nrows, const StageView& sv) {
   uint32_t st[kMaxDepth], sf[kMaxDepth];
   uint32_t tt = 0, tf = 0;
   int d = 0;  // values on the stack; the top is (tt, tf)
@@ -292,7 +330,7 @@ __device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64
       uint32_t t, f;
       if (op == D_TRUE) { t = ~0u; f = 0; }
       else if (op == D_FALSE) { t = 0; f = ~0u; }
-      else eval_leaf<FULL>(op, I, tb, lane, nrows, tt, tf, t, f);
+      else eval_leaf<FULL>(op, I, tb, lane, nrows, tt, tf, t, f, sv);
       spill(st, sf, d - 1, tt, tf);
       tt = t; tf = f;
       ++d;
@@ -357,6 +395,23 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t W = (uint64_t)gridDim.x * nw;
+  extern __shared__ uint32_t sbm[];
+  const StageView sv{(const CONSTANT BatchBitmap*)a.stage, a.nstage, sbm};
+  if (a.nstage) {
+    // the program's small bitmaps, each followed by a zero word
+    for (uint32_t k = 0; k < a.nstage; ++k) {
+      const CONSTANT BatchBitmap* B = sv.list + k;
+      const uint32_t n = B->words, last = B->last_mask;
+      const GLOBAL uint32_t* src = gptr<uint32_t>(B->src);
+      uint32_t* dst = sbm + B->lds_word;
+      for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
+        uint32_t w = 0;
+        if (i < n) w = i + 1 == n ? src[i] & last : src[i];
+        dst[i] = w;
+      }
+    }
+    __syncthreads();
+  }
   uint32_t cnt = 0, oor = 0;
   // M_MASK: result words of the last 8 tiles, written together with
   // nontemporal stores (fewer, fuller store bursts interleaved with the loads)
@@ -369,9 +424,9 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
     const uint64_t tb = tile * kTileRows;
     uint32_t T;
     if (tb + kTileRows <= a.nrows) {
-      T = eval_tile<true>(prog, a.nins, tb, lane, a.nrows);
+      T = eval_tile<true>(prog, a.nins, tb, lane, a.nrows, sv);
     } else {
-      T = eval_tile<false>(prog, a.nins, tb, lane, a.nrows) & inrange_bits(tb, lane, a.nrows);
+      T = eval_tile<false>(prog, a.nins, tb, lane, a.nrows, sv) & inrange_bits(tb, lane, a.nrows);
     }
     cnt += __builtin_popcount(T);
     if constexpr (MODE == M_MASK) {
@@ -712,7 +767,7 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
     const uint32_t op = I->op;
     uint32_t* w = wl + I->slot * kWave + lane;
     if (op == D_INLIST) {
-      if (TY != T_I64 || h == 1) *w = leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u);
+      if (TY != T_I64 || h == 1) *w = leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u, StageView{});
       continue;
     }
     const uint32_t P = seg_leaf<TY>(r, op, I, bmlds, wl, lane, TY == T_I64 && h == 0 ? 16 : 0);
@@ -842,10 +897,10 @@ __device__ __forceinline__ void entry_leaves_partial(const CONSTANT BatchTable* 
       CInstr I = leaves + lb + k;
       uint32_t P;
       switch (C->type) {
-        case T_I8: P = leaf_pred<T_I8, false>(I->op, I, tb, lane, nrows, ~0u); break;
-        case T_I16: P = leaf_pred<T_I16, false>(I->op, I, tb, lane, nrows, ~0u); break;
-        case T_I32: P = leaf_pred<T_I32, false>(I->op, I, tb, lane, nrows, ~0u); break;
-        default: P = leaf_pred<T_I64, false>(I->op, I, tb, lane, nrows, ~0u); break;
+        case T_I8: P = leaf_pred<T_I8, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        case T_I16: P = leaf_pred<T_I16, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        case T_I32: P = leaf_pred<T_I32, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        default: P = leaf_pred<T_I64, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
       }
       wl[I->slot * kWave + lane] = P;
     }
@@ -1131,10 +1186,11 @@ __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 
 int sel_launch_scan(int mode, const ScanArgs& a, uint32_t grid, uint32_t block, void* stream) {
   hipStream_t s = (hipStream_t)stream;
+  const uint32_t lds = a.nstage ? 4u * a.stage_words : 0u;
   switch (mode) {
-    case M_COUNT: hipLaunchKernelGGL(k_scan<M_COUNT>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
-    case M_MASK: hipLaunchKernelGGL(k_scan<M_MASK>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
-    default: hipLaunchKernelGGL(k_scan<M_KEYBITMAP>, dim3(grid), dim3(block), 0, s, a.prog, a); break;
+    case M_COUNT: hipLaunchKernelGGL(k_scan<M_COUNT>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
+    case M_MASK: hipLaunchKernelGGL(k_scan<M_MASK>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
+    default: hipLaunchKernelGGL(k_scan<M_KEYBITMAP>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
   }
   return (int)hipGetLastError();
 }

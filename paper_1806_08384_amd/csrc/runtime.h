@@ -92,6 +92,7 @@ struct sel_ctx {
   char* hstage = nullptr;                  // pinned host staging (kStageBytes)
   hipEvent_t stage_free = nullptr;         // recorded after each copy out of hstage
   DevInstr* dstar = nullptr;               // device, star-count program (128)
+  sel::BatchBitmap* dstage = nullptr;      // device, its staged bitmaps (kMaxStage)
   DevInstr* dtrue = nullptr;               // device, the program TRUE
   void* arena_mem = nullptr;               // device, programs
   void* batch_mem = nullptr;               // device, sel_count_batch workspace
@@ -126,6 +127,8 @@ struct sel_program {
   bool own_alloc = false;           // or its own hipMalloc if the arena is full
   DevInstr* dcode = nullptr;
   std::vector<DevInstr> host_code;  // with device pointers (for star programs)
+  const sel::BatchBitmap* dstage = nullptr;   // bitmaps a scan stages in LDS
+  uint32_t nstage = 0, stage_words = 0;
   uint32_t nins = 0;
   uint32_t tune_class = 0;          // bytes-per-row and length bucket
   int depth = 0;
@@ -219,6 +222,17 @@ struct BatchPlan {
 // LDS slots a program needs in a pass of its own (distinct leaves plus
 // validity words); batching requires at most kBatchMaxSlots.
 uint32_t batch_slots_alone(const sel_program* p);
+// The bitmaps of a program that a single-program scan stages in LDS: in
+// program order, distinct, windows inside int32 for narrow columns, at most
+// kScanStageWords words with one zero word after each.  Returns the words.
+constexpr uint32_t kMaxStage = 64;
+uint32_t plan_scan_stage(const std::vector<DevInstr>& code, std::vector<sel::BatchBitmap>& out);
+inline void set_stage(sel::ScanArgs& a, const sel_program* p) {
+  a.stage = p ? p->dstage : nullptr;
+  a.nstage = p ? p->nstage : 0;
+  a.stage_words = p ? p->stage_words : 0;
+}
+
 sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
                       const sel_program* const* progs, BatchPlan& bp);
 

@@ -72,10 +72,12 @@ struct DevSlot {
 
 enum ScanMode : int { M_COUNT = 0, M_MASK = 1, M_KEYBITMAP = 2 };
 
+struct BatchBitmap;
+
 struct ScanArgs {
   const DevInstr* prog;
   uint32_t nins;
-  uint32_t pad0;
+  uint32_t nstage;             // bitmaps the workgroups copy to LDS first
   uint64_t nrows;
   uint64_t ntiles;
   DevSlot* slot;
@@ -85,11 +87,16 @@ struct ScanArgs {
   // M_KEYBITMAP
   const void* key_data;
   uint32_t key_type;
-  uint32_t pad1;
+  uint32_t stage_words;        // LDS words of the staged bitmaps
   int64_t key_min;
   uint64_t nbits;
   uint32_t* bitmap;
+  const BatchBitmap* stage;    // nstage entries (src, words, mask, offset)
 };
+
+// Single-program scans stage the program's small bitmaps (in program order,
+// up to this many words) in LDS; lookups into them skip the memory system.
+constexpr uint32_t kScanStageWords = 4096;
 
 struct CompactArgs {
   const uint32_t* mask;
@@ -158,7 +165,7 @@ struct BatchTable {            // 64 bytes: one pass over a table or a chunk
   uint32_t pad;
 };
 
-struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS
+struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS (batch or scan)
   const uint32_t* src;
   uint32_t words;              // words copied; a zero word follows them
   uint32_t last_mask;          // bits of the last word below nbits
