@@ -525,26 +525,54 @@ __global__ void __launch_bounds__(1024) k_chunk_offsets(const uint32_t* __restri
 // consecutive tiles and issues all their loads before using any.
 constexpr int kCompactTiles = 4;
 
+// Inclusive sum over the 64 lanes: DPP shifts within each 16-lane row, then
+// the row totals by readlane.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x, uint32_t lane, uint32_t& total) {
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, true);  // row_shr:1
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, true);  // row_shr:2
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, true);  // row_shr:4
+  x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, true);  // row_shr:8
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 47);
+  const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+  total = r0 + r1 + r2 + r3;
+  const uint32_t row = lane >> 4;
+  return x + (row == 0 ? 0u : row == 1 ? r0 : row == 2 ? r0 + r1 : r0 + r1 + r2);
+}
+
+// A row's rank in the tile is: TRUE rows of earlier steps + TRUE rows of this
+// step in lower lanes + TRUE rows before it in the lane's own nibble.  The
+// per-lane counts of the 8 steps are packed two to a word (16-bit fields; a
+// step holds at most 256 TRUE rows) and prefix-summed over the lanes four
+// words at a time.
 __device__ __forceinline__ void compact_tile(uint32_t w, uint64_t base, uint64_t tile,
                                              uint32_t lane, uint32_t* __restrict__ out,
                                              uint64_t cap) {
   const uint64_t tb = tile * kTileRows;
+  uint32_t excl[4], tot[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = __builtin_popcount((w >> (8 * q)) & 0xFu);
+    const uint32_t hi = __builtin_popcount((w >> (8 * q + 4)) & 0xFu);
+    const uint32_t packed = lo | (hi << 16);
+    excl[q] = wave_incl_sum(packed, lane, tot[q]) - packed;
+  }
 #pragma unroll
   for (int j = 0; j < kSteps; ++j) {
     const uint32_t nib = (w >> (4 * j)) & 0xFu;
-    uint32_t below = 0, total = 0;
+    const uint32_t sh = 16 * (j & 1);
+    const uint32_t below = (excl[j >> 1] >> sh) & 0xFFFFu;
+    const uint32_t total = (tot[j >> 1] >> sh) & 0xFFFFu;
+    if (nib) {
+      const uint64_t pos = base + below;
+      const uint32_t id = (uint32_t)(tb + 256u * j + 4u * lane);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const unsigned long long bal = __ballot((nib >> i) & 1u);
-      below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, below));
-      total += (uint32_t)__builtin_popcountll(bal);
-    }
-    uint64_t pos = base + below;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if ((nib >> i) & 1u) {
-        if (pos < cap) out[pos] = (uint32_t)(tb + 256u * j + 4u * lane + i);
-        ++pos;
+      for (int i = 0; i < 4; ++i) {
+        if ((nib >> i) & 1u) {
+          const uint64_t p = pos + __builtin_popcount(nib & ((1u << i) - 1u));
+          if (p < cap) out[p] = id + i;
+        }
       }
     }
     base += total;
