@@ -24,7 +24,8 @@ struct Candidate {
 
 std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, bool batch, uint32_t batch_slots) {
   std::vector<Candidate> c;
-  for (uint32_t block : {64u, 128u, 256u}) {
+  for (uint32_t block : {64u, 128u, 256u, 512u}) {
+    if (block == 512 && !batch) continue;   // the scan kernels take at most 256
     int occ = 0;
     const int e = batch ? sel_batch_occupancy(block, batch_slots * 256u * (block / kWave), &occ) : sel_scan_occupancy(occ_mode, block, &occ);
     if (e != 0 || occ < 1) occ = 1;
@@ -176,7 +177,9 @@ sel_status sel_tune_load(sel_ctx* ctx, const char* path) {
     unsigned long long key;
     unsigned block, grid;
     if (std::sscanf(line, "%llu %u %u", &key, &block, &grid) != 3) continue;
-    if (block != 64 && block != 128 && block != 256) continue;
+    // 512 only for the batch kernel (the scan kernels take at most 256)
+    const bool batch_key = (key & 0xFull) == (unsigned long long)TK_BATCH;
+    if (block != 64 && block != 128 && block != 256 && !(block == 512 && batch_key)) continue;
     if (cus && cus != ctx->num_cus) grid = (uint32_t)((uint64_t)grid * ctx->num_cus / cus);
     ctx->tune[key] = sel_launch{block, grid};
   }

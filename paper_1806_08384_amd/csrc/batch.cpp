@@ -79,11 +79,11 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
 namespace {
 
 // Launch shape of a batch: fixed by the caller, else tuned for this
-// (program count, size) class, else as many workgroups of 256 as fit a CU
-// (registers and the plan's LDS slots), at most 16 waves per CU.
+// (program count, size) class, else as many workgroups of 512 as fit a CU
+// (registers and the plan's LDS), at most 16 waves per CU.
 void batch_shape(sel_ctx* ctx, uint32_t nprogs, const BatchPlan& bp, uint32_t& grid,
                  uint32_t& block) {
-  block = 256;
+  block = 512;
   uint64_t g = 0;
   if (ctx->launch_fixed) {
     block = ctx->launch.block;

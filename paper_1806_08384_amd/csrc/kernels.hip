@@ -1035,7 +1035,7 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
 // ticket moves the finished lines out and zeroes them.  Entries may be
 // chunks of tables (row_begin), and lines not finished by this launch keep
 // accumulating: a cooperative scan adds one chunk per launch.
-__global__ void __launch_bounds__(256) k_batch(BatchArgs a) {
+__global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
   // LDS: per-program counters, tables and staged bitmaps, each wave's slots
   extern __shared__ uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

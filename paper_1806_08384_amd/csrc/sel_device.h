@@ -115,7 +115,7 @@ struct CompactArgs {
 // an LDS slot of its own; then each program's combinators run over the
 // slots.  A column is thus read from HBM once per entry, however many
 // programs and leaves use it.
-constexpr uint32_t kBatchSlots = 48;      // LDS slots per wave (256 B each) that
+constexpr uint32_t kBatchSlots = 64;      // LDS slots per wave (256 B each) that
                                           // passes are packed to
 constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
                                           // and 32 validity words
@@ -126,15 +126,15 @@ constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
 // leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
-// most this many words per workgroup in all.  With 48 slots per wave, a
-// 256-thread workgroup of a batch of up to 256 programs holds at most
-// 48 + 31 + 1 (counters) = 80 KB of LDS: two workgroups (eight waves, two
-// per SIMD) share a CU.
-constexpr uint32_t kBatchBmWords = 7936;
+// most this many words per workgroup in all.  The batch kernel runs
+// 512-thread workgroups (eight waves, two per SIMD) that share one set of
+// tables: 8 x 64 slots x 256 B + 28 KB of tables + at most 4 KB of counters
+// = 160 KB, one workgroup per CU.
+constexpr uint32_t kBatchBmWords = 7168;
 constexpr uint32_t kNoLds = 0xFFFFFFFFu;
 // Entry tile ranges are padded to a multiple of this, so that the waves of
-// one workgroup (1, 2 or 4) always work on the same entry.
-constexpr uint32_t kBatchTileAlign = 4;
+// one workgroup (1, 2, 4 or 8) always work on the same entry.
+constexpr uint32_t kBatchTileAlign = 8;
 
 // Combinator op of a batched program: op | p_slot << 8 | v_slot << 20.
 //   D_RANGE    leaf with predicate word in p_slot (any value test)

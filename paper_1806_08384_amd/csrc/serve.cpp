@@ -335,12 +335,12 @@ bool launch_round(sel_server* s) {
   a.ndone = ngroups;
   a.out = (unsigned long long*)((char*)rs.dev + o_out);
   a.slot = rs.slot;
-  const uint32_t block = 256;
+  const uint32_t block = 512;
   const uint32_t lds = bp.lds_bytes(block);
   int occ = 1;
   if (sel_batch_occupancy(block, lds, &occ) != 0 || occ < 1) occ = 1;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(
-      1, std::min<uint64_t>((uint64_t)std::min(occ, 4) * s->ctx->num_cus, (bp.total_tiles + 3) / 4));
+      1, std::min<uint64_t>((uint64_t)std::min(occ, 2) * s->ctx->num_cus, (bp.total_tiles + 7) / 8));
   bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
   ok = ok && bp.launch(a, d_builds, grid, block, s->stream) == 0;
   ok = ok && hipMemcpyAsync(rs.h_out, a.out, (size_t)ngroups * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;

@@ -133,7 +133,7 @@ def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
     assert block in (64, 128, 256) and grid > 0 and ms > 0
     ctx.autotune(*pairs[-1], with_mask=True, reps=2)
     (bb, bg), bms = ctx.autotune_batch(pairs, reps=1)
-    assert bb in (64, 128, 256) and bg > 0
+    assert bb in (64, 128, 256, 512) and bg > 0
     assert ctx.tune_entries >= 3
     assert ctx.count(*pairs[-1]) == want[-1]
     assert ctx.count_batch(pairs) == want
