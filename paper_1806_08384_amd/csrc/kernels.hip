@@ -970,7 +970,10 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
         case D_TRUE: t = ~0u; f = 0; break;
         default: t = 0; f = ~0u; break;  // D_FALSE
       }
-      spill(st, sf, d - 1, tt, tf);
+      if (d > 0) {
+        st[uni(d - 1)] = tt;
+        sf[uni(d - 1)] = tf;
+      }
       tt = t; tf = f;
       ++d;
     } else if (op == D_NOT) {
@@ -978,8 +981,7 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
     } else if (op == D_ISUNK) {
       const uint32_t k = tt | tf; tt = ~k; tf = k;
     } else {
-      uint32_t at, af;
-      fill(st, sf, d - 2, at, af);
+      const uint32_t at = st[uni(d - 2)], af = sf[uni(d - 2)];
       if (op == D_AND) { tt &= at; tf |= af; }
       else { tt |= at; tf &= af; }
       --d;
@@ -1007,9 +1009,7 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
       uint32_t t;
       if (op == D_RANGE) t = wl[((w >> 8) & 0xFFFu) * kWave + lane];
       else t = (op == D_NN_TRUE || op == D_NOTNULL || op == D_TRUE) ? ~0u : 0u;
-#pragma unroll
-      for (int k = 0; k < kMaxDepth; ++k)
-        if (k == d - 1) st[k] = tt;
+      if (d > 0) st[uni(d - 1)] = tt;
       tt = t;
       ++d;
     } else if (op == D_NOT) {
@@ -1017,10 +1017,7 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
     } else if (op == D_ISUNK) {
       tt = 0;
     } else {
-      uint32_t at = 0;
-#pragma unroll
-      for (int k = 0; k < kMaxDepth; ++k)
-        if (k == d - 2) at = st[k];
+      const uint32_t at = st[uni(d - 2)];
       if (op == D_AND) tt &= at;
       else tt |= at;
       --d;
