@@ -202,7 +202,7 @@ def bench_star(ctx, fact_rows, threads, log):
     return res, (dfact, ddims, dims)
 
 
-def bench_serve(ctx, small, fact_dt, star, threads, log, seconds):
+def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=None):
     """Poisson stream (2000 requests/s) of estimate requests, 1-12 programs
     each over the resident tables (1M uniform, 2M, 60M, the 300M fact table
     and the 480M star fact table), 10 % with a push-down with row ids, served
@@ -243,7 +243,7 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds):
         mx = sel.max_rows(tables[tb].nrows, 0.05)
         pd_bufs[tb] = (mx, [torch.empty(max(1, mx), dtype=torch.int32, device="cuda")
                             for _ in range(4)])
-    srv = ctx.server(hbm_budget_bytes=4 << 30)
+    srv = ctx.server(**({"hbm_budget_bytes": 4 << 30} | dict(server_cfg or {})))
     tickets = [None] * len(trace)
     err = []
 

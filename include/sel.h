@@ -326,8 +326,8 @@ typedef struct sel_server_config {
   uint64_t hbm_budget_bytes;   /* device bytes admitted requests may hold (0 = 1 GiB) */
   uint64_t chunk_rows;         /* most rows per cooperative-scan chunk (0 = no cap) */
   uint32_t max_programs;       /* programs in flight (<= 4096; 0 = 4096) */
-  uint32_t rounds_in_flight;   /* rounds queued on the device (1..4; 0 = 2) */
-  uint32_t rounds_per_cycle;   /* chunks per table (0 = 8) */
+  uint32_t rounds_in_flight;   /* rounds queued on the device (1..4; 0 = 1) */
+  uint32_t rounds_per_cycle;   /* chunks per table (0 = 4) */
   uint32_t pad;
 } sel_server_config;
 

@@ -130,7 +130,7 @@ namespace {
 // Rows per chunk of a table: 1/rounds_per_cycle of it, capped by chunk_rows,
 // whole tiles.
 uint64_t chunk_rows_of(const sel_server* s, uint64_t nrows) {
-  const uint64_t r = s->cfg.rounds_per_cycle ? s->cfg.rounds_per_cycle : 8;
+  const uint64_t r = s->cfg.rounds_per_cycle ? s->cfg.rounds_per_cycle : 4;
   uint64_t c = (nrows + r - 1) / r;
   if (s->cfg.chunk_rows) c = std::min<uint64_t>(c, s->cfg.chunk_rows);
   c = std::max<uint64_t>(c, 1);
@@ -359,7 +359,7 @@ bool launch_round(sel_server* s) {
 void worker_main(sel_server* s) {
   (void)hipSetDevice(s->ctx->device);
   const uint32_t depth = std::min<uint32_t>(
-      s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 2, kMaxRoundsInFlight);
+      s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 1, kMaxRoundsInFlight);
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
@@ -447,7 +447,7 @@ sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_ser
   s->ctx = ctx;
   if (cfg) s->cfg = *cfg;
   DeviceGuard g(ctx->device);
-  const uint32_t depth = std::min<uint32_t>(s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 2, kMaxRoundsInFlight);
+  const uint32_t depth = std::min<uint32_t>(s->cfg.rounds_in_flight ? s->cfg.rounds_in_flight : 1, kMaxRoundsInFlight);
   s->slots.resize(depth + 1);
   hipError_t e = hipSuccess;
   const char* where = "";
