@@ -215,3 +215,26 @@ def test_batch_star_programs(sel, ctx):
     for _ in range(2):
         assert b.run() == want
     b.destroy()
+
+
+def test_batch_full_size(sel, ctx):
+    """The batching workload at its full sizes (10k / 2M / 60M / 300M rows,
+    64 programs) in the default launch shape and as a graph: every count
+    equals the threaded oracle."""
+    say("batch full: generating tables")
+    tables = datagen.cfg3_tables(threads=16)
+    dts = [sel.device_table(ctx, t) for t in tables]
+    progs = datagen.cfg3_programs()
+    pairs = [(dts[t], ctx.program(dts[t], tree)) for t, tree in progs]
+    say("batch full: GPU batch")
+    got = ctx.count_batch(pairs)
+    b = ctx.batch(pairs)
+    got_graph = b.run()
+    b.destroy()
+    say("batch full: oracle")
+    orcs = [oracle.Oracle(t) for t in tables]
+    want = [orcs[t].count(tree, threads=16) for t, tree in progs]
+    assert got == want
+    assert got_graph == want
+    del dts, pairs
+    torch.cuda.empty_cache()
