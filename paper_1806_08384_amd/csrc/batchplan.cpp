@@ -47,43 +47,52 @@ constexpr uint64_t kMaxDeviceTable = 1ull << 19;   // entries (2 MB)
 // A table read only where guards hold may be larger: few rows reach it.
 constexpr uint64_t kMaxGuardedDeviceTable = 1ull << 23;   // entries (32 MB)
 
-// Instruction indices of the value-test leaves on columns without NULLs that
-// are top-level factors of the program's conjunction (the program is
-// FALSE wherever one of them is).
-std::vector<size_t> and_factor_leaves(const std::vector<DevInstr>& code) {
-  struct Node { uint32_t op; size_t idx; int a, b; };
+// A program split at its top-level conjunction: the instruction ranges
+// [begin, end) of its AND factors (postfix subtrees are contiguous) and the
+// stack depth each needs.  One factor if the root is not an AND.
+struct Factors {
+  std::vector<std::pair<size_t, size_t>> ranges;
+  std::vector<int> depth;
+  bool ok = false;
+};
+
+Factors split_and(const std::vector<DevInstr>& code) {
+  struct Node { uint32_t op; size_t begin, end; int a, b, depth; };
   std::vector<Node> nodes;
   std::vector<int> st;
+  Factors F;
   for (size_t k = 0; k < code.size(); ++k) {
     const uint32_t op = code[k].op;
     if (op == D_AND || op == D_OR) {
-      if (st.size() < 2) return {};
+      if (st.size() < 2) return F;
       const int b = st.back(); st.pop_back();
       const int a = st.back(); st.pop_back();
-      nodes.push_back(Node{op, k, a, b});
+      nodes.push_back(Node{op, nodes[a].begin, k + 1, a, b,
+                           std::max(nodes[a].depth, 1 + nodes[b].depth)});
     } else if (op == D_NOT || op == D_ISUNK) {
-      if (st.empty()) return {};
+      if (st.empty()) return F;
       const int a = st.back(); st.pop_back();
-      nodes.push_back(Node{op, k, a, -1});
+      nodes.push_back(Node{op, nodes[a].begin, k + 1, a, -1, nodes[a].depth});
     } else {
-      nodes.push_back(Node{op, k, -1, -1});
+      nodes.push_back(Node{op, k, k + 1, -1, -1, 1});
     }
     st.push_back((int)nodes.size() - 1);
   }
-  std::vector<size_t> out;
-  if (st.size() != 1) return out;
+  if (st.size() != 1) return F;
   std::vector<int> todo{st.back()};
   while (!todo.empty()) {
-    const Node& n = nodes[todo.back()];
+    const Node n = nodes[todo.back()];
     todo.pop_back();
     if (n.op == D_AND) {
-      todo.push_back(n.a);
       todo.push_back(n.b);
-    } else if (is_value_test(n.op) && code[n.idx].valid == nullptr) {
-      out.push_back(n.idx);
+      todo.push_back(n.a);
+    } else {
+      F.ranges.push_back({n.begin, n.end});
+      F.depth.push_back(n.depth);
     }
   }
-  return out;
+  F.ok = true;
+  return F;
 }
 
 void type_range(uint32_t t, int64_t& lo, int64_t& hi) {
@@ -121,8 +130,7 @@ struct Pass {
   std::map<const uint32_t*, uint32_t> valid_slot;
   std::vector<std::pair<std::vector<uint32_t>, uint32_t>> progs;  // (ops, acc line)
   uint32_t slots = 0;
-  std::vector<std::vector<uint32_t>> factors;   // per program: slots of its AND factors
-  std::map<uint32_t, uint32_t> slot_uses;       // leaf slot -> references
+  std::vector<uint32_t> inits;   // accumulator slots to reset per tile (| kInitTrue: to ~0)
   std::vector<BatchBitmap> bms;             // staged in LDS
   std::map<const void*, uint32_t> bm_at;    // source -> its BatchBitmap
   uint32_t bm_words = 0;
@@ -133,7 +141,6 @@ struct Pass {
   // then the bitmaps of the remaining leaves.  Table leaves move to the
   // front of their column.
   void finalize() {
-    set_guards();
     std::vector<PassCol*> order;
     for (PassCol& c : cols) order.push_back(&c);
     std::stable_sort(order.begin(), order.end(),
@@ -217,20 +224,56 @@ struct Pass {
     L.n = (uint32_t)words * 32;   // index of a zero bit past the copy
   }
 
+  // A program's plan in this pass: its direct factors (single value-test
+  // leaves on narrow columns, applied straight to the program's accumulator
+  // words), the other factors in the order they are emitted, and whether
+  // no column it reads has NULLs.
+  struct Split {
+    std::vector<size_t> direct;
+    std::vector<std::pair<size_t, size_t>> rest;
+    bool two = true;
+  };
+  static Split split(const sel_program* p) {
+    Split S;
+    const std::vector<DevInstr>& code = p->host_code;
+    for (const DevInstr& I : code)
+      if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid) S.two = false;
+    Factors F = split_and(code);
+    if (!F.ok) {
+      S.rest.push_back({0, code.size()});
+      return S;
+    }
+    std::vector<std::pair<int, std::pair<size_t, size_t>>> rest;
+    for (size_t k = 0; k < F.ranges.size(); ++k) {
+      const auto r = F.ranges[k];
+      const DevInstr& I = code[r.first];
+      if (r.second == r.first + 1 && is_value_test(I.op) && I.type != T_I64) S.direct.push_back(r.first);
+      else rest.push_back({F.depth[k], r});
+    }
+    // deepest factor first: the chain then needs no more stack than the
+    // program did
+    std::stable_sort(rest.begin(), rest.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& r : rest) S.rest.push_back(r.second);
+    return S;
+  }
   // slots a program would add to this pass
   uint32_t new_slots(const sel_program* p) const {
+    const Split S = split(p);
     std::vector<LeafKey> nl;
     std::vector<const uint32_t*> nv;
-    for (const DevInstr& I : p->host_code) {
-      if (is_value_test(I.op)) {
-        const LeafKey k = key_of(I);
-        if (!leaf_slot.count(k) && std::find(nl.begin(), nl.end(), k) == nl.end()) nl.push_back(k);
+    for (const auto& r : S.rest)
+      for (size_t k = r.first; k < r.second; ++k) {
+        const DevInstr& I = p->host_code[k];
+        if (!is_value_test(I.op)) continue;
+        const LeafKey key = key_of(I);
+        if (!leaf_slot.count(key) && std::find(nl.begin(), nl.end(), key) == nl.end()) nl.push_back(key);
       }
+    for (const DevInstr& I : p->host_code)
       if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid && !valid_slot.count(I.valid) &&
           std::find(nv.begin(), nv.end(), I.valid) == nv.end())
         nv.push_back(I.valid);
-    }
-    return (uint32_t)(nl.size() + nv.size());
+    const uint32_t acc = S.direct.empty() ? 0u : (S.two ? 1u : 2u);
+    return (uint32_t)(nl.size() + nv.size()) + acc;
   }
   uint32_t vslot_of(const DevInstr& I) {
     if (!I.valid) return kNoSlot;
@@ -253,49 +296,74 @@ struct Pass {
     home->vslot = s;
     return s;
   }
-  void add(const sel_program* p, uint32_t acc) {
-    std::vector<uint32_t> ops;
-    ops.reserve(p->host_code.size());
-    const std::vector<size_t> fidx = and_factor_leaves(p->host_code);
-    std::vector<uint32_t> fslots;
-    for (size_t pc = 0; pc < p->host_code.size(); ++pc) {
-      const DevInstr& I = p->host_code[pc];
+  PassCol& home_of(const DevInstr& I) {
+    for (PassCol& c : cols)
+      if (c.data == I.data) return c;
+    cols.push_back(PassCol{});
+    cols.back().data = I.data;
+    cols.back().type = I.type;
+    return cols.back();
+  }
+  // ops of instructions [b, e) of a program, leaves shared across programs
+  void emit(const std::vector<DevInstr>& code, size_t b, size_t e, std::vector<uint32_t>& ops) {
+    for (size_t pc = b; pc < e; ++pc) {
+      const DevInstr& I = code[pc];
       const uint32_t op = I.op;
       if (is_value_test(op)) {
         const LeafKey k = key_of(I);
         auto it = leaf_slot.find(k);
-        uint32_t s;
+        uint32_t sl;
         if (it != leaf_slot.end()) {
-          s = it->second;
+          sl = it->second;
         } else {
-          s = slots++;
-          leaf_slot[k] = s;
-          PassCol* home = nullptr;
-          for (PassCol& c : cols)
-            if (c.data == I.data) { home = &c; break; }
-          if (!home) {
-            cols.push_back(PassCol{});
-            home = &cols.back();
-            home->data = I.data;
-            home->type = I.type;
-          }
+          sl = slots++;
+          leaf_slot[k] = sl;
           DevInstr L = I;
           L.flags = kNoGuard;
-          L.slot = s;
+          L.slot = sl;
           L.lds_word = kNoLds;
-          home->leaves.push_back(L);
+          home_of(I).leaves.push_back(L);
         }
-        slot_uses[s] += 1;
-        if (std::find(fidx.begin(), fidx.end(), pc) != fidx.end()) fslots.push_back(s);
-        ops.push_back(batch_op(D_RANGE, s, vslot_of(I)));
+        ops.push_back(batch_op(D_RANGE, sl, vslot_of(I)));
       } else if (is_null_test(op)) {
         ops.push_back(batch_op(op, 0, vslot_of(I)));
       } else {
         ops.push_back(batch_op(op, 0, 0));
       }
     }
-    // a value-test leaf that is the right operand of the AND / OR right
-    // after it combines with the top of the stack directly
+  }
+  void add(const sel_program* p, uint32_t acc) {
+    const std::vector<DevInstr>& code = p->host_code;
+    const Split S = split(p);
+    std::vector<uint32_t> ops;
+    ops.reserve(code.size() + 2);
+    for (size_t k = 0; k < S.rest.size(); ++k) {
+      emit(code, S.rest[k].first, S.rest[k].second, ops);
+      if (k > 0) ops.push_back(batch_op(D_AND, 0, 0));
+    }
+    if (!S.direct.empty()) {
+      // the program's accumulator: TRUE word (reset to ~0 per tile) and, if
+      // a column has NULLs, FALSE word (reset to 0); each direct factor ANDs
+      // into it when its column is evaluated, and a direct bitmap factor
+      // skips lookups on rows the accumulator already holds FALSE
+      const uint32_t ts = slots++;
+      const uint32_t fs = S.two ? kNoSlot : slots++;
+      inits.push_back(ts | kInitTrue);
+      if (fs != kNoSlot) inits.push_back(fs);
+      for (size_t pc : S.direct) {
+        const DevInstr& I = code[pc];
+        const uint32_t vs = vslot_of(I);
+        DevInstr L = I;
+        L.flags = I.op == D_BITMAP ? kAccGuard : kNoGuard;
+        L.slot = kAccTarget | ((vs == kNoSlot ? kAccNoValid : vs) << 24) | (fs << 12) | ts;
+        L.lds_word = kNoLds;
+        home_of(I).leaves.push_back(L);
+      }
+      ops.push_back(batch_op(B_ACC, ts, fs));
+      if (!S.rest.empty()) ops.push_back(batch_op(D_AND, 0, 0));
+    }
+    // a value-test leaf (or the accumulator) that is the right operand of
+    // the AND / OR right after it combines with the top of the stack directly
     std::vector<uint32_t> fused;
     fused.reserve(ops.size());
     for (size_t k = 0; k < ops.size(); ++k) {
@@ -303,38 +371,14 @@ struct Pass {
       if (op == D_RANGE && (next == D_AND || next == D_OR)) {
         fused.push_back((ops[k] & ~0xFFu) | (next == D_AND ? B_AND_LEAF : B_OR_LEAF));
         ++k;
+      } else if (op == B_ACC && next == D_AND) {
+        fused.push_back((ops[k] & ~0xFFu) | B_AND_ACC);
+        ++k;
       } else {
         fused.push_back(ops[k]);
       }
     }
     progs.emplace_back(std::move(fused), acc);
-    factors.push_back(std::move(fslots));
-  }
-
-  // Guards: a bitmap leaf that only one program uses, as a factor of its
-  // conjunction, need not look up rows where a factor on an earlier column
-  // is already FALSE (the program is FALSE there whatever the leaf says);
-  // those rows read word 0 instead, so the gather collapses.
-  void set_guards() {
-    std::map<uint32_t, std::pair<size_t, size_t>> where;   // slot -> (column, leaf)
-    for (size_t c = 0; c < cols.size(); ++c)
-      for (size_t k = 0; k < cols[c].leaves.size(); ++k) where[cols[c].leaves[k].slot] = {c, k};
-    for (const std::vector<uint32_t>& f : factors) {
-      for (uint32_t s : f) {
-        if (slot_uses[s] != 1) continue;
-        const auto ws = where.at(s);
-        DevInstr& L = cols[ws.first].leaves[ws.second];
-        if (L.op != D_BITMAP) continue;
-        uint32_t g = kNoGuard;
-        int n = 0;
-        for (uint32_t t : f) {
-          if (t == s || n == 4 || where.at(t).first >= ws.first) continue;
-          g = (g & ~(0xFFu << (8 * n))) | (t << (8 * n));
-          ++n;
-        }
-        L.flags = g;
-      }
-    }
   }
 };
 
@@ -374,6 +418,9 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     e.col_begin = (uint32_t)cols.size();
     e.col_count = (uint32_t)ps.cols.size();
     e.ntiles = tiles;
+    e.init_begin = (uint32_t)ops.size();
+    e.init_count = (uint32_t)ps.inits.size();
+    ops.insert(ops.end(), ps.inits.begin(), ps.inits.end());
     e.bm_begin = (uint32_t)bms.size();
     e.bm_count = (uint32_t)ps.bms.size();
     bms.insert(bms.end(), ps.bms.begin(), ps.bms.end());
@@ -503,6 +550,7 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
   a.leaves = (const DevInstr*)(dev + o_leaves);
   a.progs = (const BatchProg*)(dev + o_progs);
   a.bms = (const BatchBitmap*)(dev + o_bms);
+  a.ops = (const uint32_t*)(dev + o_ops);
   a.ntables = (uint32_t)entries.size();
   a.nprogs = (uint32_t)progs.size();
   a.total_tiles = total_tiles;

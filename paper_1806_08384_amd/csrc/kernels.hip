@@ -666,11 +666,43 @@ __device__ __forceinline__ void seg_issue(Seg& r, uint32_t& V, const CONSTANT Ba
   if (h == 0 && C->vslot != kNoSlot) V = valid_bits<true>(C->valid, tb, lane, tb + kTileRows);
 }
 
+// Rows a direct factor of a conjunction still needs tested: those its
+// program's accumulator does not already hold FALSE.
+__device__ __forceinline__ uint32_t acc_need(uint32_t sl, const uint32_t* wl, uint32_t lane) {
+  const uint32_t ts = sl & 0xFFFu, fs = (sl >> 12) & 0xFFFu;
+  return fs != kNoSlot ? ~wl[fs * kWave + lane] : wl[ts * kWave + lane];
+}
+
+// Stores a leaf's truth word: into its slot, or for a direct factor of a
+// conjunction into its program's accumulator (TRUE &= P on non-NULL rows,
+// FALSE |= NOT P on non-NULL rows).
+__device__ __forceinline__ void put_leaf(uint32_t* wl, uint32_t lane, uint32_t sl, uint32_t P) {
+  if (sl & kAccTarget) {
+    const uint32_t ts = sl & 0xFFFu, fs = (sl >> 12) & 0xFFFu, vs = (sl >> 24) & 0x7Fu;
+    const uint32_t V = vs == kAccNoValid ? ~0u : wl[vs * kWave + lane];
+    wl[ts * kWave + lane] &= P & V;
+    if (fs != kNoSlot) wl[fs * kWave + lane] |= ~P & V;
+  } else {
+    wl[sl * kWave + lane] = P;
+  }
+}
+
+// Resets the accumulators of an entry's programs for a new tile.
+__device__ __forceinline__ void reset_acc(const CONSTANT BatchTable* E, const CONSTANT uint32_t* ops,
+                                          uint32_t* wl, uint32_t lane) {
+  const uint32_t ib = E->init_begin, in = E->init_count;
+  for (uint32_t k = 0; k < in; ++k) {
+    const uint32_t w = ops[ib + k];
+    wl[(w & 0xFFFu) * kWave + lane] = (w & kInitTrue) ? ~0u : 0u;
+  }
+}
+
 // Value tests of one leaf on a segment: bits [0, nb) of the result, highest
-// row first.  A bitmap leaf in global memory may carry a guard (slots of
-// factors on earlier columns): rows outside it read word 0 and test FALSE.
-// `gshift` places the segment's rows in the guard word (16 for the upper
-// half of an int64 column).
+// row first.  A bitmap leaf in global memory that is a direct factor of a
+// conjunction looks up only rows its program's accumulator does not hold
+// FALSE; the others read word 0 and test FALSE.  `gshift` places the
+// segment's rows in the guard word (16 for the upper half of an int64
+// column).
 template <int TY>
 __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I,
                                              const uint32_t* bmlds, const uint32_t* wl,
@@ -726,15 +758,7 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
   } else {  // D_BITMAP in global memory
     const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
     uint32_t need = ~0u;
-    const uint32_t gd = I->flags;
-    if (gd != kNoGuard) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const uint32_t gs = (gd >> (8 * k)) & 0xFFu;
-        if (gs != 0xFFu) need &= wl[gs * kWave + lane];
-      }
-      need >>= gshift;
-    }
+    if (I->flags == kAccGuard) need = acc_need(I->slot, wl, lane) >> gshift;
 #pragma unroll
     for (int b = nb - 1; b >= 0; --b) {
       uint64_t d;
@@ -793,14 +817,19 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
   for (uint32_t k = tabled ? C->tab_count : 0u; k < ln; ++k) {
     CInstr I = leaves + lb + k;
     const uint32_t op = I->op;
-    uint32_t* w = wl + I->slot * kWave + lane;
     if (op == D_INLIST) {
-      if (TY != T_I64 || h == 1) *w = leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u, StageView{});
+      if (TY != T_I64 || h == 1)
+        put_leaf(wl, lane, I->slot, leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u, StageView{}));
       continue;
     }
     const uint32_t P = seg_leaf<TY>(r, op, I, bmlds, wl, lane, TY == T_I64 && h == 0 ? 16 : 0);
-    if (TY != T_I64 || h == 0) *w = P;
-    else *w = (*w << 16) | P;
+    if constexpr (TY != T_I64) {
+      put_leaf(wl, lane, I->slot, P);
+    } else {  // int64 leaves always have a slot of their own
+      uint32_t* w = wl + I->slot * kWave + lane;
+      if (h == 0) *w = P;
+      else *w = (*w << 16) | P;
+    }
   }
   if constexpr (TY != T_I64) {
     const GLOBAL uint32_t* gtab = gptr<uint32_t>(C->gtab);
@@ -821,16 +850,7 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
           // rows some table leaf needs: the union of the leaves' guards
           need = 0;
           const uint32_t m = C->tab_count;
-          for (uint32_t i = 0; i < m; ++i) {
-            const uint32_t gd = leaves[lb + i].flags;
-            uint32_t g = ~0u;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              const uint32_t gs = (gd >> (8 * k)) & 0xFFu;
-              if (gs != 0xFFu) g &= wl[gs * kWave + lane];
-            }
-            need |= g;
-          }
+          for (uint32_t i = 0; i < m; ++i) need |= acc_need(leaves[lb + i].slot, wl, lane);
         }
 #pragma unroll
         for (int b = 0; b < 32; ++b) {
@@ -845,17 +865,17 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
         transpose32<8>(T);
 #pragma unroll
         for (int i = 0; i < 8; ++i)
-          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
       } else if (m <= 16) {
         transpose32<16>(T);
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
       } else {
         transpose32<32>(T);
 #pragma unroll
         for (int i = 0; i < 32; ++i)
-          if ((uint32_t)i < m) wl[leaves[lb + i].slot * kWave + lane] = T[i];
+          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
       }
     }
   }
@@ -867,8 +887,9 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
 __device__ __forceinline__ void entry_leaves_full(const CONSTANT BatchTable* E,
                                                   const CONSTANT BatchCol* cols, CInstr leaves,
                                                   uint64_t tb, uint32_t lane, uint32_t* wl,
-                                                  const uint32_t* bmlds) {
+                                                  const uint32_t* bmlds, const CONSTANT uint32_t* ops) {
   const uint32_t cb = E->col_begin, cn = E->col_count;
+  reset_acc(E, ops, wl, lane);
   // columns that only null tests read: validity alone
   for (uint32_t c = 0; c < cn; ++c) {
     const CONSTANT BatchCol* C = cols + cb + c;
@@ -916,11 +937,15 @@ __device__ __forceinline__ void entry_leaves_full(const CONSTANT BatchTable* E,
 __device__ __forceinline__ void entry_leaves_partial(const CONSTANT BatchTable* E,
                                                      const CONSTANT BatchCol* cols, CInstr leaves,
                                                      uint64_t tb, uint32_t lane, uint64_t nrows,
-                                                     uint32_t* wl) {
+                                                     uint32_t* wl, const CONSTANT uint32_t* ops) {
   const uint32_t cb = E->col_begin, cn = E->col_count;
+  reset_acc(E, ops, wl, lane);
   for (uint32_t c = 0; c < cn; ++c) {
     const CONSTANT BatchCol* C = cols + cb + c;
     const uint32_t lb = C->leaf_begin, ln = C->leaf_count;
+    // validity first: direct factors read it when they are stored
+    const uint32_t vs = C->vslot;
+    if (vs != kNoSlot) wl[vs * kWave + lane] = valid_bits<false>(C->valid, tb, lane, nrows);
     for (uint32_t k = 0; k < ln; ++k) {
       CInstr I = leaves + lb + k;
       uint32_t P;
@@ -930,10 +955,8 @@ __device__ __forceinline__ void entry_leaves_partial(const CONSTANT BatchTable* 
         case T_I32: P = leaf_pred<T_I32, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
         default: P = leaf_pred<T_I64, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
       }
-      wl[I->slot * kWave + lane] = P;
+      put_leaf(wl, lane, I->slot, P);
     }
-    const uint32_t vs = C->vslot;
-    if (vs != kNoSlot) wl[vs * kWave + lane] = valid_bits<false>(C->valid, tb, lane, nrows);
   }
 }
 
@@ -947,12 +970,26 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
   for (uint32_t pc = 0; pc < nops; ++pc) {
     const uint32_t w = ops[pc];
     const uint32_t op = w & 0xFFu;
-    if (op >= B_AND_LEAF) {
+    if (op == B_AND_LEAF || op == B_OR_LEAF) {
       const uint32_t vs = w >> 20;
       const uint32_t V = vs == kNoSlot ? ~0u : wl[vs * kWave + lane];
       const uint32_t P = wl[((w >> 8) & 0xFFFu) * kWave + lane];
       if (op == B_AND_LEAF) { tt &= P & V; tf |= ~P & V; }
       else { tt |= P & V; tf &= ~P & V; }
+    } else if (op == B_ACC || op == B_AND_ACC) {
+      const uint32_t fs = w >> 20;
+      const uint32_t T = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+      const uint32_t F = fs == kNoSlot ? ~T : wl[fs * kWave + lane];
+      if (op == B_AND_ACC) {
+        tt &= T; tf |= F;
+      } else {
+        if (d > 0) {
+          st[uni(d - 1)] = tt;
+          sf[uni(d - 1)] = tf;
+        }
+        tt = T; tf = F;
+        ++d;
+      }
     } else if (op < D_AND || op == D_TRUE || op == D_FALSE) {
       uint32_t t, f;
       const uint32_t vs = w >> 20;
@@ -1001,10 +1038,17 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
   for (uint32_t pc = 0; pc < nops; ++pc) {
     const uint32_t w = ops[pc];
     const uint32_t op = w & 0xFFu;
-    if (op >= B_AND_LEAF) {
+    if (op >= B_AND_LEAF) {   // fused leaves and the accumulator
       const uint32_t P = wl[((w >> 8) & 0xFFFu) * kWave + lane];
-      if (op == B_AND_LEAF) tt &= P;
-      else tt |= P;
+      if (op == B_AND_LEAF || op == B_AND_ACC) {
+        tt &= P;
+      } else if (op == B_OR_LEAF) {
+        tt |= P;
+      } else {  // B_ACC
+        if (d > 0) st[uni(d - 1)] = tt;
+        tt = P;
+        ++d;
+      }
     } else if (op < D_AND || op == D_TRUE || op == D_FALSE) {
       uint32_t t;
       if (op == D_RANGE) t = wl[((w >> 8) & 0xFFFu) * kWave + lane];
@@ -1114,9 +1158,9 @@ __global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
     const bool full = tb + kTileRows <= nrows;
     uint32_t inr = ~0u;
     if (full) {
-      entry_leaves_full(E, cols, leaves, tb, lane, wl, bmlds);
+      entry_leaves_full(E, cols, leaves, tb, lane, wl, bmlds, (const CONSTANT uint32_t*)a.ops);
     } else {
-      entry_leaves_partial(E, cols, leaves, tb, lane, nrows, wl);
+      entry_leaves_partial(E, cols, leaves, tb, lane, nrows, wl, (const CONSTANT uint32_t*)a.ops);
       inr = inrange_bits(tb, lane, nrows);
     }
     // programs in pairs: both popcounts (at most 2048 per wave each) share

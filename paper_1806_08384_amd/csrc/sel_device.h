@@ -120,8 +120,8 @@ constexpr uint32_t kBatchSlots = 64;      // LDS slots per wave (256 B each) tha
 constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
                                           // and 32 validity words
 constexpr uint32_t kNoSlot = 0xFFFu;
-// Batched leaves reuse DevInstr::flags as a guard: up to four slots, one
-// per byte (0xFF = none), whose words AND to the rows that need a lookup.
+// Batched leaves reuse DevInstr::flags for their guard: kNoGuard (test every
+// row) or kAccGuard (below).
 constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
@@ -145,11 +145,30 @@ constexpr uint32_t kBatchTileAlign = 8;
 // v_slot == kNoSlot: the column has no NULLs (validity all ones).
 constexpr uint32_t B_AND_LEAF = 24;
 constexpr uint32_t B_OR_LEAF = 25;
+//   B_ACC        push the program's accumulator: TRUE word in p_slot, FALSE
+//                word in v_slot (kNoSlot: no NULLs, FALSE = NOT TRUE)
+//   B_AND_ACC    top = top AND accumulator
+constexpr uint32_t B_ACC = 26;
+constexpr uint32_t B_AND_ACC = 27;
+
+// A batched leaf whose slot field has kAccTarget set is a direct factor of
+// one program's conjunction: its truth word is ANDed into that program's
+// accumulator (TRUE slot in bits 0..11, FALSE slot in bits 12..23 or
+// kNoSlot, the slot of its column's validity word in bits 24..30 or
+// kAccNoValid) instead of being parked in a slot of its own.
+constexpr uint32_t kAccTarget = 0x80000000u;
+constexpr uint32_t kAccNoValid = 0x7Fu;
+// Its flags field kAccGuard: lookups are needed only on rows the
+// accumulator does not already hold FALSE.
+constexpr uint32_t kAccGuard = 0xFFFFFFFEu;
+// Accumulator reset list entries: slot | kInitTrue (reset to ~0) or slot
+// (reset to 0), once per tile before the first column.
+constexpr uint32_t kInitTrue = 0x80000000u;
 inline constexpr uint32_t batch_op(uint32_t op, uint32_t p, uint32_t v) {
   return op | (p << 8) | (v << 20);
 }
 
-struct BatchTable {            // 64 bytes: one pass over a table or a chunk
+struct BatchTable {            // 80 bytes: one pass over a table or a chunk
   uint64_t nrows;              // rows of the whole table
   uint64_t tile_begin;         // first flat tile index of this entry
   uint64_t row_begin;          // first row of the entry (a multiple of kTileRows)
@@ -162,7 +181,9 @@ struct BatchTable {            // 64 bytes: one pass over a table or a chunk
   uint32_t bm_begin;           // into the BatchBitmap array
   uint32_t bm_count;
   uint32_t ntab;               // columns with a lookup table
-  uint32_t pad;
+  uint32_t init_begin;         // accumulator reset list, in the ops array
+  uint32_t init_count;
+  uint32_t pad[3];
 };
 
 struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS (batch or scan)
@@ -223,6 +244,7 @@ struct BatchArgs {
   const DevInstr* leaves;
   const BatchProg* progs;
   const BatchBitmap* bms;
+  const uint32_t* ops;         // combinator words and accumulator reset lists
   uint32_t ntables;
   uint32_t nprogs;
   uint64_t total_tiles;        // a multiple of kBatchTileAlign
