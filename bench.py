@@ -271,7 +271,7 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
     log(f"serve: {len(trace)} requests over {warm + seconds:.0f} s")
     th = threading.Thread(target=client)
     th.start()
-    lat, mismatches = [], 0
+    lat, mismatches, by_big = [], 0, {}
     for i in range(len(trace)):
         while tickets[i] is None and not err:
             time.sleep(0.0002)
@@ -282,6 +282,9 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
             mismatches += 1
         if i >= n_warm:
             lat.append(ms)
+            big = max([tables[tb].nrows for tb, _ in trace[i][1]] +
+                      ([tables[trace[i][2][0]].nrows] if trace[i][2] else []))
+            by_big.setdefault(big, []).append(ms)
     th.join()
     if err:
         raise err[0]
@@ -321,6 +324,15 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
         "max_ms": stats["max_ms"],
         "rounds": stats["rounds"],
         "programs_per_round": stats["round_programs"] / max(1, stats["rounds"]),
+        "distinct_programs_per_round": stats["round_groups"] / max(1, stats["rounds"]),
+        "round_gpu_ms_mean": stats["round_gpu_ms"] / max(1, stats["rounds"]),
+        "round_host_ms_mean": stats["round_host_ms"] / max(1, stats["rounds"]),
+        "gpu_busy_fraction": (stats["round_gpu_ms"] / (stats["elapsed_s"] * 1e3)
+                              if stats["elapsed_s"] else None),
+        "by_largest_table_rows": {
+            str(k): {"requests": len(v), "p50_ms": percentile(sorted(v), 50),
+                     "p99_ms": percentile(sorted(v), 99)}
+            for k, v in sorted(by_big.items())},
         "shared_rounds": stats["shared_rounds"],
         "max_admitted": stats["max_admitted"],
         "results_equal_alone": True,

@@ -358,6 +358,9 @@ typedef struct sel_server_stats {
   uint32_t pad;
   double p50_ms, p99_ms, mean_ms, max_ms;  /* request latency, submit -> completion */
   double elapsed_s;                    /* first submit -> last completion */
+  uint64_t round_groups;               /* distinct programs summed over rounds */
+  double round_gpu_ms;                 /* device time of the rounds, summed */
+  double round_host_ms;                /* host time planning and launching them */
 } sel_server_stats;
 
 /* Start a server (two worker threads, its own streams and a push-down

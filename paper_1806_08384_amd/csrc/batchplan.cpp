@@ -41,11 +41,11 @@ struct PassCol {
 };
 
 // A device-memory table pays when it stays in L2 (4 MB per XCD): past this
-// many entries, random lookups into it miss and each costs an HBM burst,
-// while separate (guarded) bitmaps of the same leaves are 32 times smaller.
-constexpr uint64_t kMaxDeviceTable = 1ull << 19;   // entries (2 MB)
+// size, random lookups into it miss and each costs an HBM burst, while
+// separate (guarded) bitmaps of the same leaves are 8 to 32 times smaller.
+constexpr uint64_t kMaxDeviceTableBytes = 2ull << 20;
 // A table read only where guards hold may be larger: few rows reach it.
-constexpr uint64_t kMaxGuardedDeviceTable = 1ull << 23;   // entries (32 MB)
+constexpr uint64_t kMaxGuardedDeviceTableBytes = 32ull << 20;
 
 // A program split at its top-level conjunction: the instruction ranges
 // [begin, end) of its AND factors (postfix subtrees are contiguous) and the
@@ -177,12 +177,13 @@ struct Pass {
       // leaf needs; the other rows all read its zero entry
       bool guarded = true;
       for (const DevInstr& L : tab) guarded &= L.flags != kNoGuard;
+      const uint64_t bytes = (n + 1) * tab_entry_bytes((uint32_t)tab.size());
       if (round == 0) {
-        if (n + 1 > kBatchBmWords - bm_words) continue;
+        if ((bytes + 3) / 4 > kBatchBmWords - bm_words) continue;
         c->tab_word = bm_words;
-        bm_words += (uint32_t)n + 1;
+        bm_words += (uint32_t)((bytes + 3) / 4);
       } else {
-        if (n > (guarded ? kMaxGuardedDeviceTable : kMaxDeviceTable)) continue;
+        if (bytes > (guarded ? kMaxGuardedDeviceTableBytes : kMaxDeviceTableBytes)) continue;
         c->gtab = true;
         c->tab_guarded = guarded;
       }
@@ -449,7 +450,8 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
         builds.push_back(tbd);
         col_gtab.back() = gtab_words;
         table_entries += (uint64_t)c.tab_n + 1;
-        gtab_words += ((uint64_t)c.tab_n + 1 + 63) & ~63ull;   // 256-byte aligned tables
+        const uint64_t bytes = ((uint64_t)c.tab_n + 1) * tab_entry_bytes(c.tab_count);
+        gtab_words += ((bytes + 255) & ~255ull) / 4;   // 256-byte aligned tables
       }
       e.ntab += c.tab_word != kNoLds ? 1u : 0u;
       leaves.insert(leaves.end(), c.leaves.begin(), c.leaves.end());

@@ -802,6 +802,43 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32]) {
   transpose_stage<1, NOUT>(a, 0x55555555u);
 }
 
+// The table leaves of a narrow column on one segment: one lookup per row
+// (entries of E: one bit per leaf, NOUT >= the leaf count) serves them all;
+// transposed, word i holds leaf i's truth bits.
+template <class E, int NOUT, int TY>
+__device__ __forceinline__ void tab_leaves(const Seg& r, const CONSTANT BatchCol* C, CInstr tl,
+                                           const uint32_t* bmlds, uint32_t* wl, uint32_t lane) {
+  const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n, m = C->tab_count;
+  uint32_t T[32];
+  if (C->tab_word != kNoLds) {
+    const E* tab = (const E*)(bmlds + C->tab_word);
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+      T[b] = tab[d < n ? d : n];
+    }
+  } else {
+    const GLOBAL E* tab = gptr<E>(C->gtab);
+    uint32_t need = ~0u;
+    if (C->tab_guarded) {
+      // rows some table leaf needs: the union of the leaves' guards
+      need = 0;
+      for (uint32_t i = 0; i < m; ++i) need |= acc_need(tl[i].slot, wl, lane);
+    }
+#pragma unroll
+    for (int b = 0; b < 32; ++b) {
+      const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+      T[b] = tab[d < n && ((need >> b) & 1u) ? d : n];
+    }
+  }
+  // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf i's
+  // word (bit b = row b)
+  transpose32<NOUT>(T);
+#pragma unroll
+  for (int i = 0; i < NOUT; ++i)
+    if ((uint32_t)i < m) put_leaf(wl, lane, tl[i].slot, T[i]);
+}
+
 // Every leaf of one segment; truth words go to the wave's slots.  An int64
 // column's upper half (h = 0) writes bits 16..31, its lower half completes
 // them.  Sparse value lists take the element path once, with the last
@@ -832,51 +869,11 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
     }
   }
   if constexpr (TY != T_I64) {
-    const GLOBAL uint32_t* gtab = gptr<uint32_t>(C->gtab);
-    if (tw != kNoLds || gtab != nullptr) {
-      // one table lookup per row serves every table leaf of the column
-      const uint32_t L32 = (uint32_t)C->tab_lo, n = C->tab_n;
-      uint32_t T[32];
-      if (tw != kNoLds) {
-        const uint32_t* tab = bmlds + tw;
-#pragma unroll
-        for (int b = 0; b < 32; ++b) {
-          const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
-          T[b] = tab[d < n ? d : n];
-        }
-      } else {
-        uint32_t need = ~0u;
-        if (C->tab_guarded) {
-          // rows some table leaf needs: the union of the leaves' guards
-          need = 0;
-          const uint32_t m = C->tab_count;
-          for (uint32_t i = 0; i < m; ++i) need |= acc_need(leaves[lb + i].slot, wl, lane);
-        }
-#pragma unroll
-        for (int b = 0; b < 32; ++b) {
-          const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
-          T[b] = gtab[d < n && ((need >> b) & 1u) ? d : n];
-        }
-      }
-      // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf
-      // i's word (bit b = row b)
+    if (tw != kNoLds || C->gtab != nullptr) {
       const uint32_t m = C->tab_count;
-      if (m <= 8) {
-        transpose32<8>(T);
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
-      } else if (m <= 16) {
-        transpose32<16>(T);
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
-      } else {
-        transpose32<32>(T);
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-          if ((uint32_t)i < m) put_leaf(wl, lane, leaves[lb + i].slot, T[i]);
-      }
+      if (m <= 8) tab_leaves<uint8_t, 8, TY>(r, C, leaves + lb, bmlds, wl, lane);
+      else if (m <= 16) tab_leaves<uint16_t, 16, TY>(r, C, leaves + lb, bmlds, wl, lane);
+      else tab_leaves<uint32_t, 32, TY>(r, C, leaves + lb, bmlds, wl, lane);
     }
   }
 }
@@ -1116,6 +1113,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
         const int64_t L = C->tab_lo;
         CInstr tl = leaves + C->leaf_begin;
         uint32_t* dst = bmlds + C->tab_word;
+        const uint32_t eb = tab_entry_bytes(m);
         for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
           uint32_t w = 0;
           if (i < n) {
@@ -1133,7 +1131,9 @@ __global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
               w |= bit << k;
             }
           }
-          dst[i] = w;
+          if (eb == 1) ((uint8_t*)dst)[i] = (uint8_t)w;
+          else if (eb == 2) ((uint16_t*)dst)[i] = (uint16_t)w;
+          else dst[i] = w;
         }
       }
       for (uint32_t k = 0; k < E->bm_count; ++k) {
@@ -1242,7 +1242,10 @@ __global__ void __launch_bounds__(256) k_tables(const TableBuild* __restrict__ t
         w |= bit << k;
       }
     }
-    B.dst[i] = w;
+    const uint32_t eb = tab_entry_bytes(B.m);
+    if (eb == 1) ((uint8_t*)B.dst)[i] = (uint8_t)w;
+    else if (eb == 2) ((uint16_t*)B.dst)[i] = (uint16_t)w;
+    else B.dst[i] = w;
   }
 }
 

@@ -131,6 +131,9 @@ constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // tables: 8 x 64 slots x 256 B + 28 KB of tables + at most 4 KB of counters
 // = 160 KB, one workgroup per CU.
 constexpr uint32_t kBatchBmWords = 7168;
+// Bytes per lookup-table entry (LDS or device memory): the narrowest of 1,
+// 2 and 4 that holds one bit per table leaf (at most 32).
+inline constexpr uint32_t tab_entry_bytes(uint32_t m) { return m <= 8 ? 1u : m <= 16 ? 2u : 4u; }
 constexpr uint32_t kNoLds = 0xFFFFFFFFu;
 // Entry tile ranges are padded to a multiple of this, so that the waves of
 // one workgroup (1, 2, 4 or 8) always work on the same entry.
@@ -202,9 +205,10 @@ struct BatchCol {              // 64 bytes: a column one entry reads
   uint32_t leaf_begin;         // its leaf tests: DevInstr array, slot field set
   uint32_t leaf_count;
   // Lookup table (narrow columns): its first tab_count leaves are bits
-  // 0 .. tab_count-1 of word min(x - tab_lo, tab_n), at LDS offset tab_word
-  // or, for a table too large for LDS, in device memory at gtab; word tab_n
-  // is zero.  tab_word == kNoLds and gtab == nullptr: no table.
+  // 0 .. tab_count-1 of entry min(x - tab_lo, tab_n), at LDS word offset
+  // tab_word or, for a table too large for LDS, in device memory at gtab;
+  // entry tab_n is zero.  Entries are tab_entry_bytes(tab_count) wide.
+  // tab_word == kNoLds and gtab == nullptr: no table.
   uint32_t tab_word;
   uint32_t tab_count;
   int32_t tab_lo;
@@ -217,7 +221,8 @@ struct BatchCol {              // 64 bytes: a column one entry reads
 
 // A lookup table in device memory, built by k_tables before the batch
 // launch: entry i (i < n) holds bit k = leaf k's test of value lo + i, for
-// the m leaves at `leaves`; entry n is zero.
+// the m leaves at `leaves`; entry n is zero.  Entries are
+// tab_entry_bytes(m) wide.
 struct TableBuild {            // 48 bytes
   uint32_t* dst;
   const DevInstr* leaves;

@@ -81,7 +81,7 @@ struct RoundSlot {                          // per in-flight round
   uint8_t* host = nullptr;                  // pinned staging for descriptors
   selrt::BatchPlan plan;                    // this round's descriptors
   unsigned long long* h_out = nullptr;      // pinned, finished counts
-  hipEvent_t done_ev = nullptr;
+  hipEvent_t start_ev = nullptr, done_ev = nullptr;   // the round's device time
   DevSlot* slot = nullptr;                  // ticket of this slot's launches
   std::vector<Member> members;              // programs this round counts for
   uint32_t ngroups = 0;                     // distinct programs (lines) in it
@@ -116,7 +116,8 @@ struct sel_server {
 
   // statistics
   uint64_t submitted = 0, completed = 0, rejected = 0, rounds = 0, round_programs = 0,
-           shared_rounds = 0;
+           shared_rounds = 0, round_groups = 0;
+  double round_gpu_ms = 0, round_host_ms = 0;
   uint32_t max_admitted = 0;
   std::vector<double> latencies;
   Clock::time_point t_first{}, t_last{};
@@ -212,7 +213,10 @@ void admit_locked(sel_server* s) {
 // every request program attached to it (rounds retire in launch order, so a
 // program's last round retires after all its earlier ones).
 void retire_round(sel_server* s, RoundSlot& rs) {
+  float ms = 0;
+  if (hipEventElapsedTime(&ms, rs.start_ev, rs.done_ev) != hipSuccess) ms = 0;
   std::lock_guard<std::mutex> lk(s->mu);
+  s->round_gpu_ms += ms;
   for (const Member& m : rs.members) {
     m.a.req->counts[m.a.index] += rs.h_out[m.group];
     if (m.last) {
@@ -242,6 +246,7 @@ bool wait_oldest(sel_server* s) {
 // by different requests are evaluated once per chunk; their chunk count is
 // handed to each of them.
 bool launch_round(sel_server* s) {
+  const Clock::time_point t0 = Clock::now();
   RoundSlot& rs = s->slots[s->next_slot];
   BatchPlan& bp = rs.plan;
   bp.clear();
@@ -290,6 +295,7 @@ bool launch_round(sel_server* s) {
     }
     rs.ngroups = ngroups;
     s->rounds += 1;
+    s->round_groups += ngroups;
     s->round_programs += rs.members.size();
     waits.swap(s->round_waits);
   }
@@ -341,7 +347,8 @@ bool launch_round(sel_server* s) {
   if (sel_batch_occupancy(block, lds, &occ) != 0 || occ < 1) occ = 1;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(
       1, std::min<uint64_t>((uint64_t)std::min(occ, 2) * s->ctx->num_cus, (bp.total_tiles + 7) / 8));
-  bool ok = hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
+  bool ok = hipEventRecord(rs.start_ev, s->stream) == hipSuccess;
+  ok = ok && hipMemcpyAsync(rs.dev, rs.host, o_out, hipMemcpyHostToDevice, s->stream) == hipSuccess;
   ok = ok && bp.launch(a, d_builds, grid, block, s->stream) == 0;
   ok = ok && hipMemcpyAsync(rs.h_out, a.out, (size_t)ngroups * 8, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
   ok = ok && hipEventRecord(rs.done_ev, s->stream) == hipSuccess;
@@ -351,6 +358,10 @@ bool launch_round(sel_server* s) {
     return false;
   }
   rs.busy = true;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->round_host_ms += std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+  }
   s->inflight.push_back(s->next_slot);
   s->next_slot = (s->next_slot + 1) % (uint32_t)s->slots.size();
   return true;
@@ -420,6 +431,7 @@ void pd_worker_main(sel_server* s) {
 void release_server(sel_server* s) {
   for (RoundSlot& rs : s->slots) {
     if (rs.done_ev) (void)hipEventDestroy(rs.done_ev);
+    if (rs.start_ev) (void)hipEventDestroy(rs.start_ev);
     if (rs.dev) (void)hipFree(rs.dev);
     if (rs.host) (void)hipHostFree(rs.host);
     if (rs.h_out) (void)hipHostFree(rs.h_out);
@@ -459,7 +471,8 @@ sel_status sel_server_create(sel_ctx* ctx, const sel_server_config* cfg, sel_ser
     if ((e = hipMemset(s->d_acc, 0, acc_bytes + slot_bytes)) != hipSuccess) { where = "hipMemset(server)"; break; }
     for (size_t k = 0; k < s->slots.size(); ++k) {
       s->slots[k].slot = (DevSlot*)((char*)s->d_acc + acc_bytes + 256 * k);
-      if ((e = hipEventCreateWithFlags(&s->slots[k].done_ev, hipEventDisableTiming)) != hipSuccess) { where = "hipEventCreate"; break; }
+      if ((e = hipEventCreate(&s->slots[k].done_ev)) != hipSuccess ||
+          (e = hipEventCreate(&s->slots[k].start_ev)) != hipSuccess) { where = "hipEventCreate"; break; }
     }
   } while (0);
   if (e != hipSuccess) {
@@ -594,6 +607,9 @@ sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset)
   out->round_programs = s->round_programs;
   out->shared_rounds = s->shared_rounds;
   out->max_admitted = s->max_admitted;
+  out->round_groups = s->round_groups;
+  out->round_gpu_ms = s->round_gpu_ms;
+  out->round_host_ms = s->round_host_ms;
   std::vector<double> v = s->latencies;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
@@ -611,6 +627,8 @@ sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset)
   if (s->any && s->completed) out->elapsed_s = std::chrono::duration<double>(s->t_last - s->t_first).count();
   if (reset) {
     s->submitted = s->completed = s->rejected = s->rounds = s->round_programs = s->shared_rounds = 0;
+    s->round_groups = 0;
+    s->round_gpu_ms = s->round_host_ms = 0;
     s->max_admitted = s->admitted;
     s->latencies.clear();
     s->any = false;
