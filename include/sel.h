@@ -395,7 +395,7 @@ void sel_server_destroy(sel_server* s);
 /* ---- launch configuration and timing ------------------------------------ */
 
 typedef struct sel_launch {
-  uint32_t block;        /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+  uint32_t block;        /* threads per workgroup: 64, 128 or 256 */
   uint32_t grid;         /* workgroups; 0 = library default                   */
 } sel_launch;
 
@@ -414,7 +414,8 @@ sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch);
 sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
                         int with_mask, uint32_t reps, sel_launch* best, double* best_ms);
 
-/* Same for the batched count of these n pairs (see sel_count_batch). */
+/* Same for the batched count of these n pairs (see sel_count_batch), with
+ * workgroups of 64 to 768 threads whose LDS fits the batch's plan. */
 sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
                               const sel_program* const* progs, uint32_t reps,
                               sel_launch* best, double* best_ms);

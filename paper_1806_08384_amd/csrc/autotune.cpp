@@ -22,12 +22,16 @@ struct Candidate {
   uint32_t block, grid;
 };
 
-std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, bool batch, uint32_t batch_slots) {
+// Launch shapes to time: for a batch (bp != nullptr) the workgroup sizes
+// whose LDS fits the plan.
+std::vector<Candidate> candidates(sel_ctx* ctx, int occ_mode, const BatchPlan* bp) {
   std::vector<Candidate> c;
-  for (uint32_t block : {64u, 128u, 256u, 512u}) {
-    if (block == 512 && !batch) continue;   // the scan kernels take at most 256
+  const bool batch = bp != nullptr;
+  for (uint32_t block : {64u, 128u, 256u, 512u, kBatchBlock}) {
+    if (block > 256 && !batch) continue;   // the scan kernels take at most 256
+    if (batch && bp->lds_bytes(block) > kLdsPerCu) continue;
     int occ = 0;
-    const int e = batch ? sel_batch_occupancy(block, batch_slots * 256u * (block / kWave), &occ) : sel_scan_occupancy(occ_mode, block, &occ);
+    const int e = batch ? sel_batch_occupancy(block, bp->lds_bytes(block), &occ) : sel_scan_occupancy(occ_mode, block, &occ);
     if (e != 0 || occ < 1) occ = 1;
     const int max_waves = occ * (int)(block / kWave);
     for (int waves : {4, 8, 12, 16, 20, 24, 32}) {
@@ -110,7 +114,7 @@ sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program*
   Candidate b{256, 0};
   double ms = 0;
   const uint64_t need_waves = std::max<uint64_t>(1, ntiles);
-  sel_status st = time_candidates(ctx, candidates(ctx, mode, false, 0), reps, [&](const Candidate& c) {
+  sel_status st = time_candidates(ctx, candidates(ctx, mode, nullptr), reps, [&](const Candidate& c) {
     const uint64_t need = (need_waves + c.block / kWave - 1) / (c.block / kWave);
     return sel_launch_scan(mode, a, (uint32_t)std::min<uint64_t>(c.grid, need), c.block, ctx->stream);
   }, b, ms);
@@ -137,7 +141,7 @@ sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* 
   DeviceGuard g(ctx->device);
   Candidate b{256, 0};
   double ms = 0;
-  sel_status st = time_candidates(ctx, candidates(ctx, 0, true, bp.max_slots), reps, [&](const Candidate& c) {
+  sel_status st = time_candidates(ctx, candidates(ctx, 0, &bp), reps, [&](const Candidate& c) {
     ctx->launch = sel_launch{c.block, c.grid};
     ctx->launch_fixed = true;
     return (int)sel_count_batch(ctx, n, tables, progs, out.data()) == SEL_OK ? 0 : 1;
@@ -177,9 +181,11 @@ sel_status sel_tune_load(sel_ctx* ctx, const char* path) {
     unsigned long long key;
     unsigned block, grid;
     if (std::sscanf(line, "%llu %u %u", &key, &block, &grid) != 3) continue;
-    // 512 only for the batch kernel (the scan kernels take at most 256)
+    // 512 and kBatchBlock only for the batch kernel (the scan kernels take
+    // at most 256)
     const bool batch_key = (key & 0xFull) == (unsigned long long)TK_BATCH;
-    if (block != 64 && block != 128 && block != 256 && !(block == 512 && batch_key)) continue;
+    if (block != 64 && block != 128 && block != 256 &&
+        !((block == 512 || block == kBatchBlock) && batch_key)) continue;
     if (cus && cus != ctx->num_cus) grid = (uint32_t)((uint64_t)grid * ctx->num_cus / cus);
     ctx->tune[key] = sel_launch{block, grid};
   }

@@ -79,11 +79,12 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
 namespace {
 
 // Launch shape of a batch: fixed by the caller, else tuned for this
-// (program count, size) class, else as many workgroups of 512 as fit a CU
-// (registers and the plan's LDS), at most 16 waves per CU.
+// (program count, size) class, else as many workgroups of the plan's
+// default size as fit a CU (registers and the plan's LDS), at most 16 waves
+// per CU.  A block whose LDS would not fit the plan falls back to 512.
 void batch_shape(sel_ctx* ctx, uint32_t nprogs, const BatchPlan& bp, uint32_t& grid,
                  uint32_t& block) {
-  block = 512;
+  block = bp.default_block();
   uint64_t g = 0;
   if (ctx->launch_fixed) {
     block = ctx->launch.block;
@@ -94,6 +95,10 @@ void batch_shape(sel_ctx* ctx, uint32_t nprogs, const BatchPlan& bp, uint32_t& g
       block = it->second.block;
       g = it->second.grid;
     }
+  }
+  if (bp.lds_bytes(block) > kLdsPerCu) {
+    block = 512;
+    g = 0;
   }
   if (g == 0) {
     int occ = 1;

@@ -1073,7 +1073,7 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
 // ticket moves the finished lines out and zeroes them.  Entries may be
 // chunks of tables (row_begin), and lines not finished by this launch keep
 // accumulating: a cooperative scan adds one chunk per launch.
-__global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
+__global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   // LDS: per-program counters, tables and staged bitmaps, each wave's slots
   extern __shared__ uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1090,7 +1090,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchArgs a) {
   const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
   const CONSTANT BatchBitmap* bms = (const CONSTANT BatchBitmap*)a.bms;
   // the workgroup takes groups of nw consecutive tiles; entry ranges are
-  // padded to multiples of 4, so a group never straddles two entries and the
+  // padded to multiples of kBatchTileAlign, so a group never straddles two entries and the
   // loop below (with its barriers) is uniform over the workgroup
   const uint64_t ngroups = a.total_tiles / nw;
   uint32_t staged = 0xFFFFFFFFu;

@@ -217,6 +217,9 @@ struct BatchPlan {
   uint32_t lds_bytes(uint32_t block) const {
     return 4u * (acc_words() + max_bm_words) + max_slots * 256u * (block / 64);
   }
+  // Workgroup size: kBatchBlock when its LDS fits a CU, else 512 (a pass
+  // with more than kBatchSlots slots).
+  uint32_t default_block() const { return lds_bytes(sel::kBatchBlock) <= sel::kLdsPerCu ? sel::kBatchBlock : 512u; }
 };
 
 // LDS slots a program needs in a pass of its own (distinct leaves plus

@@ -115,10 +115,11 @@ struct CompactArgs {
 // an LDS slot of its own; then each program's combinators run over the
 // slots.  A column is thus read from HBM once per entry, however many
 // programs and leaves use it.
-constexpr uint32_t kBatchSlots = 64;      // LDS slots per wave (256 B each) that
+constexpr uint32_t kBatchSlots = 40;      // LDS slots per wave (256 B each) that
                                           // passes are packed to
 constexpr uint32_t kBatchMaxSlots = 64;   // one program alone: at most 32 leaves
-                                          // and 32 validity words
+                                          // and 32 validity words (its pass then
+                                          // runs in 512-thread workgroups)
 constexpr uint32_t kNoSlot = 0xFFFu;
 // Batched leaves reuse DevInstr::flags for their guard: kNoGuard (test every
 // row) or kAccGuard (below).
@@ -126,18 +127,21 @@ constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
 // leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
-// most this many words per workgroup in all.  The batch kernel runs
-// 512-thread workgroups (eight waves, two per SIMD) that share one set of
-// tables: 8 x 64 slots x 256 B + 28 KB of tables + at most 4 KB of counters
-// = 160 KB, one workgroup per CU.
+// most this many words per workgroup in all.  The batch kernel runs one
+// workgroup per CU whose waves share one set of tables: 768 threads (twelve
+// waves, three per SIMD) when every pass fits 40 slots, 12 x 40 slots x
+// 256 B + 28 KB of tables + at most 4 KB of counters = 152 KB; else 512
+// threads with up to 64 slots, 8 x 64 x 256 B + 32 KB = 160 KB.
 constexpr uint32_t kBatchBmWords = 7168;
+constexpr uint32_t kBatchBlock = 768;
+constexpr uint32_t kLdsPerCu = 160u * 1024u;
 // Bytes per lookup-table entry (LDS or device memory): the narrowest of 1,
 // 2 and 4 that holds one bit per table leaf (at most 32).
 inline constexpr uint32_t tab_entry_bytes(uint32_t m) { return m <= 8 ? 1u : m <= 16 ? 2u : 4u; }
 constexpr uint32_t kNoLds = 0xFFFFFFFFu;
 // Entry tile ranges are padded to a multiple of this, so that the waves of
-// one workgroup (1, 2, 4 or 8) always work on the same entry.
-constexpr uint32_t kBatchTileAlign = 8;
+// one workgroup (1, 2, 3, 4, 6, 8 or 12) always work on the same entry.
+constexpr uint32_t kBatchTileAlign = 24;
 
 // Combinator op of a batched program: op | p_slot << 8 | v_slot << 20.
 //   D_RANGE    leaf with predicate word in p_slot (any value test)

@@ -341,7 +341,7 @@ bool launch_round(sel_server* s) {
   a.ndone = ngroups;
   a.out = (unsigned long long*)((char*)rs.dev + o_out);
   a.slot = rs.slot;
-  const uint32_t block = 512;
+  const uint32_t block = bp.default_block();
   const uint32_t lds = bp.lds_bytes(block);
   int occ = 1;
   if (sel_batch_occupancy(block, lds, &occ) != 0 || occ < 1) occ = 1;

@@ -133,7 +133,7 @@ def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
     assert block in (64, 128, 256) and grid > 0 and ms > 0
     ctx.autotune(*pairs[-1], with_mask=True, reps=2)
     (bb, bg), bms = ctx.autotune_batch(pairs, reps=1)
-    assert bb in (64, 128, 256, 512) and bg > 0
+    assert bb in (64, 128, 256, 512, 768) and bg > 0
     assert ctx.tune_entries >= 3
     assert ctx.count(*pairs[-1]) == want[-1]
     assert ctx.count_batch(pairs) == want
@@ -173,12 +173,15 @@ def test_batch_random_programs(sel, ctx, n):
     b.destroy()
 
 
-def test_batch_star_programs(sel, ctx):
-    """Star semi-join programs in one batch, over dimensions large enough
-    that the batch takes every lookup route: an LDS table (2556 keys),
-    device-memory tables (30k and 600k keys, read where the earlier probes
-    leave rows), and guarded bitmap probes (9M keys).  With fact-side
-    predicates, a plain fact program and a program used twice (no guard)."""
+@pytest.mark.parametrize("nstar", [12, 20])
+def test_batch_star_programs(sel, ctx, nstar):
+    """Star semi-join programs in one batch, over dimensions that take every
+    lookup route: with 12 programs (2-byte entries) an LDS table (2556 keys)
+    and device-memory tables (30k, 600k and 9M keys, the largest read only
+    where the earlier probes leave rows); with 20 (4-byte entries) the 600k
+    table is read only where guards hold and the 9M keys are probed in the
+    dimension bitmaps themselves.  With fact-side predicates, a plain fact
+    program and a program used twice (no guard)."""
     sizes = (2556, 30_000, 600_000, 9_000_000)
     say("batch star: generating dimensions and fact")
     dims = datagen.star_dims(seed=42, sizes=sizes)
@@ -188,7 +191,7 @@ def test_batch_star_programs(sel, ctx):
     ofact = oracle.Oracle(fact)
     fp = datagen.star_fact_predicate()
     progs, want, keep = [], [], []
-    for k, combo in enumerate(datagen.star_dim_programs(7, 12, dims)):
+    for k, combo in enumerate(datagen.star_dim_programs(7, nstar, dims)):
         bms_gpu, bms_cpu = [], []
         for d, dt, p in zip(dims, ddims, combo):
             bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
@@ -211,6 +214,100 @@ def test_batch_star_programs(sel, ctx):
     assert [ctx.count(*p) for p in pairs] == want
     assert ctx.count_batch(pairs) == want
     assert ctx.count_batch(pairs[:5]) == want[:5]
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
+
+
+def _nulls(rng, n, rate):
+    """Validity words (bit i % 32 of word i / 32 = not NULL) and NULL count."""
+    isnull = rng.random(n) < rate
+    bits = np.packbits((~isnull).astype(np.uint8), bitorder="little")
+    buf = np.zeros((n + 31) // 32 * 4, dtype=np.uint8)
+    buf[: bits.size] = bits
+    return buf.view(np.uint32).copy(), int(isnull.sum())
+
+
+@pytest.mark.parametrize("k,span", [(6, 50_000), (12, 50_000), (24, 50_000), (12, 500_000),
+                                    (24, 500_000)])
+def test_batch_table_widths(sel, ctx, k, span):
+    """k programs over the same two narrow columns, so that one lookup table
+    per column serves all their leaves, with entries of 1, 2 or 4 bytes (up
+    to 8, 16 or 32 leaves): in LDS for an int8 column with NULLs, and in
+    device memory for an int32 code column of `span` values (code sets of a
+    compiled program are at most 512k bits; the larger guarded tables and
+    probes are reached by the star programs).  Every fourth program puts its
+    int8 test in an OR, which keeps that leaf out of the accumulator.
+    Counts equal the oracle and the plain counts, eager and replayed."""
+    say(f"batch table widths k={k} span={span}")
+    rng = np.random.default_rng(31_000 + 7 * k + span)
+    n = 200_003
+    t = datagen.Table("widths", n)
+    t.columns.append(datagen.Column("a", "i32", rng.integers(0, span, n).astype(np.int32),
+                                    dict_card=span))
+    vb, nb = _nulls(rng, n, 0.1)
+    t.columns.append(datagen.Column("b", "i8", rng.integers(-100, 101, n).astype(np.int8),
+                                    valid=vb, null_count=nb))
+    vc, nc = _nulls(rng, n, 0.05)
+    t.columns.append(datagen.Column("c", "i64", rng.integers(0, 1_000_000, n).astype(np.int64),
+                                    valid=vc, null_count=nc))
+    nw = (span + 31) // 32
+    trees = []
+    for i in range(k):
+        lo = int(rng.integers(-100, 60))
+        hi = lo + int(rng.integers(5, 80))
+        words = rng.integers(0, 2**32, nw, dtype=np.uint32)
+        for _ in range(int(rng.integers(0, 3))):   # code density 1/2, 1/4 or 1/8
+            words &= rng.integers(0, 2**32, nw, dtype=np.uint32)
+        thr = int(rng.integers(0, 1_000_000))
+        if i % 4 == 3:
+            trees.append(("and", ("or", ("between", 1, lo, hi), ("cmp", 2, "<", thr)),
+                          ("codeset", 0, span, words)))
+        else:
+            trees.append(("and", ("between", 1, lo, hi), ("codeset", 0, span, words),
+                          ("cmp", 2, ">=", thr)))
+    dt = sel.device_table(ctx, t)
+    pairs = [(dt, ctx.program(dt, tree)) for tree in trees]
+    orc = oracle.Oracle(t)
+    want = [orc.count(tree) for tree in trees]
+    assert ctx.count_batch(pairs) == want
+    assert [ctx.count(*p) for p in pairs[:4]] == want[:4]
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
+
+
+def test_batch_wide_program(sel, ctx):
+    """A program with more leaf and validity words than a shared pass packs
+    (an OR of 32 int64 range tests over 12 nullable columns: 44 slots) runs
+    in a pass of its own with smaller workgroups; batched with ordinary
+    programs, alone, and replayed, every count equals the oracle."""
+    say("batch wide program")
+    rng = np.random.default_rng(41_000)
+    n = 100_003
+    t = datagen.Table("wide", n)
+    for c in range(12):
+        v, nn = _nulls(rng, n, 0.05)
+        t.columns.append(datagen.Column(f"c{c}", "i64", rng.integers(0, 10**6, n).astype(np.int64),
+                                        valid=v, null_count=nn))
+    leaves = []
+    for i in range(32):
+        lo = int(rng.integers(0, 10**6 - 10**4))
+        leaves.append(("between", i % 12, lo, lo + 10**4))
+    trees = [("or", *leaves)]
+    for i in range(6):
+        lo = int(rng.integers(0, 10**6 - 10**5))
+        trees.append(("and", ("cmp", i, ">=", int(rng.integers(0, 10**6))),
+                      ("between", i + 1, lo, lo + 10**5)))
+    dt = sel.device_table(ctx, t)
+    pairs = [(dt, ctx.program(dt, tree)) for tree in trees]
+    orc = oracle.Oracle(t)
+    want = [orc.count(tree) for tree in trees]
+    assert ctx.count_batch(pairs) == want
+    assert ctx.count_batch(pairs[:1]) == want[:1]
+    assert ctx.count_batch(pairs[1:]) == want[1:]
     b = ctx.batch(pairs)
     for _ in range(2):
         assert b.run() == want
