@@ -227,18 +227,14 @@ struct Pass {
 
   // A program's plan in this pass: its direct factors (single value-test
   // leaves on narrow columns, applied straight to the program's accumulator
-  // words), the other factors in the order they are emitted, and whether
-  // no column it reads has NULLs.
+  // word) and the other factors in the order they are emitted.
   struct Split {
     std::vector<size_t> direct;
     std::vector<std::pair<size_t, size_t>> rest;
-    bool two = true;
   };
   static Split split(const sel_program* p) {
     Split S;
     const std::vector<DevInstr>& code = p->host_code;
-    for (const DevInstr& I : code)
-      if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid) S.two = false;
     Factors F = split_and(code);
     if (!F.ok) {
       S.rest.push_back({0, code.size()});
@@ -273,7 +269,7 @@ struct Pass {
       if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid && !valid_slot.count(I.valid) &&
           std::find(nv.begin(), nv.end(), I.valid) == nv.end())
         nv.push_back(I.valid);
-    const uint32_t acc = S.direct.empty() ? 0u : (S.two ? 1u : 2u);
+    const uint32_t acc = S.direct.empty() ? 0u : 1u;
     return (uint32_t)(nl.size() + nv.size()) + acc;
   }
   uint32_t vslot_of(const DevInstr& I) {
@@ -314,6 +310,7 @@ struct Pass {
         const LeafKey k = key_of(I);
         auto it = leaf_slot.find(k);
         uint32_t sl;
+        const uint32_t vs = vslot_of(I);
         if (it != leaf_slot.end()) {
           sl = it->second;
         } else {
@@ -321,11 +318,11 @@ struct Pass {
           leaf_slot[k] = sl;
           DevInstr L = I;
           L.flags = kNoGuard;
-          L.slot = sl;
+          L.slot = ((vs == kNoSlot ? kAccNoValid : vs) << 24) | sl;
           L.lds_word = kNoLds;
           home_of(I).leaves.push_back(L);
         }
-        ops.push_back(batch_op(D_RANGE, sl, vslot_of(I)));
+        ops.push_back(batch_op(D_RANGE, sl, vs));
       } else if (is_null_test(op)) {
         ops.push_back(batch_op(op, 0, vslot_of(I)));
       } else {
@@ -343,24 +340,24 @@ struct Pass {
       if (k > 0) ops.push_back(batch_op(D_AND, 0, 0));
     }
     if (!S.direct.empty()) {
-      // the program's accumulator: TRUE word (reset to ~0 per tile) and, if
-      // a column has NULLs, FALSE word (reset to 0); each direct factor ANDs
-      // into it when its column is evaluated, and a direct bitmap factor
-      // skips lookups on rows the accumulator already holds FALSE
+      // the program's accumulator: the TRUE word of the conjunction of its
+      // direct factors (reset to ~0 per tile).  The count needs only TRUE
+      // rows, and the root is an AND, so FALSE and UNKNOWN rows of the
+      // accumulator need no word of their own.  Each direct factor ANDs its
+      // TRUE word into it when its column is evaluated, and a direct bitmap
+      // factor skips lookups on rows that are no longer TRUE.
       const uint32_t ts = slots++;
-      const uint32_t fs = S.two ? kNoSlot : slots++;
       inits.push_back(ts | kInitTrue);
-      if (fs != kNoSlot) inits.push_back(fs);
       for (size_t pc : S.direct) {
         const DevInstr& I = code[pc];
         const uint32_t vs = vslot_of(I);
         DevInstr L = I;
         L.flags = I.op == D_BITMAP ? kAccGuard : kNoGuard;
-        L.slot = kAccTarget | ((vs == kNoSlot ? kAccNoValid : vs) << 24) | (fs << 12) | ts;
+        L.slot = kAccTarget | ((vs == kNoSlot ? kAccNoValid : vs) << 24) | ts;
         L.lds_word = kNoLds;
         home_of(I).leaves.push_back(L);
       }
-      ops.push_back(batch_op(B_ACC, ts, fs));
+      ops.push_back(batch_op(B_ACC, ts, kNoSlot));
       if (!S.rest.empty()) ops.push_back(batch_op(D_AND, 0, 0));
     }
     // a value-test leaf (or the accumulator) that is the right operand of
@@ -461,10 +458,10 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
       BatchProg bp{};
       bp.ops = (const uint32_t*)(uintptr_t)ops.size();
       bp.nops = (uint32_t)pr.first.size();
-      bool two = true;   // every validity reference is kNoSlot
+      bool two = true;   // TRUE words suffice: no NOT, no IS UNKNOWN
       for (uint32_t w : pr.first) {
         const uint32_t op = w & 0xFFu;
-        if ((op < D_AND || op >= B_AND_LEAF) && (w >> 20) != kNoSlot) two = false;
+        if (op == D_NOT || op == D_ISUNK) two = false;
       }
       if (two) bp.nops |= kTwoValued;
       bp.acc_index = pr.second;

@@ -667,24 +667,24 @@ __device__ __forceinline__ void seg_issue(Seg& r, uint32_t& V, const CONSTANT Ba
 }
 
 // Rows a direct factor of a conjunction still needs tested: those its
-// program's accumulator does not already hold FALSE.
+// program's accumulator still holds TRUE.
 __device__ __forceinline__ uint32_t acc_need(uint32_t sl, const uint32_t* wl, uint32_t lane) {
-  const uint32_t ts = sl & 0xFFFu, fs = (sl >> 12) & 0xFFFu;
-  return fs != kNoSlot ? ~wl[fs * kWave + lane] : wl[ts * kWave + lane];
+  return wl[(sl & 0xFFFu) * kWave + lane];
 }
 
-// Stores a leaf's truth word: into its slot, or for a direct factor of a
-// conjunction into its program's accumulator (TRUE &= P on non-NULL rows,
-// FALSE |= NOT P on non-NULL rows).
+// Validity word of a leaf's column (all ones without NULLs).
+__device__ __forceinline__ uint32_t leaf_valid(uint32_t sl, const uint32_t* wl, uint32_t lane) {
+  const uint32_t vs = (sl >> 24) & 0x7Fu;
+  return vs == kAccNoValid ? ~0u : wl[vs * kWave + lane];
+}
+
+// Stores a leaf's TRUE word (its test on non-NULL rows): into its slot, or
+// for a direct factor of a conjunction ANDed into its program's accumulator.
 __device__ __forceinline__ void put_leaf(uint32_t* wl, uint32_t lane, uint32_t sl, uint32_t P) {
-  if (sl & kAccTarget) {
-    const uint32_t ts = sl & 0xFFFu, fs = (sl >> 12) & 0xFFFu, vs = (sl >> 24) & 0x7Fu;
-    const uint32_t V = vs == kAccNoValid ? ~0u : wl[vs * kWave + lane];
-    wl[ts * kWave + lane] &= P & V;
-    if (fs != kNoSlot) wl[fs * kWave + lane] |= ~P & V;
-  } else {
-    wl[sl * kWave + lane] = P;
-  }
+  const uint32_t T = P & leaf_valid(sl, wl, lane);
+  uint32_t* w = wl + (sl & 0xFFFu) * kWave + lane;
+  if (sl & kAccTarget) *w &= T;
+  else *w = T;
 }
 
 // Resets the accumulators of an entry's programs for a new tile.
@@ -863,9 +863,10 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
     if constexpr (TY != T_I64) {
       put_leaf(wl, lane, I->slot, P);
     } else {  // int64 leaves always have a slot of their own
-      uint32_t* w = wl + I->slot * kWave + lane;
+      const uint32_t sl = I->slot;
+      uint32_t* w = wl + (sl & 0xFFFu) * kWave + lane;
       if (h == 0) *w = P;
-      else *w = (*w << 16) | P;
+      else *w = ((*w << 16) | P) & leaf_valid(sl, wl, lane);
     }
   }
   if constexpr (TY != T_I64) {
@@ -1024,9 +1025,10 @@ __device__ __forceinline__ uint32_t run_ops(const CONSTANT uint32_t* ops, uint32
   return tt;
 }
 
-// The same for a program none of whose columns has NULLs: no value is
-// UNKNOWN, so FALSE is the complement of TRUE and one word per stack entry
-// suffices.
+// The same for a program with no NOT and no IS UNKNOWN: the TRUE word of an
+// AND or OR is the AND or OR of its operands' TRUE words, so the TRUE words
+// of leaves (NULL rows cleared) and null tests are all it needs, one word
+// per stack entry.
 __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint32_t nops,
                                              const uint32_t* wl, uint32_t lane) {
   uint32_t st[kMaxDepth];
@@ -1048,8 +1050,13 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
       }
     } else if (op < D_AND || op == D_TRUE || op == D_FALSE) {
       uint32_t t;
-      if (op == D_RANGE) t = wl[((w >> 8) & 0xFFFu) * kWave + lane];
-      else t = (op == D_NN_TRUE || op == D_NOTNULL || op == D_TRUE) ? ~0u : 0u;
+      if (op == D_RANGE) {
+        t = wl[((w >> 8) & 0xFFFu) * kWave + lane];
+      } else {
+        const uint32_t vs = w >> 20;
+        const uint32_t V = (vs == kNoSlot || op >= D_TRUE) ? ~0u : wl[vs * kWave + lane];
+        t = (op == D_NN_TRUE || op == D_NOTNULL) ? V : op == D_ISNULL ? ~V : op == D_TRUE ? ~0u : 0u;
+      }
       if (d > 0) st[uni(d - 1)] = tt;
       tt = t;
       ++d;

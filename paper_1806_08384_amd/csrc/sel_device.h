@@ -152,21 +152,22 @@ constexpr uint32_t kBatchTileAlign = 24;
 // v_slot == kNoSlot: the column has no NULLs (validity all ones).
 constexpr uint32_t B_AND_LEAF = 24;
 constexpr uint32_t B_OR_LEAF = 25;
-//   B_ACC        push the program's accumulator: TRUE word in p_slot, FALSE
-//                word in v_slot (kNoSlot: no NULLs, FALSE = NOT TRUE)
+//   B_ACC        push the program's accumulator: its TRUE word in p_slot
+//                (v_slot is kNoSlot; FALSE is taken as NOT TRUE, which the
+//                AND at the program's root never lets reach its TRUE word)
 //   B_AND_ACC    top = top AND accumulator
 constexpr uint32_t B_ACC = 26;
 constexpr uint32_t B_AND_ACC = 27;
 
-// A batched leaf whose slot field has kAccTarget set is a direct factor of
-// one program's conjunction: its truth word is ANDed into that program's
-// accumulator (TRUE slot in bits 0..11, FALSE slot in bits 12..23 or
-// kNoSlot, the slot of its column's validity word in bits 24..30 or
-// kAccNoValid) instead of being parked in a slot of its own.
+// The slot field of a batched leaf: bits 0..11 its slot, bits 24..30 the
+// slot of its column's validity word or kAccNoValid (no NULLs); the leaf
+// stores its TRUE word (test AND validity) there.  With kAccTarget set the
+// leaf is a direct factor of one program's conjunction, and bits 0..11 name
+// that program's accumulator, into which its TRUE word is ANDed.
 constexpr uint32_t kAccTarget = 0x80000000u;
 constexpr uint32_t kAccNoValid = 0x7Fu;
 // Its flags field kAccGuard: lookups are needed only on rows the
-// accumulator does not already hold FALSE.
+// accumulator still holds TRUE.
 constexpr uint32_t kAccGuard = 0xFFFFFFFEu;
 // Accumulator reset list entries: slot | kInitTrue (reset to ~0) or slot
 // (reset to 0), once per tile before the first column.
@@ -239,7 +240,7 @@ struct TableBuild {            // 48 bytes
 
 struct BatchProg {             // 16 bytes
   const uint32_t* ops;         // batch_op words, postfix
-  uint32_t nops;               // | kTwoValued: no column of the program has NULLs
+  uint32_t nops;               // | kTwoValued: no NOT and no IS UNKNOWN (TRUE words suffice)
   uint32_t acc_index;          // accumulator line this program adds into
 };
 
