@@ -227,11 +227,22 @@ struct Pass {
 
   // A program's plan in this pass: its direct factors (single value-test
   // leaves on narrow columns, applied straight to the program's accumulator
-  // word) and the other factors in the order they are emitted.
+  // word), its OR factors over such leaves only (each ORed into one word of
+  // its own), and the other factors in the order they are emitted.
   struct Split {
     std::vector<size_t> direct;
+    std::vector<std::pair<size_t, size_t>> ors;
     std::vector<std::pair<size_t, size_t>> rest;
   };
+  static bool narrow_test(const DevInstr& I) { return is_value_test(I.op) && I.type != T_I64; }
+  // [b, e) is an OR of at least two narrow value tests (postfix: tests and
+  // ORs only)
+  static bool or_of_tests(const std::vector<DevInstr>& code, size_t b, size_t e) {
+    if (e - b < 3) return false;
+    for (size_t k = b; k < e; ++k)
+      if (!narrow_test(code[k]) && code[k].op != D_OR) return false;
+    return true;
+  }
   static Split split(const sel_program* p) {
     Split S;
     const std::vector<DevInstr>& code = p->host_code;
@@ -244,7 +255,8 @@ struct Pass {
     for (size_t k = 0; k < F.ranges.size(); ++k) {
       const auto r = F.ranges[k];
       const DevInstr& I = code[r.first];
-      if (r.second == r.first + 1 && is_value_test(I.op) && I.type != T_I64) S.direct.push_back(r.first);
+      if (r.second == r.first + 1 && narrow_test(I)) S.direct.push_back(r.first);
+      else if (or_of_tests(code, r.first, r.second)) S.ors.push_back(r);
       else rest.push_back({F.depth[k], r});
     }
     // deepest factor first: the chain then needs no more stack than the
@@ -269,7 +281,7 @@ struct Pass {
       if ((is_value_test(I.op) || is_null_test(I.op)) && I.valid && !valid_slot.count(I.valid) &&
           std::find(nv.begin(), nv.end(), I.valid) == nv.end())
         nv.push_back(I.valid);
-    const uint32_t acc = S.direct.empty() ? 0u : 1u;
+    const uint32_t acc = (S.direct.empty() ? 0u : 1u) + (uint32_t)S.ors.size();
     return (uint32_t)(nl.size() + nv.size()) + acc;
   }
   uint32_t vslot_of(const DevInstr& I) {
@@ -359,6 +371,26 @@ struct Pass {
       }
       ops.push_back(batch_op(B_ACC, ts, kNoSlot));
       if (!S.rest.empty()) ops.push_back(batch_op(D_AND, 0, 0));
+    }
+    // an OR factor of narrow tests: its TRUE word (reset to 0 per tile) is
+    // the OR of its leaves' TRUE words, ORed in as their columns are
+    // evaluated; it then enters the AND chain like a leaf.  As with the
+    // accumulator, only its TRUE rows matter under the root AND.
+    for (size_t k = 0; k < S.ors.size(); ++k) {
+      const uint32_t os = slots++;
+      inits.push_back(os);
+      for (size_t pc = S.ors[k].first; pc < S.ors[k].second; ++pc) {
+        const DevInstr& I = code[pc];
+        if (!is_value_test(I.op)) continue;
+        const uint32_t vs = vslot_of(I);
+        DevInstr L = I;
+        L.flags = kNoGuard;
+        L.slot = kAccTarget | kAccOr | ((vs == kNoSlot ? kAccNoValid : vs) << 24) | os;
+        L.lds_word = kNoLds;
+        home_of(I).leaves.push_back(L);
+      }
+      ops.push_back(batch_op(D_RANGE, os, kNoSlot));
+      if (!S.rest.empty() || !S.direct.empty() || k > 0) ops.push_back(batch_op(D_AND, 0, 0));
     }
     // a value-test leaf (or the accumulator) that is the right operand of
     // the AND / OR right after it combines with the top of the stack directly

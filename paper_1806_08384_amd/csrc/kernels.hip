@@ -679,12 +679,14 @@ __device__ __forceinline__ uint32_t leaf_valid(uint32_t sl, const uint32_t* wl, 
 }
 
 // Stores a leaf's TRUE word (its test on non-NULL rows): into its slot, or
-// for a direct factor of a conjunction ANDed into its program's accumulator.
+// for a direct factor of a conjunction ANDed into its program's accumulator,
+// or for a leaf of an OR factor of narrow tests ORed into that factor's word.
 __device__ __forceinline__ void put_leaf(uint32_t* wl, uint32_t lane, uint32_t sl, uint32_t P) {
   const uint32_t T = P & leaf_valid(sl, wl, lane);
   uint32_t* w = wl + (sl & 0xFFFu) * kWave + lane;
-  if (sl & kAccTarget) *w &= T;
-  else *w = T;
+  if (!(sl & kAccTarget)) *w = T;
+  else if (sl & kAccOr) *w |= T;
+  else *w &= T;
 }
 
 // Resets the accumulators of an entry's programs for a new tile.

@@ -164,7 +164,10 @@ constexpr uint32_t B_AND_ACC = 27;
 // stores its TRUE word (test AND validity) there.  With kAccTarget set the
 // leaf is a direct factor of one program's conjunction, and bits 0..11 name
 // that program's accumulator, into which its TRUE word is ANDed.
+// With kAccOr set as well, the leaf belongs to an OR factor of narrow tests
+// and its TRUE word is ORed into that factor's word instead.
 constexpr uint32_t kAccTarget = 0x80000000u;
+constexpr uint32_t kAccOr = 0x00800000u;
 constexpr uint32_t kAccNoValid = 0x7Fu;
 // Its flags field kAccGuard: lookups are needed only on rows the
 // accumulator still holds TRUE.
