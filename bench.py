@@ -346,6 +346,83 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
     return res
 
 
+def bench_sweeps(ctx, dt, n, threads, log, reps=3):
+    """Count-kernel rate against selectivity and against the number of leaves
+    on the 300M-row fact table (the analogues of the thesis' overhead versus
+    selectivity and versus attribute count experiments), with the push-down
+    step (count + mask, limit, scan, ascending ids) at each selectivity; and
+    the three-column uniform table at 300M rows, a pure bandwidth probe."""
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+
+    def count_ms(table, prog):
+        ctx.count(table, prog)
+        ctx.read_timing(reset=True)
+        for _ in range(reps):
+            c = ctx.count(table, prog)
+        ms, l = ctx.read_timing(reset=True)
+        return c, ms[sel.K_COUNT] / max(1, l[sel.K_COUNT])
+
+    ids = torch.empty(n, dtype=torch.int32, device="cuda")
+    sel_rows = []
+    cases = [("P2, date window %d days" % w, datagen.cfg2_predicate(365, 365 + w - 1))
+             for w in (1, 10, 100, 365)]
+    cases.append(("P2, every date", datagen.cfg2_predicate(0, 2556)))
+    cases += [("date range, %d%% of days" % int(100 * f), ("between", 0, 0, int(round(f * 2557)) - 1))
+              for f in (0.1, 0.3, 0.6, 0.9)]
+    for name, tree in cases:
+        prog = ctx.program(dt, tree)
+        c, kms = count_ms(dt, prog)
+        bpr = prog.bytes_per_row
+        st, cnt = ctx.pushdown_rowids(dt, prog, sel.UINT64_MAX, ids)
+        assert st == sel.SEL_OK and cnt == c, (st, cnt, c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.pushdown_rowids(dt, prog, sel.UINT64_MAX, ids)
+        torch.cuda.synchronize()
+        pd_ms = (time.perf_counter() - t0) / reps * 1e3
+        gbs = n * bpr / kms / 1e6
+        sel_rows.append({"program": name, "selected_rows": c, "selectivity": c / n,
+                         "count_kernel_ms": kms, "count_GBps": gbs,
+                         "count_frac_of_peak": gbs / HBM_PEAK_GBS,
+                         "pushdown_step_ms": pd_ms, "ids_bytes": 4 * c})
+        log(f"sweep: {name}: selectivity {c / n:.2e}, count {kms:.3f} ms, push-down {pd_ms:.3f} ms")
+    del ids
+    torch.cuda.empty_cache()
+
+    leaves = [("between", 0, 0, 1999), ("cmp", 1, "<", 45), ("between", 2, 0, 9),
+              ("cmp", 3, ">=", 2000), ("in", 5, tuple(range(0, 24))),
+              ("codeset", 6, 4500, datagen.cfg2_like_bitmap() | 0xAAAAAAAA),
+              ("in", 4, (0, 1, 2, 3, 4, 5)), ("cmp", 0, ">=", 10)]
+    leaf_rows = []
+    for k in range(1, len(leaves) + 1):
+        tree = leaves[0] if k == 1 else ("and", *leaves[:k])
+        prog = ctx.program(dt, tree)
+        c, kms = count_ms(dt, prog)
+        bpr = prog.bytes_per_row
+        gbs = n * bpr / kms / 1e6
+        leaf_rows.append({"leaves": k, "bytes_per_row": bpr, "selected_rows": c,
+                          "count_kernel_ms": kms, "rows_per_s": n / kms * 1e3,
+                          "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS})
+        log(f"sweep: {k} leaves, {bpr} B/row: count {kms:.3f} ms, {gbs:.0f} GB/s")
+
+    log("sweep: three uniform int32 columns at 300M rows")
+    u = datagen.cfg1(n=300_000_000, threads=threads)
+    du = sel.device_table(ctx, u)
+    del u
+    prog = ctx.program(du, datagen.cfg1_predicate())
+    c, kms = count_ms(du, prog)
+    gbs = du.nrows * prog.bytes_per_row / kms / 1e6
+    uni = {"rows": du.nrows, "bytes_per_row": prog.bytes_per_row, "selected_rows": c,
+           "count_kernel_ms": kms, "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS}
+    del du, prog
+    torch.cuda.empty_cache()
+    return {"selectivity": sel_rows, "leaves": leaf_rows, "uniform3_300M": uni}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +439,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the serving (Poisson request stream) measurement")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the selectivity / leaf-count sweeps and the bandwidth probe")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain "
                          "copy kernel of known size, to calibrate HBM byte counters)")
@@ -497,6 +576,8 @@ def main():
                       f"row ranges split over {threads} threads; {dt_cpu:.2f} s wall",
         }
     del table
+    if not args.no_sweeps:
+        out["sweeps"] = bench_sweeps(ctx, dt, n, threads, log)
     small = star = None
     if not args.no_batch:
         out["batch"], small = bench_batch(ctx, dt, threads, log)

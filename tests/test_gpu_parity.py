@@ -263,5 +263,27 @@ def test_cfg2_full_size(sel, ctx):
         want_ids = oracle.Oracle(sub).rowids(tree).astype(np.int64) + lo
         got_ids = ids[(ids >= lo) & (ids < hi)]
         np.testing.assert_array_equal(got_ids, want_ids)
-    del dt, out
+    del out
+    # a date range holding about 90 % of the rows: 270M ascending ids (1.08
+    # GB), the limit one below the count refuses them, the count itself
+    # accepts them
+    wide = ("between", 0, 0, 2300)
+    prog = ctx.program(dt, wide)
+    want = orc.count(wide, threads=16)
+    say(f"cfg2 full: 90 % range, count {want}")
+    out = torch.empty(want + 16, dtype=torch.int32, device="cuda")
+    st, cnt = ctx.pushdown_rowids(dt, prog, want - 1, out)
+    assert (st, cnt) == (sel.SEL_OVER_LIMIT, want)
+    st, cnt = ctx.pushdown_rowids(dt, prog, want, out)
+    assert (st, cnt) == (sel.SEL_OK, want)
+    ids = as_u32(out)[:cnt]
+    assert np.all(ids[1:] > ids[:-1])
+    for k in range(4):
+        lo = int(rng.integers(0, t.nrows - 3_000_000)) // 32 * 32
+        hi = lo + 1_000_000 + int(rng.integers(0, 1000))
+        sub = slice_table(t, lo, hi)
+        want_ids = oracle.Oracle(sub).rowids(wide).astype(np.int64) + lo
+        a, b = np.searchsorted(ids, [lo, hi])
+        np.testing.assert_array_equal(ids[a:b].astype(np.int64), want_ids)
+    del dt, out, ids
     torch.cuda.empty_cache()
