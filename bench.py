@@ -202,6 +202,43 @@ def bench_star(ctx, fact_rows, threads, log):
     return res, (dfact, ddims, dims)
 
 
+def bench_select_pushdown(ctx, small, fact_dt, star, log, reps=10):
+    """Algorithm 1's whole decision (size queue, probe skipped, exact count,
+    limit, ids of each pushed relation) on two queries: the star schema
+    (480M-row fact table probed, four dimensions evaluated) and the four
+    fact-schema tables (300M probed; 60M, 2M and 10k rows evaluated), at
+    PUSH_DOWN_MAX_SELECTIVITY 0.05 and PUSH_DOWN_MIN_TABLE_SIZE 1000."""
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+    dfact, ddims, _ = star
+    queries = {
+        "star_480M_fact_4_dims": [(dfact, None)] + list(zip(ddims, datagen.star_dim_predicates())),
+        "fact_tables_300M_60M_2M_10k": [(fact_dt, datagen.cfg2_predicate())] + [
+            (t, datagen.cfg2_predicate(0, 1000)) for t in small],
+    }
+    out = {}
+    for name, rels in queries.items():
+        args = []
+        for t, tree in rels:
+            buf = torch.empty(max(1, sel.max_rows(t.nrows, 0.05)), dtype=torch.int32, device="cuda")
+            args.append((t, ctx.program(t, tree) if tree is not None else None, buf))
+        ctx.select_pushdown(args)
+        ms, res = _timed(lambda: ctx.select_pushdown(args), reps)
+        out[name] = {
+            "relations_rows": [t.nrows for t, _ in rels],
+            "decisions": [r["decision"] for r in res],
+            "counts": [r["count"] for r in res],
+            "max_rows": [r["max_rows"] for r in res],
+            "call_ms_median": ms,
+        }
+        log(f"algorithm 1, {name}: {ms:.3f} ms, {[r['decision'] for r in res]}")
+        del args
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=None):
     """Poisson stream (2000 requests/s) of estimate requests, 1-12 programs
     each over the resident tables (1M uniform, 2M, 60M, the 300M fact table
@@ -583,6 +620,8 @@ def main():
         out["batch"], small = bench_batch(ctx, dt, threads, log)
     if not args.no_star:
         out["star"], star = bench_star(ctx, args.star_rows, threads, log)
+    if small is not None and star is not None:
+        out["select_pushdown"] = bench_select_pushdown(ctx, small, dt, star, log)
     if not args.no_serve and small is not None and star is not None:
         out["serving"] = bench_serve(ctx, small, dt, star, threads, log, args.serve_seconds)
     if args.copy_probe_mb:

@@ -256,6 +256,53 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact,
                           const uint32_t* const* d_bitmaps,
                           const uint64_t* nbits, uint64_t* out_count);
 
+/* ---- the push-down decision over a query's relations (Algorithm 1) ------ */
+
+/* One scanned relation R of a query: its table, the selection extracted for
+ * it (NULL: the query has no predicate on R), and a caller-owned device
+ * buffer for the ascending row ids of sigma(R) should it be pushed down. */
+typedef struct sel_spd_relation {
+  const sel_table* table;
+  const sel_program* pred;     /* bound to table, or NULL */
+  uint32_t* d_out;             /* device, caller owned; may be NULL if cap == 0 */
+  uint64_t cap;                /* capacity of d_out in row ids */
+} sel_spd_relation;
+
+typedef enum sel_spd_decision {
+  SEL_SPD_PUSHED = 0,     /* count <= maxSize: sigma(R) materialised in d_out */
+  SEL_SPD_REVERTED = 1,   /* count > maxSize (or > cap): push-down reverted   */
+  SEL_SPD_PROBE = 2,      /* the largest relation: kept for the probe side    */
+  SEL_SPD_SMALL = 3,      /* size <= min_table_size: never evaluated          */
+  SEL_SPD_NO_PRED = 4     /* queued, but no selection to push down            */
+} sel_spd_decision;
+
+typedef struct sel_spd_result {
+  int32_t decision;       /* sel_spd_decision                                  */
+  int32_t status;         /* sel_pushdown_rowids' status for an evaluated R    */
+                          /* (SEL_OK, SEL_OVER_LIMIT or SEL_E_CAPACITY), else 0 */
+  uint32_t order;         /* position in the evaluation order, or UINT32_MAX   */
+  uint32_t pad;
+  uint64_t count;         /* exact |sigma(R)| of an evaluated R, else 0        */
+  uint64_t max_rows;      /* maxSize = sel_max_rows(R.size, max_selectivity)   */
+} sel_spd_result;
+
+/* EvaluateAndPushDown of Algorithm 1 (Ch.4 sec.4.2) over n relations:
+ * relations larger than min_table_size (PUSH_DOWN_MIN_TABLE_SIZE, strict >)
+ * enter a queue ordered by size, largest first (equal sizes: lower index
+ * first); the first, the relation to be probed, is removed; each other
+ * queued relation with a selection is then, in queue order, counted exactly
+ * and either pushed down (ids written to d_out) or reverted, by
+ * sel_pushdown_rowids with max_rows = maxSize = floor(R.size *
+ * max_selectivity) (PUSH_DOWN_MAX_SELECTIVITY).  A count above cap reverts
+ * too (status SEL_E_CAPACITY, nothing written).  out (host, n) gets one
+ * result per relation, in input order.  Errors: SEL_E_INVALID (n == 0,
+ * NULL arrays or tables, a program bound to another table, NaN ratio; checked
+ * before any launch), or the first error of a push-down (device or memory),
+ * which ends the loop with the results so far filled in. */
+sel_status sel_select_pushdown(sel_ctx* ctx, uint32_t n, const sel_spd_relation* rels,
+                               uint64_t min_table_size, double max_selectivity,
+                               sel_spd_result* out);
+
 /* ---- batching (Algorithm 1 counts every candidate relation) ------------- */
 
 /* Exact counts of n (table, program) pairs in ONE persistent launch

@@ -13,11 +13,15 @@ Every function here restates the thesis' definitions (Shin 2018):
   keybitmap -- Ch.3 sec.3.3 / Algorithm 1: a pushed-down non-probe relation,
                kept as the set of its qualifying keys
   star_count-- fact rows whose foreign keys all hit those key sets
+  select_pushdown -- Algorithm 1, EvaluateAndPushDown: the size-ordered
+               queue of a query's relations, the probe relation skipped, and
+               Execute(compound, true, maxSize) on each other one
 Parity pins: see tests/test_oracle_*.py.
 """
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import numpy as np
@@ -207,6 +211,70 @@ class Oracle:
         return int(self.lib.oc_star_count(ctypes.byref(e) if e is not None else None,
                                           self._cols, self.table.nrows, nfk, fk.ctypes.data,
                                           ptrs, nb.ctypes.data, threads))
+
+
+def max_size(nrows: int, ratio: float) -> int:
+    """maxSize = R.size * PUSH_DOWN_MAX_SELECTIVITY (Algorithm 1), the product
+    taken in double as the algorithm states it; an integer count exceeds it
+    iff it exceeds its floor.  A ratio <= 0 (or NaN) gives 0, >= 1 gives
+    nrows."""
+    if not ratio > 0.0:
+        return 0
+    if ratio >= 1.0:
+        return nrows
+    return min(nrows, math.floor(float(nrows) * float(ratio)))
+
+
+def select_pushdown(relations, min_table_size: int = 1000, max_selectivity: float = 0.05):
+    """EvaluateAndPushDown of Algorithm 1 (Ch.4 sec.4.2), step by step.
+
+    relations: [(table, tree or None[, cap])] -- a query's scanned relations,
+    each with the selection extracted for it (None: no predicate on it) and
+    optionally the capacity of the buffer its ids go to.  Returns one dict per
+    relation, in input order: decision ('pushed', 'reverted', 'probe',
+    'small', 'no_pred'), status (Execute's outcome for an evaluated relation:
+    0 pushed, 1 count above maxSize, 2 above the capacity), order (position in
+    the evaluation loop), count, max_rows and, for a pushed relation, its
+    ascending row ids."""
+    res = []
+    for item in relations:
+        t = item[0]
+        res.append({"decision": None, "status": 0, "order": None, "count": 0,
+                    "max_rows": max_size(t.nrows, max_selectivity), "ids": None})
+    # the priority queue holds the relations larger than
+    # PUSH_DOWN_MIN_TABLE_SIZE, by size, largest first; equal sizes keep the
+    # order in which the scans were listed
+    queue = []
+    for i, item in enumerate(relations):
+        if item[0].nrows > min_table_size:
+            queue.append((item[0].nrows, i))
+        else:
+            res[i]["decision"] = "small"
+    queue.sort(key=lambda e: (-e[0], e[1]))
+    if not queue:
+        return res
+    # pop the largest relation: it is the one to be probed
+    _, probe = queue.pop(0)
+    res[probe]["decision"] = "probe"
+    for k, (_, i) in enumerate(queue):
+        t, tree = relations[i][0], relations[i][1]
+        cap = relations[i][2] if len(relations[i]) > 2 else t.nrows
+        res[i]["order"] = k
+        if tree is None:
+            res[i]["decision"] = "no_pred"
+            continue
+        # Execute(compound, true, maxSize): the exact count of sigma(R); a
+        # count above maxSize throws and the push-down of R is reverted,
+        # otherwise sigma(R) is materialised
+        st, c, ids = Oracle(t).pushdown(tree, res[i]["max_rows"], cap)
+        res[i]["status"] = st
+        res[i]["count"] = c
+        if st == 0:
+            res[i]["decision"] = "pushed"
+            res[i]["ids"] = ids
+        else:
+            res[i]["decision"] = "reverted"
+    return res
 
 
 def _clamp64(v: int) -> int:

@@ -62,6 +62,19 @@ class sel_launch(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32)]
 
 
+class sel_spd_relation(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("pred", ctypes.c_void_p), ("d_out", ctypes.c_void_p),
+                ("cap", ctypes.c_uint64)]
+
+
+class sel_spd_result(ctypes.Structure):
+    _fields_ = [("decision", ctypes.c_int32), ("status", ctypes.c_int32), ("order", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("count", ctypes.c_uint64), ("max_rows", ctypes.c_uint64)]
+
+
+SPD_DECISIONS = ("pushed", "reverted", "probe", "small", "no_pred")
+
+
 class sel_server_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_uint64),
                 ("max_programs", ctypes.c_uint32), ("rounds_in_flight", ctypes.c_uint32),
@@ -131,6 +144,8 @@ sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i
 sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
                       _P(_u64))
 sel_count_batch = _sig("sel_count_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_u64))
+sel_select_pushdown = _sig("sel_select_pushdown", _i32, _vp, _u32, _P(sel_spd_relation), _u64,
+                           ctypes.c_double, _P(sel_spd_result))
 sel_batch_create = _sig("sel_batch_create", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_vp))
 sel_batch_set_program = _sig("sel_batch_set_program", _i32, _vp, _u32, _vp)
 sel_batch_run = _sig("sel_batch_run", _i32, _vp, _P(_u64))
@@ -322,6 +337,23 @@ class Context:
         st = sel_pushdown_rowids(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
         self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
         return st, int(out.value)
+
+    def select_pushdown(self, relations, min_table_size: int = 1000, max_selectivity: float = 0.05):
+        """Algorithm 1 over [(table, program or None, out tensor or None)]:
+        one dict per relation (decision, status, order, count, max_rows);
+        the ids of a pushed relation land in its tensor[:count]."""
+        n = len(relations)
+        rels = (sel_spd_relation * max(1, n))()
+        for i, (t, p, o) in enumerate(relations):
+            rels[i].table = t.h
+            rels[i].pred = p.h if p is not None else None
+            rels[i].d_out = o.data_ptr() if o is not None else None
+            rels[i].cap = o.numel() if o is not None else 0
+        res = (sel_spd_result * max(1, n))()
+        self.check(sel_select_pushdown(self.h, n, rels, min_table_size, max_selectivity, res))
+        return [{"decision": SPD_DECISIONS[r.decision], "status": r.status,
+                 "order": None if r.order == 0xFFFFFFFF else r.order,
+                 "count": r.count, "max_rows": r.max_rows} for r in res[:n]]
 
     def pushdown_keybitmap(self, dim, key_col: int, key_min: int, prog, bitmap_tensor, nbits: int):
         """Returns (status, count); status SEL_OK or SEL_E_RANGE."""
