@@ -83,6 +83,69 @@ def cpu_baseline(table, tree, threads):
     return c, dt
 
 
+def host_info():
+    """The host the oracle runs on: logical CPUs, those this process may use,
+    CPU model and memory."""
+    info = {"logical_cpus": os.cpu_count(), "usable_cpus": host_threads()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["mem_total_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return info
+
+
+def cpu_workloads(table, tree, threads, log):
+    """The oracle on more of the workloads, each bounded to seconds: one
+    thread on the first 20M rows of the fact table; the 1M-row three-column
+    table; the 64 batching programs over their four tables (the fact table
+    is the 300M one), all threads."""
+    import numpy as np
+
+    import datagen
+    import oracle
+    out = {}
+    k = min(20_000_000, table.nrows) // 32 * 32
+    sub = datagen.Table(f"fact[0:{k}]", k)
+    for c in table.columns:
+        v = None if c.valid is None else c.valid[: k // 32]
+        sub.columns.append(datagen.Column(c.name, c.type, c.data[:k], v, c.dict_card))
+    t0 = time.perf_counter()
+    oracle.Oracle(sub).count(tree, threads=1)
+    dt = time.perf_counter() - t0
+    out["fact_one_thread"] = {"rows": sub.nrows, "threads": 1, "rows_per_s": sub.nrows / dt,
+                              "wall_s": dt}
+    u = datagen.cfg1(1_000_000)
+    orc = oracle.Oracle(u)
+    for th in (1, threads):
+        t0 = time.perf_counter()
+        for _ in range(20):
+            orc.count(datagen.cfg1_predicate(), threads=th)
+        dt = (time.perf_counter() - t0) / 20
+        out[f"uniform3_1M_{th}_threads"] = {"rows": u.nrows, "threads": th,
+                                            "rows_per_s": u.nrows / dt, "wall_s": dt}
+    log("cpu baseline: the 64 batching programs")
+    small = datagen.cfg3_tables(rows=datagen.CFG3_ROWS[:3], threads=threads)
+    tabs = small + [table]
+    orcs = [oracle.Oracle(t) for t in tabs]
+    progs = datagen.cfg3_programs()
+    t0 = time.perf_counter()
+    for ti, tr in progs:
+        orcs[ti].count(tr, threads=threads)
+    dt = time.perf_counter() - t0
+    prow = sum(tabs[ti].nrows for ti, _ in progs)
+    out["batch_64_programs"] = {"program_rows": prow, "threads": threads,
+                                "program_rows_per_s": prow / dt, "wall_s": dt}
+    del small, tabs, orcs
+    return out
+
+
 def _timed(fn, reps):
     """Median wall time of fn() over reps runs, in ms (fn synchronises)."""
     ts = []
@@ -154,7 +217,7 @@ def bench_batch(ctx, fact_dt, threads, log):
     return res, dts[:3]
 
 
-def bench_star(ctx, fact_rows, threads, log):
+def bench_star(ctx, fact_rows, threads, log, cpu=False):
     """Star push-down: dimension predicates become key bitmaps (2556 / 30k /
     200k / 3.2M-row dimensions), then the exact fact count by a conjunctive
     bitmap semi-join probe over a 480M-row fact table (4 int32 foreign keys)."""
@@ -168,6 +231,17 @@ def bench_star(ctx, fact_rows, threads, log):
     fact = datagen.star_fact(fact_rows, threads=threads)
     ddims = [sel.device_table(ctx, d) for d in dims]
     dfact = sel.device_table(ctx, fact)
+    cpu_star = None
+    if cpu:
+        import oracle
+        log("star: the oracle's key bitmaps and star count")
+        obms = [oracle.Oracle(d).keybitmap(p, 0, 0, d.nrows)[2] for d, p in zip(dims, preds)]
+        t0 = time.perf_counter()
+        oc = oracle.Oracle(fact).star_count([0, 1, 2, 3], obms, [d.nrows for d in dims],
+                                            threads=threads)
+        dt = time.perf_counter() - t0
+        cpu_star = {"rows": fact_rows, "threads": threads, "rows_per_s": fact_rows / dt,
+                    "wall_s": dt, "star_count": oc}
     del fact
     bitmaps, nbits, dim_ms = [], [], []
     for d, p in zip(ddims, preds):
@@ -199,7 +273,82 @@ def bench_star(ctx, fact_rows, threads, log):
         "star_GBps": bytes_ / (kms / 1e3) / 1e9,
         "star_frac_of_peak": bytes_ / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
     }
+    if cpu_star is not None:
+        assert cpu_star["star_count"] == c, (cpu_star["star_count"], c)
+        res["cpu_oracle"] = cpu_star
     return res, (dfact, ddims, dims)
+
+
+def bench_achievable(log, gib=4, reps=10):
+    """What plain streaming reaches on this GPU: a read-only reduction and a
+    copy of a 4 GiB buffer (torch's kernels), timed with events on torch's
+    stream; the lines against which the scan and the gather are read."""
+    import torch
+    n = (gib << 30) // 4
+    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = torch.empty_like(x)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        return {"ms": ms, "GBps": nbytes / ms / 1e6, "frac_of_peak": nbytes / ms / 1e6 / HBM_PEAK_GBS}
+
+    res = {"bytes": 4 * n,
+           "read_only_sum": rate(lambda: torch.sum(x, dtype=torch.int64), 4 * n),
+           "copy": rate(lambda: y.copy_(x), 8 * n)}
+    log(f"achievable: read {res['read_only_sum']['GBps']:.0f} GB/s, copy {res['copy']['GBps']:.0f} GB/s")
+    del x, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_gather(ctx, dt, table_cols, log, reps=5):
+    """Projected columns of a materialised selection, gathered at its row
+    ids on the 300M-row fact table: the 6-leaf predicate's ids (date, qty,
+    price with NULLs, s25) and a date range selecting 90 % of the rows
+    (date, price).  Algorithmic bytes per id: the id, each value read and
+    written, and a nullable column's validity bit read and written."""
+    import torch
+
+    import datagen
+    from paper_1806_08384_amd import sel
+    width = {"i8": 1, "i16": 2, "i32": 4, "i64": 8}
+    res = {}
+    cases = [("P2 selection", datagen.cfg2_predicate(), [0, 1, 3, 5]),
+             ("date range, 90% of rows", ("between", 0, 0, 2300), [0, 3])]
+    for name, tree, cols in cases:
+        prog = ctx.program(dt, tree)
+        cnt = ctx.count(dt, prog)
+        ids = torch.empty(max(1, cnt), dtype=torch.int32, device="cuda")
+        st, c2 = ctx.pushdown_rowids(dt, prog, sel.UINT64_MAX, ids)
+        assert st == sel.SEL_OK and c2 == cnt
+        outs = [torch.empty(max(1, cnt), dtype=getattr(torch, {"i8": "int8", "i32": "int32",
+                                                               "i64": "int64"}[table_cols[c][0]]),
+                            device="cuda") for c in cols]
+        vouts = [torch.empty(max(1, (cnt + 31) // 32), dtype=torch.int32, device="cuda")
+                 if table_cols[c][1] else None for c in cols]
+        ctx.gather(dt, ids, cnt, cols, outs, vouts)
+        ctx.read_timing(reset=True)
+        for _ in range(reps):
+            ctx.gather(dt, ids, cnt, cols, outs, vouts)
+        ms, l = ctx.read_timing(reset=True)
+        kms = ms[sel.K_GATHER] / max(1, l[sel.K_GATHER])
+        per_id = 4 + sum(2 * width[table_cols[c][0]] + (0.25 if table_cols[c][1] else 0) for c in cols)
+        gbs = cnt * per_id / kms / 1e6
+        res[name] = {"ids": cnt, "columns": [table_cols[c][2] for c in cols],
+                     "bytes_per_id": per_id, "gather_kernel_ms": kms, "GBps": gbs,
+                     "frac_of_peak": gbs / HBM_PEAK_GBS}
+        log(f"gather, {name}: {cnt} ids x {len(cols)} columns, {kms:.3f} ms, {gbs:.0f} GB/s")
+        del ids, outs, vouts
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_select_pushdown(ctx, small, fact_dt, star, log, reps=10):
@@ -611,15 +760,23 @@ def main():
             "kind": "oracle",
             "sample": f"the full {n}-row table, COUNT only (the oracle's count), "
                       f"row ranges split over {threads} threads; {dt_cpu:.2f} s wall",
+            "host": host_info(),
+            "per_workload": cpu_workloads(table, tree, threads, log),
         }
+    table_cols = [(c.type, c.valid is not None, c.name) for c in table.columns]
     del table
+    out["gather"] = bench_gather(ctx, dt, table_cols, log)
+    out["achievable"] = bench_achievable(log)
     if not args.no_sweeps:
         out["sweeps"] = bench_sweeps(ctx, dt, n, threads, log)
     small = star = None
     if not args.no_batch:
         out["batch"], small = bench_batch(ctx, dt, threads, log)
     if not args.no_star:
-        out["star"], star = bench_star(ctx, args.star_rows, threads, log)
+        out["star"], star = bench_star(ctx, args.star_rows, threads, log,
+                                       cpu="cpu_baseline" in out)
+        if "cpu_oracle" in out["star"]:
+            out["cpu_baseline"]["per_workload"]["star_480M"] = out["star"].pop("cpu_oracle")
     if small is not None and star is not None:
         out["select_pushdown"] = bench_select_pushdown(ctx, small, dt, star, log)
     if not args.no_serve and small is not None and star is not None:

@@ -256,6 +256,23 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact,
                           const uint32_t* const* d_bitmaps,
                           const uint64_t* nbits, uint64_t* out_count);
 
+/* Projected columns of a materialised sigma(R) (Ch.3 sec.3.3: the pushed-down
+ * selection is stored with the columns the query needs, while R is resident;
+ * Algorithm 1's CoalesceNodes fuses the selection with that projection).
+ * For k in [0, count): d_out[c][k] = column cols[c] of `table` at row
+ * d_ids[k] (values of the column's width, sign as stored), and, when
+ * d_valid_out is not NULL and d_valid_out[c] is not NULL, bit k % 32 of
+ * word k / 32 of d_valid_out[c] = that row's validity (1 = not NULL; every
+ * word up to ceil(count/32) is written whole, bits past count are 0).  The
+ * ids are typically sel_pushdown_rowids' output (ascending, any order
+ * works).  ncols in 1..16; cols, d_out and d_valid_out are host arrays of
+ * ncols entries; d_ids and the outputs are device memory, caller owned.
+ * Errors: SEL_E_INVALID for bad arguments (before any launch) or, after
+ * the launch, for ids >= the table's rows (their outputs are 0 and NULL). */
+sel_status sel_gather(sel_ctx* ctx, const sel_table* table, const uint32_t* d_ids, uint64_t count,
+                      uint32_t ncols, const uint32_t* cols, void* const* d_out,
+                      uint32_t* const* d_valid_out);
+
 /* ---- the push-down decision over a query's relations (Algorithm 1) ------ */
 
 /* One scanned relation R of a query: its table, the selection extracted for
@@ -486,7 +503,8 @@ typedef enum sel_kernel_kind {
   SEL_K_KEYBITMAP = 4,   /* dimension key bitmap build                  */
   SEL_K_STAR = 5,        /* star semi-join probe count                  */
   SEL_K_BATCH = 6,       /* persistent batched count                    */
-  SEL_K_NKINDS = 7
+  SEL_K_GATHER = 7,      /* projected columns by row id                 */
+  SEL_K_NKINDS = 8
 } sel_kernel_kind;
 
 typedef struct sel_timing {

@@ -13,6 +13,8 @@ Every function here restates the thesis' definitions (Shin 2018):
   keybitmap -- Ch.3 sec.3.3 / Algorithm 1: a pushed-down non-probe relation,
                kept as the set of its qualifying keys
   star_count-- fact rows whose foreign keys all hit those key sets
+  gather    -- Ch.3 sec.3.3: the materialised sigma(R) carries the columns
+               the query projects, read at its row ids
   select_pushdown -- Algorithm 1, EvaluateAndPushDown: the size-ordered
                queue of a query's relations, the probe relation skipped, and
                Execute(compound, true, maxSize) on each other one
@@ -211,6 +213,23 @@ class Oracle:
         return int(self.lib.oc_star_count(ctypes.byref(e) if e is not None else None,
                                           self._cols, self.table.nrows, nfk, fk.ctypes.data,
                                           ptrs, nb.ctypes.data, threads))
+
+
+def gather(table, ids, cols):
+    """The projected columns of a materialised selection (Ch.3 sec.3.3):
+    for each column index in `cols`, (values, valid) with values[k] the
+    stored value at row ids[k] and valid[k] False where that row is NULL."""
+    ids = np.asarray(ids, dtype=np.int64)
+    out = []
+    for c in cols:
+        col = table.columns[c]
+        vals = col.data[ids]
+        if col.valid is None:
+            valid = np.ones(ids.size, dtype=bool)
+        else:
+            valid = ((col.valid[ids >> 5] >> (ids & 31).astype(np.uint32)) & 1).astype(bool)
+        out.append((vals, valid))
+    return out
 
 
 def max_size(nrows: int, ratio: float) -> int:

@@ -642,6 +642,51 @@ sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t k
   return SEL_OK;
 }
 
+sel_status sel_gather(sel_ctx* ctx, const sel_table* table, const uint32_t* d_ids, uint64_t count,
+                      uint32_t ncols, const uint32_t* cols, void* const* d_out,
+                      uint32_t* const* d_valid_out) {
+  if (!ctx || !table) return set_err(ctx, SEL_E_INVALID, "NULL handle");
+  if (table->ctx != ctx) return set_err(ctx, SEL_E_INVALID, "table of another context");
+  if (ncols == 0 || ncols > kMaxGatherCols || !cols || !d_out)
+    return set_err(ctx, SEL_E_INVALID, "ncols must be 1..16 with column and output arrays");
+  if (count >= (1ull << 32)) return set_err(ctx, SEL_E_INVALID, "count must be < 2^32");
+  if (count > 0 && !d_ids) return set_err(ctx, SEL_E_INVALID, "d_ids is NULL");
+  GatherArgs a{};
+  a.ids = d_ids;
+  a.count = count;
+  a.nrows = table->nrows;
+  a.ncols = ncols;
+  for (uint32_t c = 0; c < ncols; ++c) {
+    if (cols[c] >= table->cols.size()) return set_err(ctx, SEL_E_INVALID, "column index out of range");
+    if (count > 0 && !d_out[c]) return set_err(ctx, SEL_E_INVALID, "output column is NULL");
+    const sel_column& col = table->cols[cols[c]];
+    GatherCol& g = a.cols[c];
+    g.src = col.data;
+    g.valid = col.valid;
+    g.out = d_out[c];
+    g.out_valid = d_valid_out ? d_valid_out[c] : nullptr;
+    g.width = col.type == SEL_I8 ? 1u : col.type == SEL_I16 ? 2u : col.type == SEL_I32 ? 4u : 8u;
+  }
+  if (count == 0) return SEL_OK;
+  DeviceGuard g(ctx->device);
+  a.slot = ctx->slot;
+  a.out = ctx->dout;
+  const uint32_t block = 256;   // 4 waves, each taking 256 consecutive outputs per step
+  const uint64_t want = (count + 4 * block - 1) / (4 * block);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)ctx->num_cus * 8);
+  {
+    TimedLaunch tl(ctx, SEL_K_GATHER);
+    const int e = sel_launch_gather(a, grid, block, ctx->stream);
+    tl.done();
+    if (e != 0) return hip_err(ctx, (hipError_t)e, "gather kernel launch");
+  }
+  uint64_t bad = 0;
+  const sel_status st = read_out(ctx, nullptr, &bad);
+  if (st != SEL_OK) return st;
+  if (bad) return set_err(ctx, SEL_E_INVALID, std::to_string(bad) + " row ids >= the table's rows");
+  return SEL_OK;
+}
+
 }  // extern "C"
 
 namespace {

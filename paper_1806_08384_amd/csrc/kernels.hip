@@ -603,6 +603,75 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
   }
 }
 
+// ---------------------------------------------------- projected columns --
+// Materialised sigma(R) with its projected columns (Ch.3 sec.3.3): each wave
+// takes kGatherUnroll x 64 consecutive outputs, loads all their row ids
+// first (coalesced; ascending ids make neighbouring lanes read neighbouring
+// rows), then per column issues every gather before any store; the validity
+// bits of each 64 outputs are one ballot, written as two words.  An id past
+// the table's rows gives 0 and NULL and is counted.
+constexpr int kGatherUnroll = 4;
+
+template <class T>
+__device__ __forceinline__ void gather_col(const GatherCol& C, uint64_t base, uint32_t lane,
+                                           const uint32_t (&row)[kGatherUnroll],
+                                           const bool (&in)[kGatherUnroll],
+                                           const bool (&ok)[kGatherUnroll]) {
+  const GLOBAL T* src = gptr<T>(C.src);
+  T v[kGatherUnroll];
+#pragma unroll
+  for (int j = 0; j < kGatherUnroll; ++j) v[j] = ok[j] ? src[row[j]] : (T)0;
+#pragma unroll
+  for (int j = 0; j < kGatherUnroll; ++j)
+    if (in[j]) ((T*)C.out)[base + 64 * j + lane] = v[j];
+}
+
+__global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kGatherUnroll;
+  uint32_t bad = 0;
+  for (uint64_t base = ((uint64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63u)) * kGatherUnroll;
+       base < a.count; base += stride) {
+    uint32_t row[kGatherUnroll];
+    bool in[kGatherUnroll], ok[kGatherUnroll];
+#pragma unroll
+    for (int j = 0; j < kGatherUnroll; ++j) {
+      const uint64_t k = base + 64 * j + lane;
+      in[j] = k < a.count;
+      row[j] = in[j] ? __builtin_nontemporal_load(gptr<uint32_t>(a.ids) + k) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kGatherUnroll; ++j) {
+      ok[j] = in[j] && row[j] < a.nrows;
+      bad += (in[j] && !ok[j]) ? 1u : 0u;
+    }
+    for (uint32_t c = 0; c < a.ncols; ++c) {
+      const GatherCol& C = a.cols[c];
+      switch (C.width) {
+        case 1: gather_col<uint8_t>(C, base, lane, row, in, ok); break;
+        case 2: gather_col<uint16_t>(C, base, lane, row, in, ok); break;
+        case 4: gather_col<uint32_t>(C, base, lane, row, in, ok); break;
+        default: gather_col<uint64_t>(C, base, lane, row, in, ok); break;
+      }
+      if (C.out_valid) {
+        uint32_t vw[kGatherUnroll];
+#pragma unroll
+        for (int j = 0; j < kGatherUnroll; ++j)
+          vw[j] = ok[j] && C.valid != nullptr ? gptr<uint32_t>(C.valid)[row[j] >> 5] : ~0u;
+#pragma unroll
+        for (int j = 0; j < kGatherUnroll; ++j) {
+          const bool v = ok[j] && ((vw[j] >> (row[j] & 31)) & 1u);
+          const uint64_t m = __ballot(v);
+          const uint64_t w = (base + 64 * j) >> 5;
+          if (lane == 0 && in[j]) C.out_valid[w] = (uint32_t)m;
+          if (lane == 32 && in[j]) C.out_valid[w + 1] = (uint32_t)(m >> 32);
+        }
+      }
+    }
+  }
+  finish(a.slot, a.out, 0u, bad, true);
+}
+
 // --------------------------------------------------------- batched count --
 // Column values of one pipeline segment: a full tile of a narrow column or
 // half a tile of an int64 column, 128 B per lane at most.  Narrow types use
@@ -1290,6 +1359,11 @@ int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* c
 
 int sel_launch_compact(const CompactArgs& a, uint32_t grid, uint32_t block, void* stream) {
   hipLaunchKernelGGL(k_compact, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int sel_launch_gather(const GatherArgs& a, uint32_t grid, uint32_t block, void* stream) {
+  hipLaunchKernelGGL(k_gather, dim3(grid), dim3(block), 0, (hipStream_t)stream, a);
   return (int)hipGetLastError();
 }
 

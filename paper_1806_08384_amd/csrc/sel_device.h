@@ -107,6 +107,29 @@ struct CompactArgs {
   uint64_t cap;
 };
 
+// Projected columns of a materialised sigma(R): value k of each output
+// column is the source column's value at row ids[k] (and bit k of its
+// validity words that row's validity); at most kMaxGatherCols columns per
+// launch, all passed by value.
+constexpr uint32_t kMaxGatherCols = 16;
+struct GatherCol {             // 40 bytes
+  const void* src;
+  const uint32_t* valid;       // nullptr: the column has no NULLs
+  void* out;
+  uint32_t* out_valid;         // nullptr: no validity wanted
+  uint32_t width;              // bytes per value: 1, 2, 4 or 8
+  uint32_t pad;
+};
+struct GatherArgs {
+  const uint32_t* ids;
+  uint64_t count;
+  uint64_t nrows;
+  DevSlot* slot;
+  unsigned long long* out;     // out[1]: ids >= nrows
+  uint32_t ncols, pad;
+  GatherCol cols[kMaxGatherCols];
+};
+
 // Batched count (many programs over several tables in one launch),
 // evaluated leaf-major.  Tiles of all entries form one flat index space.  For
 // its tile a wave loads each column the entry's programs read once, runs
@@ -282,6 +305,7 @@ int sel_launch_scan(int mode, const sel::ScanArgs& a, uint32_t grid, uint32_t bl
 int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* chunk_sums,
                           uint32_t* chunk_offs, uint64_t n, void* stream);
 int sel_launch_compact(const sel::CompactArgs& a, uint32_t grid, uint32_t block, void* stream);
+int sel_launch_gather(const sel::GatherArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream);
 int sel_launch_tables(const sel::TableBuild* d_builds, uint32_t nbuilds, uint64_t nentries,
                       void* stream);

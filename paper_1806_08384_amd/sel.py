@@ -37,7 +37,7 @@ TYPES = {"i8": 1, "i16": 2, "i32": 3, "i64": 4}
 OP = {"=": 1, "<>": 2, "<": 3, "<=": 4, ">": 5, ">=": 6, "between": 7, "in": 8, "codeset": 9,
       "isnull": 10, "notnull": 11, "and": 16, "or": 17, "not": 18, "isunknown": 19,
       "true": 20, "false": 21}
-K_COUNT, K_MASK, K_SCAN, K_COMPACT, K_KEYBITMAP, K_STAR, K_BATCH, K_NKINDS = range(8)
+K_COUNT, K_MASK, K_SCAN, K_COMPACT, K_KEYBITMAP, K_STAR, K_BATCH, K_GATHER, K_NKINDS = range(9)
 INT64_MIN, INT64_MAX = -(2 ** 63), 2 ** 63 - 1
 UINT64_MAX = 2 ** 64 - 1
 
@@ -144,6 +144,7 @@ sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i
 sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
                       _P(_u64))
 sel_count_batch = _sig("sel_count_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_u64))
+sel_gather = _sig("sel_gather", _i32, _vp, _vp, _vp, _u64, _u32, _P(_u32), _P(_vp), _P(_vp))
 sel_select_pushdown = _sig("sel_select_pushdown", _i32, _vp, _u32, _P(sel_spd_relation), _u64,
                            ctypes.c_double, _P(sel_spd_result))
 sel_batch_create = _sig("sel_batch_create", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_vp))
@@ -337,6 +338,20 @@ class Context:
         st = sel_pushdown_rowids(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
         self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
         return st, int(out.value)
+
+    def gather(self, table, ids_tensor, count: int, cols, outs, valid_outs=None):
+        """Projected columns of a materialised selection: outs[c][:count] =
+        column cols[c] at rows ids_tensor[:count]; valid_outs[c] (or None)
+        receives the validity bits."""
+        n = len(cols)
+        cidx = (ctypes.c_uint32 * max(1, n))(*cols)
+        optr = (ctypes.c_void_p * max(1, n))(*[o.data_ptr() for o in outs])
+        vptr = None
+        if valid_outs is not None:
+            vptr = (ctypes.c_void_p * max(1, n))(*[v.data_ptr() if v is not None else None
+                                                   for v in valid_outs])
+        self.check(sel_gather(self.h, table.h, ids_tensor.data_ptr() if ids_tensor is not None else None,
+                              count, n, cidx, optr, vptr))
 
     def select_pushdown(self, relations, min_table_size: int = 1000, max_selectivity: float = 0.05):
         """Algorithm 1 over [(table, program or None, out tensor or None)]:

@@ -263,7 +263,18 @@ def test_cfg2_full_size(sel, ctx):
         want_ids = oracle.Oracle(sub).rowids(tree).astype(np.int64) + lo
         got_ids = ids[(ids >= lo) & (ids < hi)]
         np.testing.assert_array_equal(got_ids, want_ids)
-    del out
+    # the selection's projected columns (date, qty, price with NULLs, s25)
+    # gathered at its ids, against numpy indexing of the host table
+    cols = [0, 1, 3, 5]
+    outs = [torch.empty(cnt, dtype=getattr(torch, {"i8": "int8", "i32": "int32", "i64": "int64"}[
+        t.columns[c].type]), device="cuda") for c in cols]
+    vouts = [torch.empty((cnt + 31) // 32, dtype=torch.int32, device="cuda") for _ in cols]
+    ctx.gather(dt, out, cnt, cols, outs, vouts)
+    for c, o, vo, (wv, wvalid) in zip(cols, outs, vouts, oracle.gather(t, ids, cols)):
+        np.testing.assert_array_equal(o.cpu().numpy(), wv)
+        bits = np.unpackbits(as_u32(vo).view(np.uint8), bitorder="little")[:cnt].astype(bool)
+        np.testing.assert_array_equal(bits, wvalid)
+    del out, outs, vouts
     # a date range holding about 90 % of the rows: 270M ascending ids (1.08
     # GB), the limit one below the count refuses them, the count itself
     # accepts them

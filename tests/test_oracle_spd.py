@@ -1,4 +1,5 @@
-"""CPU pins of the oracle's Algorithm 1 (EvaluateAndPushDown, Ch.4 sec.4.2).
+"""CPU pins of the oracle's Algorithm 1 (EvaluateAndPushDown, Ch.4 sec.4.2)
+and of its projected-column gather (Ch.3 sec.3.3).
 
 The relations here have a column that holds the row index, so a range
 predicate [a, b] selects exactly rows a..b: every count and id list below is
@@ -94,3 +95,27 @@ def test_max_size_rounding_reading():
     assert oracle.max_size(7, float("nan")) == 0
     assert oracle.max_size(7, -1.0) == 0 and oracle.max_size(7, 2.0) == 7
     assert oracle.max_size(300_000_000, 0.05) == 15_000_000
+
+
+def test_gather_closed_forms():
+    """The oracle's projected columns on columns whose value and validity are
+    closed forms of the row: value 3r + 7 (wrapped to the type) and NULL
+    exactly where r % 3 == 0."""
+    n = 10_000
+    r = np.arange(n, dtype=np.int64)
+    t = datagen.Table("g", n)
+    isnull = r % 3 == 0
+    bits = np.packbits(~isnull, bitorder="little")
+    words = np.zeros((n + 31) // 32 * 4, dtype=np.uint8)
+    words[: bits.size] = bits
+    words = words.view(np.uint32)
+    for ty, dt in (("i8", np.int8), ("i16", np.int16), ("i32", np.int32), ("i64", np.int64)):
+        t.columns.append(datagen.Column(ty, ty, (3 * r + 7).astype(dt), valid=words))
+    ids = np.array([0, 1, 2, 3, 85, 86, 9_999], dtype=np.uint32)
+    got = oracle.gather(t, ids, [0, 1, 2, 3])
+    for (vals, valid), dt in zip(got, (np.int8, np.int16, np.int32, np.int64)):
+        want = [(3 * int(i) + 7) for i in ids]
+        assert [int(v) for v in vals] == [int(np.array(w).astype(dt)) for w in want]
+        assert list(valid) == [int(i) % 3 != 0 for i in ids]
+    # the int8 column wraps: row 85 holds 262 mod 256 = 6, row 86 holds 265 - 256 = 9
+    assert int(got[0][0][4]) == 6 and int(got[0][0][5]) == 9
