@@ -285,7 +285,7 @@ def bench_achievable(log, gib=4, reps=10):
     stream; the lines against which the scan and the gather are read."""
     import torch
     n = (gib << 30) // 4
-    x = torch.ones(n, dtype=torch.int32, device="cuda")
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
 
     def rate(fn, nbytes):
@@ -301,7 +301,7 @@ def bench_achievable(log, gib=4, reps=10):
         return {"ms": ms, "GBps": nbytes / ms / 1e6, "frac_of_peak": nbytes / ms / 1e6 / HBM_PEAK_GBS}
 
     res = {"bytes": 4 * n,
-           "read_only_sum": rate(lambda: torch.sum(x, dtype=torch.int64), 4 * n),
+           "read_only_sum": rate(lambda: torch.sum(x), 4 * n),
            "copy": rate(lambda: y.copy_(x), 8 * n)}
     log(f"achievable: read {res['read_only_sum']['GBps']:.0f} GB/s, copy {res['copy']['GBps']:.0f} GB/s")
     del x, y
@@ -349,6 +349,37 @@ def bench_gather(ctx, dt, table_cols, log, reps=5):
         del ids, outs, vouts
     torch.cuda.empty_cache()
     return res
+
+
+def bench_estimate_error(ctx, small, fact_dt, log):
+    """What exact counting replaces (Ch.1 sec.1.1): for the 6-leaf fact
+    predicate and for the 64 batching programs, the product of the
+    conjuncts' selectivities (the independence estimate) against the exact
+    count, from each program's conjunct counts (one batched launch each)."""
+    import datagen
+    dts = list(small) + [fact_dt]
+    prog = ctx.program(fact_dt, datagen.cfg2_predicate())
+    c, fc = ctx.factor_counts(fact_dt, prog)
+    est = ctx.independence_estimate(fact_dt.nrows, fc)
+    qs = []
+    t0 = time.perf_counter()
+    for ti, tree in datagen.cfg3_programs():
+        p = ctx.program(dts[ti], tree)
+        cc, ff = ctx.factor_counts(dts[ti], p)
+        e = ctx.independence_estimate(dts[ti].nrows, ff)
+        qs.append(max(max(e, 1.0) / max(cc, 1.0), max(cc, 1.0) / max(e, 1.0)))
+    dt = time.perf_counter() - t0
+    qs.sort()
+    q = lambda f: qs[min(len(qs) - 1, int(round(f * (len(qs) - 1))))]
+    log(f"estimate error: fact predicate exact {c}, independence {est:.0f}; "
+        f"64 programs q-error median {q(0.5):.2f}, max {qs[-1]:.1f}")
+    return {
+        "fact_predicate": {"rows": fact_dt.nrows, "exact": c, "conjunct_counts": fc,
+                           "independence_estimate": est,
+                           "q_error": max(max(est, 1.0) / max(c, 1.0), max(c, 1.0) / max(est, 1.0))},
+        "batch_64_programs": {"q_error_median": q(0.5), "q_error_p90": q(0.9),
+                              "q_error_max": qs[-1], "calls_s": dt},
+    }
 
 
 def bench_select_pushdown(ctx, small, fact_dt, star, log, reps=10):
@@ -777,6 +808,8 @@ def main():
                                        cpu="cpu_baseline" in out)
         if "cpu_oracle" in out["star"]:
             out["cpu_baseline"]["per_workload"]["star_480M"] = out["star"].pop("cpu_oracle")
+    if small is not None:
+        out["estimate_error"] = bench_estimate_error(ctx, small, dt, log)
     if small is not None and star is not None:
         out["select_pushdown"] = bench_select_pushdown(ctx, small, dt, star, log)
     if not args.no_serve and small is not None and star is not None:

@@ -365,6 +365,26 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
                             const uint32_t* const* d_bitmaps, const uint64_t* nbits,
                             sel_program** out);
 
+/* ---- conjunct counts: the estimate that exact counting replaces --------- */
+
+/* Exact counts of the top-level AND factors (conjuncts) of a selection and
+ * of the whole selection, in one batched launch: the figures behind the
+ * worked example of Ch.1 sec.1.1, where the product of per-predicate
+ * selectivities (the attribute-value independence assumption of
+ * statistics-based estimators) gives 0.0015 while the selection's true
+ * selectivity is 0.167.  *nfactors = number of factors (1 if the root is
+ * not an AND), in the order the compiled program evaluates them (the
+ * compiler may reorder operands); factor_counts (host, cap entries) receives
+ * their counts and *count the selection's count.  Errors: SEL_E_INVALID;
+ * SEL_E_CAPACITY (positive) when *nfactors > cap, with nothing counted. */
+sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                             uint32_t cap, uint64_t* factor_counts, uint32_t* nfactors,
+                             uint64_t* count);
+
+/* The independence estimate of a conjunction's count: nrows * prod over
+ * the n factors of (counts[k] / nrows), in double; 0 when nrows is 0. */
+double sel_independence_estimate(uint64_t nrows, uint32_t n, const uint64_t* counts);
+
 /* ---- serving: continuous batching of estimate requests ------------------ */
 
 /* A server keeps the tables resident (they are the caller's) and answers

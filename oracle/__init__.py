@@ -15,6 +15,9 @@ Every function here restates the thesis' definitions (Shin 2018):
   star_count-- fact rows whose foreign keys all hit those key sets
   gather    -- Ch.3 sec.3.3: the materialised sigma(R) carries the columns
                the query projects, read at its row ids
+  factor_counts, independence_estimate, q_error -- Ch.1 sec.1.1: the
+               counts of a selection's conjuncts, the product estimate that
+               assumes them independent, and its error against the count
   select_pushdown -- Algorithm 1, EvaluateAndPushDown: the size-ordered
                queue of a query's relations, the probe relation skipped, and
                Execute(compound, true, maxSize) on each other one
@@ -213,6 +216,41 @@ class Oracle:
         return int(self.lib.oc_star_count(ctypes.byref(e) if e is not None else None,
                                           self._cols, self.table.nrows, nfk, fk.ctypes.data,
                                           ptrs, nb.ctypes.data, threads))
+
+
+def and_factors(tree):
+    """The conjuncts of a predicate tree: the operands of its top-level AND,
+    nested ANDs flattened; the tree itself if its root is not an AND."""
+    if tree[0] != "and":
+        return [tree]
+    out = []
+    for t in tree[1:]:
+        out += and_factors(t)
+    return out
+
+
+def factor_counts(table, tree, threads: int = 1):
+    """(count of the selection, [count of each conjunct])."""
+    orc = Oracle(table)
+    return orc.count(tree, threads), [orc.count(f, threads) for f in and_factors(tree)]
+
+
+def independence_estimate(nrows: int, counts) -> float:
+    """|R| times the product of the conjuncts' selectivities: the estimate of
+    a conjunction under the attribute-value independence assumption (the
+    0.2 x 0.167 x 0.167 x 0.27 of Ch.1 sec.1.1)."""
+    if nrows == 0:
+        return 0.0
+    e = float(nrows)
+    for c in counts:
+        e *= float(c) / float(nrows)
+    return e
+
+
+def q_error(estimate: float, exact: int) -> float:
+    """max(estimate / exact, exact / estimate), both taken as at least 1 row."""
+    e, x = max(float(estimate), 1.0), max(float(exact), 1.0)
+    return max(e / x, x / e)
 
 
 def gather(table, ids, cols):

@@ -360,3 +360,47 @@ void sel_batch_destroy(sel_batch* b) {
 }
 
 }  // extern "C"
+
+// ---- conjunct counts beside the whole selection's (Ch.1 sec.1.1) ----------
+
+sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                             uint32_t cap, uint64_t* factor_counts, uint32_t* nfactors,
+                             uint64_t* count) {
+  if (!ctx) return SEL_E_INVALID;
+  if (!nfactors || !count) return set_err(ctx, SEL_E_INVALID, "NULL output");
+  if (!table || !prog) return set_err(ctx, SEL_E_INVALID, "NULL handle");
+  if (prog->table != table) return set_err(ctx, SEL_E_INVALID, "program is bound to another table");
+  const auto ranges = and_factors(prog->host_code);
+  *nfactors = (uint32_t)ranges.size();
+  if (ranges.size() > cap) return set_err(ctx, SEL_E_CAPACITY, "more factors than the output holds");
+  if (!factor_counts) return set_err(ctx, SEL_E_INVALID, "factor_counts is NULL");
+  // each factor as a program of its own, for the batch planner only (it
+  // reads the host copy of the code; the constants stay in prog's device
+  // blob)
+  std::vector<sel_program> fp(ranges.size());
+  std::vector<const sel_program*> progs{prog};
+  for (size_t k = 0; k < ranges.size(); ++k) {
+    sel_program& f = fp[k];
+    f.ctx = ctx;
+    f.table = table;
+    f.host_code.assign(prog->host_code.begin() + ranges[k].first,
+                       prog->host_code.begin() + ranges[k].second);
+    f.nins = (uint32_t)f.host_code.size();
+    progs.push_back(&f);
+  }
+  std::vector<const sel_table*> tabs(progs.size(), table);
+  std::vector<uint64_t> out(progs.size());
+  const sel_status st = sel_count_batch(ctx, (uint32_t)progs.size(), tabs.data(), progs.data(), out.data());
+  if (st != SEL_OK) return st;
+  *count = out[0];
+  for (size_t k = 0; k < ranges.size(); ++k) factor_counts[k] = out[k + 1];
+  return SEL_OK;
+}
+
+double sel_independence_estimate(uint64_t nrows, uint32_t n, const uint64_t* counts) {
+  if (nrows == 0) return 0.0;
+  double e = (double)nrows;
+  for (uint32_t k = 0; k < n; ++k) e *= (double)counts[k] / (double)nrows;
+  return e;
+}
+

@@ -416,6 +416,12 @@ struct Pass {
 
 uint32_t batch_slots_alone(const sel_program* p) { return Pass{}.new_slots(p); }
 
+std::vector<std::pair<size_t, size_t>> and_factors(const std::vector<DevInstr>& code) {
+  Factors F = split_and(code);
+  if (!F.ok) return {{0, code.size()}};
+  return F.ranges;
+}
+
 void BatchPlan::clear() {
   entries.clear();
   cols.clear();

@@ -222,6 +222,10 @@ struct BatchPlan {
   uint32_t default_block() const { return lds_bytes(sel::kBatchBlock) <= sel::kLdsPerCu ? sel::kBatchBlock : 512u; }
 };
 
+// The postfix ranges [begin, end) of a program's top-level AND factors,
+// left to right as the program evaluates them (the whole program if its root
+// is not an AND).
+std::vector<std::pair<size_t, size_t>> and_factors(const std::vector<sel::DevInstr>& code);
 // LDS slots a program needs in a pass of its own (distinct leaves plus
 // validity words); batching requires at most kBatchMaxSlots.
 uint32_t batch_slots_alone(const sel_program* p);

@@ -144,6 +144,8 @@ sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i
 sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
                       _P(_u64))
 sel_count_batch = _sig("sel_count_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_u64))
+sel_factor_counts = _sig("sel_factor_counts", _i32, _vp, _vp, _vp, _u32, _P(_u64), _P(_u32), _P(_u64))
+sel_independence_estimate = _sig("sel_independence_estimate", ctypes.c_double, _u64, _u32, _P(_u64))
 sel_gather = _sig("sel_gather", _i32, _vp, _vp, _vp, _u64, _u32, _P(_u32), _P(_vp), _P(_vp))
 sel_select_pushdown = _sig("sel_select_pushdown", _i32, _vp, _u32, _P(sel_spd_relation), _u64,
                            ctypes.c_double, _P(sel_spd_result))
@@ -338,6 +340,19 @@ class Context:
         st = sel_pushdown_rowids(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
         self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
         return st, int(out.value)
+
+    def factor_counts(self, table, prog):
+        """(exact count, [exact count of each top-level AND factor]) in one
+        batched launch; the factors in the program's evaluation order."""
+        fc = (ctypes.c_uint64 * 32)()
+        nf, cnt = _u32(0), _u64(0)
+        self.check(sel_factor_counts(self.h, table.h, prog.h, 32, fc, ctypes.byref(nf), ctypes.byref(cnt)))
+        return int(cnt.value), [int(fc[k]) for k in range(nf.value)]
+
+    @staticmethod
+    def independence_estimate(nrows: int, counts) -> float:
+        arr = (ctypes.c_uint64 * max(1, len(counts)))(*counts)
+        return float(sel_independence_estimate(nrows, len(counts), arr))
 
     def gather(self, table, ids_tensor, count: int, cols, outs, valid_outs=None):
         """Projected columns of a materialised selection: outs[c][:count] =

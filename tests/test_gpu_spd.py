@@ -1,6 +1,7 @@
 """GPU: the push-down decision of Algorithm 1 (sel_select_pushdown through
 the C ABI) against the oracle's step-by-step EvaluateAndPushDown: the same
-decisions, queue order, exact counts, limits and ascending row ids."""
+decisions, queue order, exact counts, limits and ascending row ids; and the
+conjunct counts behind the independence estimate (sel_factor_counts)."""
 import numpy as np
 import pytest
 
@@ -114,3 +115,30 @@ def test_spd_rejects_bad_input(sel, ctx):
     pe = ctx.program(b, ("cmp", 0, ">", 10 ** 6))
     r = ctx.select_pushdown([(a, None, None), (b, pe, None)])
     assert r[1]["decision"] == "pushed" and r[1]["count"] == 0
+
+
+def test_factor_counts_match_oracle(sel, ctx):
+    """A selection's conjunct counts and its own count, from one batched
+    launch, equal the oracle's (as multisets: the compiler may reorder
+    operands), and so does the independence estimate built from them; on
+    random programs with NULLs and on the fact-table predicate."""
+    rng = np.random.default_rng(73_000)
+    t = datagen.random_table(rng, 100_003, grid=False, null_rate=0.2)
+    dt = sel.device_table(ctx, t)
+    trees = [sqlite_ref.clamp_literals(datagen.random_tree(rng, t, grid=False)) for _ in range(12)]
+    for _ in range(3):
+        trees.append(("and",) + tuple(sqlite_ref.clamp_literals(
+            datagen.random_tree(rng, t, max_depth=3, max_leaves=3, grid=False)) for _ in range(5)))
+    for tree in trees:
+        prog = ctx.program(dt, tree)
+        c, fc = ctx.factor_counts(dt, prog)
+        wc, wfc = oracle.factor_counts(t, tree)
+        assert c == wc and sorted(fc) == sorted(wfc), tree
+        assert ctx.independence_estimate(t.nrows, fc) == pytest.approx(
+            oracle.independence_estimate(t.nrows, wfc), rel=1e-12)
+    f = datagen.cfg2(n=2_000_003, threads=16)
+    df = sel.device_table(ctx, f)
+    tree = datagen.cfg2_predicate()
+    c, fc = ctx.factor_counts(df, ctx.program(df, tree))
+    wc, wfc = oracle.factor_counts(f, tree, threads=16)
+    assert c == wc and len(fc) == 4 and sorted(fc) == sorted(wfc)
