@@ -134,13 +134,20 @@ struct Pass {
   std::vector<BatchBitmap> bms;             // staged in LDS
   std::map<const void*, uint32_t> bm_at;    // source -> its BatchBitmap
   uint32_t bm_words = 0;
+  uint32_t bm_budget = 0;                   // LDS words for tables and bitmaps
 
-  // Lookup tables and staged bitmaps, within kBatchBmWords words: first a
+  // Lookup tables and staged bitmaps, within the LDS words the pass's slots
+  // leave (bm_budget): first a
   // table for each narrow column whose value-test leaves (bitmaps and
   // ranges, at most 32) cost more per row than a lookup, most leaves first;
   // then the bitmaps of the remaining leaves.  Table leaves move to the
   // front of their column.
   void finalize() {
+    // the LDS the pass's slots leave for its tables and bitmaps: every wave
+    // of a 768-thread workgroup, or of a 512-thread one past kBatchSlots
+    const int64_t waves = slots > kBatchSlots ? 512 / kWave : kBatchBlock / kWave;
+    const int64_t left = (int64_t)kLdsPerCu - 4 * (int64_t)kBatchMaxProgs - (int64_t)slots * 256 * waves;
+    bm_budget = left > 0 ? (uint32_t)(left / 4) : 0u;
     std::vector<PassCol*> order;
     for (PassCol& c : cols) order.push_back(&c);
     std::stable_sort(order.begin(), order.end(),
@@ -179,7 +186,7 @@ struct Pass {
       for (const DevInstr& L : tab) guarded &= L.flags != kNoGuard;
       const uint64_t bytes = (n + 1) * tab_entry_bytes((uint32_t)tab.size());
       if (round == 0) {
-        if ((bytes + 3) / 4 > kBatchBmWords - bm_words) continue;
+        if ((bytes + 3) / 4 > bm_budget - bm_words) continue;
         c->tab_word = bm_words;
         bm_words += (uint32_t)((bytes + 3) / 4);
       } else {
@@ -211,7 +218,7 @@ struct Pass {
     const uint64_t words = (nbits + 31) / 32;
     auto it = bm_at.find(L.aux);
     if (it == bm_at.end() || bms[it->second].words != words) {
-      if (bm_words + words + 1 > kBatchBmWords) return;
+      if (bm_words + words + 1 > bm_budget) return;
       BatchBitmap b{};
       b.src = (const uint32_t*)L.aux;
       b.words = (uint32_t)words;
@@ -435,7 +442,6 @@ void BatchPlan::clear() {
   table_entries = 0;
   total_tiles = 0;
   max_slots = 0;
-  max_bm_words = 0;
 }
 
 void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
@@ -456,6 +462,8 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     e.ntiles = tiles;
     e.init_begin = (uint32_t)ops.size();
     e.init_count = (uint32_t)ps.inits.size();
+    e.bm_words = ps.bm_words;
+    e.slot_words = ps.slots * (uint32_t)kWave;
     ops.insert(ops.end(), ps.inits.begin(), ps.inits.end());
     e.bm_begin = (uint32_t)bms.size();
     e.bm_count = (uint32_t)ps.bms.size();
@@ -508,7 +516,6 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     }
     entries.push_back(e);
     max_slots = std::max(max_slots, ps.slots);
-    max_bm_words = std::max(max_bm_words, ps.bm_words);
     total_tiles += (tiles + kBatchTileAlign - 1) / kBatchTileAlign * kBatchTileAlign;
   };
   // Pack programs that read the same wide columns into the same passes, so
@@ -591,8 +598,6 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
   a.ntables = (uint32_t)entries.size();
   a.nprogs = (uint32_t)progs.size();
   a.total_tiles = total_tiles;
-  a.slot_words = max_slots * (uint32_t)kWave;
-  a.bm_words = max_bm_words;
   a.acc_words = acc_words();
 }
 

@@ -1159,7 +1159,7 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   const uint32_t nacc = a.acc_words;   // min(nprogs, kBatchMaxProgs)
   uint32_t* acc = dyn;
   uint32_t* bmlds = dyn + nacc;
-  uint32_t* wl = bmlds + a.bm_words + wave * a.slot_words;
+  uint32_t* wl = bmlds;   // this wave's slots, placed by each pass's layout
   for (uint32_t p = threadIdx.x; p < nacc; p += blockDim.x) acc[p] = 0;
   __syncthreads();
   const CONSTANT BatchTable* tables = (const CONSTANT BatchTable*)a.tables;
@@ -1168,8 +1168,9 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   const CONSTANT BatchProg* progs = (const CONSTANT BatchProg*)a.progs;
   const CONSTANT BatchBitmap* bms = (const CONSTANT BatchBitmap*)a.bms;
   // the workgroup takes groups of nw consecutive tiles; entry ranges are
-  // padded to multiples of kBatchTileAlign, so a group never straddles two entries and the
-  // loop below (with its barriers) is uniform over the workgroup
+  // padded to multiples of kBatchTileAlign, so a group never straddles two
+  // entries and the loop below (with its barriers) is uniform over the
+  // workgroup
   const uint64_t ngroups = a.total_tiles / nw;
   uint32_t staged = 0xFFFFFFFFu;
   for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
@@ -1182,50 +1183,55 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
     }
     lo = uni(lo);
     const CONSTANT BatchTable* E = tables + lo;
-    if ((E->bm_count || E->ntab) && lo != staged) {
-      __syncthreads();   // every wave is done with the previous tables
-      for (uint32_t c = 0; c < E->col_count; ++c) {
-        const CONSTANT BatchCol* C = cols + E->col_begin + c;
-        if (C->tab_word == kNoLds) continue;
-        const uint32_t n = C->tab_n, m = C->tab_count;
-        const int64_t L = C->tab_lo;
-        CInstr tl = leaves + C->leaf_begin;
-        uint32_t* dst = bmlds + C->tab_word;
-        const uint32_t eb = tab_entry_bytes(m);
-        for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
-          uint32_t w = 0;
-          if (i < n) {
-            const int64_t x = L + (int64_t)i;
-            for (uint32_t k = 0; k < m; ++k) {
-              CInstr I = tl + k;
-              const uint64_t d = (uint64_t)x - (uint64_t)I->lo;
-              uint32_t bit;
-              if (I->op == D_RANGE) {
-                bit = d <= I->span;
-              } else {  // D_BITMAP
-                const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
-                bit = d < I->span ? (bits[d >> 5] >> (d & 31)) & 1u : 0u;
-              }
-              w |= bit << k;
-            }
-          }
-          if (eb == 1) ((uint8_t*)dst)[i] = (uint8_t)w;
-          else if (eb == 2) ((uint16_t*)dst)[i] = (uint16_t)w;
-          else dst[i] = w;
-        }
-      }
-      for (uint32_t k = 0; k < E->bm_count; ++k) {
-        const CONSTANT BatchBitmap* B = bms + E->bm_begin + k;
-        const uint32_t n = B->words, last = B->last_mask;
-        const GLOBAL uint32_t* src = gptr<uint32_t>(B->src);
-        uint32_t* dst = bmlds + B->lds_word;
-        for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
-          uint32_t w = 0;
-          if (i < n) w = i + 1 == n ? src[i] & last : src[i];
-          dst[i] = w;
-        }
-      }
+    if (lo != staged) {
+      // a new pass: its own LDS layout (tables, bitmaps, slots), so every
+      // wave must be done with the previous one's first
       __syncthreads();
+      wl = bmlds + E->bm_words + wave * E->slot_words;
+      if (E->bm_count || E->ntab) {
+        for (uint32_t c = 0; c < E->col_count; ++c) {
+          const CONSTANT BatchCol* C = cols + E->col_begin + c;
+          if (C->tab_word == kNoLds) continue;
+          const uint32_t n = C->tab_n, m = C->tab_count;
+          const int64_t L = C->tab_lo;
+          CInstr tl = leaves + C->leaf_begin;
+          uint32_t* dst = bmlds + C->tab_word;
+          const uint32_t eb = tab_entry_bytes(m);
+          for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
+            uint32_t w = 0;
+            if (i < n) {
+              const int64_t x = L + (int64_t)i;
+              for (uint32_t k = 0; k < m; ++k) {
+                CInstr I = tl + k;
+                const uint64_t d = (uint64_t)x - (uint64_t)I->lo;
+                uint32_t bit;
+                if (I->op == D_RANGE) {
+                  bit = d <= I->span;
+                } else {  // D_BITMAP
+                  const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
+                  bit = d < I->span ? (bits[d >> 5] >> (d & 31)) & 1u : 0u;
+                }
+                w |= bit << k;
+              }
+            }
+            if (eb == 1) ((uint8_t*)dst)[i] = (uint8_t)w;
+            else if (eb == 2) ((uint16_t*)dst)[i] = (uint16_t)w;
+            else dst[i] = w;
+          }
+        }
+        for (uint32_t k = 0; k < E->bm_count; ++k) {
+          const CONSTANT BatchBitmap* B = bms + E->bm_begin + k;
+          const uint32_t n = B->words, last = B->last_mask;
+          const GLOBAL uint32_t* src = gptr<uint32_t>(B->src);
+          uint32_t* dst = bmlds + B->lds_word;
+          for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
+            uint32_t w = 0;
+            if (i < n) w = i + 1 == n ? src[i] & last : src[i];
+            dst[i] = w;
+          }
+        }
+        __syncthreads();
+      }
       staged = lo;
     }
     const uint64_t local = flat - E->tile_begin;

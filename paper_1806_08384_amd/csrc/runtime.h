@@ -195,7 +195,6 @@ struct BatchPlan {
   uint64_t table_entries = 0;            // entries k_tables writes
   uint64_t total_tiles = 0;
   uint32_t max_slots = 0;
-  uint32_t max_bm_words = 0;
   void clear();
   // acc[k]: accumulator line of progs[k].  Programs of an empty range add
   // nothing (their lines stay zero).
@@ -214,8 +213,13 @@ struct BatchPlan {
   uint32_t acc_words() const {
     return (uint32_t)std::min<size_t>(progs.size(), (size_t)sel::kBatchMaxProgs);
   }
+  // Dynamic LDS of the batch kernel: the largest pass layout (counters,
+  // tables and bitmaps, every wave's slots).
   uint32_t lds_bytes(uint32_t block) const {
-    return 4u * (acc_words() + max_bm_words) + max_slots * 256u * (block / 64);
+    uint32_t m = 0;
+    for (const sel::BatchTable& e : entries)
+      m = std::max(m, 4u * (acc_words() + e.bm_words + e.slot_words * (block / 64)));
+    return m;
   }
   // Workgroup size: kBatchBlock when its LDS fits a CU, else 512 (a pass
   // with more than kBatchSlots slots).

@@ -149,13 +149,13 @@ constexpr uint32_t kNoSlot = 0xFFFu;
 constexpr uint32_t kNoGuard = 0xFFFFFFFFu;
 // When a pass starts on a workgroup it builds, in LDS, a lookup table for
 // each narrow column with several leaves (entry x - lo holds one bit per
-// leaf), and stages the bitmaps of other leaves (code sets, IN lists); at
-// most this many words per workgroup in all.  The batch kernel runs one
-// workgroup per CU whose waves share one set of tables: 768 threads (twelve
-// waves, three per SIMD) when every pass fits 40 slots, 12 x 40 slots x
-// 256 B + 28 KB of tables + at most 4 KB of counters = 152 KB; else 512
-// threads with up to 64 slots, 8 x 64 x 256 B + 32 KB = 160 KB.
-constexpr uint32_t kBatchBmWords = 7168;
+// leaf), and stages the bitmaps of other leaves (code sets, IN lists).  The
+// batch kernel runs one workgroup per CU whose waves share one set of
+// tables: 768 threads (twelve waves, three per SIMD) when every pass fits
+// kBatchSlots slots, else 512 threads.  Each pass lays out the LDS for
+// itself: at most 4 KB of per-program counters, its tables and bitmaps, and
+// its slots for every wave; the tables get what the slots leave of 160 KB
+// (7168 words with 64 slots in 8 waves, 9216 with 40 in 12, 27648 with 16).
 constexpr uint32_t kBatchBlock = 768;
 constexpr uint32_t kLdsPerCu = 160u * 1024u;
 // Bytes per lookup-table entry (LDS or device memory): the narrowest of 1,
@@ -217,7 +217,9 @@ struct BatchTable {            // 80 bytes: one pass over a table or a chunk
   uint32_t ntab;               // columns with a lookup table
   uint32_t init_begin;         // accumulator reset list, in the ops array
   uint32_t init_count;
-  uint32_t pad[3];
+  uint32_t bm_words;           // LDS layout of this pass: words of its tables
+  uint32_t slot_words;         // and staged bitmaps; each wave's slots (slots * 64)
+  uint32_t pad;
 };
 
 struct BatchBitmap {           // 24 bytes: a bitmap staged in LDS (batch or scan)
@@ -290,8 +292,6 @@ struct BatchArgs {
   // Lines not listed keep accumulating across launches.
   const uint32_t* done;
   uint32_t ndone;
-  uint32_t slot_words;         // LDS words per wave: slots * 64
-  uint32_t bm_words;           // LDS words of staged bitmaps per workgroup
   uint32_t acc_words;          // LDS counters: min(nprogs, kBatchMaxProgs)
   unsigned long long* out;
   DevSlot* slot;
