@@ -658,6 +658,10 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the selectivity / leaf-count sweeps and the bandwidth probe")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip everything beyond the step, the count query, the batch, the star "
+                         "probe and serving (sweeps, gather, achievable rates, estimate error, "
+                         "Algorithm 1), e.g. to profile those kernels alone")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB once (a plain "
                          "copy kernel of known size, to calibrate HBM byte counters)")
@@ -796,9 +800,10 @@ def main():
         }
     table_cols = [(c.type, c.valid is not None, c.name) for c in table.columns]
     del table
-    out["gather"] = bench_gather(ctx, dt, table_cols, log)
-    out["achievable"] = bench_achievable(log)
-    if not args.no_sweeps:
+    if not args.no_extras:
+        out["gather"] = bench_gather(ctx, dt, table_cols, log)
+        out["achievable"] = bench_achievable(log)
+    if not args.no_sweeps and not args.no_extras:
         out["sweeps"] = bench_sweeps(ctx, dt, n, threads, log)
     small = star = None
     if not args.no_batch:
@@ -808,9 +813,9 @@ def main():
                                        cpu="cpu_baseline" in out)
         if "cpu_oracle" in out["star"]:
             out["cpu_baseline"]["per_workload"]["star_480M"] = out["star"].pop("cpu_oracle")
-    if small is not None:
+    if small is not None and not args.no_extras:
         out["estimate_error"] = bench_estimate_error(ctx, small, dt, log)
-    if small is not None and star is not None:
+    if small is not None and star is not None and not args.no_extras:
         out["select_pushdown"] = bench_select_pushdown(ctx, small, dt, star, log)
     if not args.no_serve and small is not None and star is not None:
         out["serving"] = bench_serve(ctx, small, dt, star, threads, log, args.serve_seconds)
