@@ -482,7 +482,9 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
       bc.tab_n = c.tab_n;
       bc.tab_guarded = c.tab_guarded ? 1u : 0u;
       col_gtab.push_back(~0ull);
-      if (c.gtab) {
+      // every lookup table is built once per launch in device memory by
+      // k_tables; an LDS table is then copied into each workgroup's LDS
+      if (c.gtab || c.tab_word != kNoLds) {
         TableBuild tbd{};
         tbd.dst = (uint32_t*)(uintptr_t)gtab_words;          // offset until written
         tbd.leaves = (const DevInstr*)(uintptr_t)bc.leaf_begin;  // index until written

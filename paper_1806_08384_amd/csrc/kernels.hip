@@ -1189,35 +1189,14 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
       __syncthreads();
       wl = bmlds + E->bm_words + wave * E->slot_words;
       if (E->bm_count || E->ntab) {
+        // lookup tables: copies of the ones k_tables built in device memory
         for (uint32_t c = 0; c < E->col_count; ++c) {
           const CONSTANT BatchCol* C = cols + E->col_begin + c;
           if (C->tab_word == kNoLds) continue;
-          const uint32_t n = C->tab_n, m = C->tab_count;
-          const int64_t L = C->tab_lo;
-          CInstr tl = leaves + C->leaf_begin;
+          const uint32_t words = ((C->tab_n + 1) * tab_entry_bytes(C->tab_count) + 3) / 4;
+          const GLOBAL uint32_t* src = gptr<uint32_t>(C->gtab);
           uint32_t* dst = bmlds + C->tab_word;
-          const uint32_t eb = tab_entry_bytes(m);
-          for (uint32_t i = threadIdx.x; i <= n; i += blockDim.x) {
-            uint32_t w = 0;
-            if (i < n) {
-              const int64_t x = L + (int64_t)i;
-              for (uint32_t k = 0; k < m; ++k) {
-                CInstr I = tl + k;
-                const uint64_t d = (uint64_t)x - (uint64_t)I->lo;
-                uint32_t bit;
-                if (I->op == D_RANGE) {
-                  bit = d <= I->span;
-                } else {  // D_BITMAP
-                  const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
-                  bit = d < I->span ? (bits[d >> 5] >> (d & 31)) & 1u : 0u;
-                }
-                w |= bit << k;
-              }
-            }
-            if (eb == 1) ((uint8_t*)dst)[i] = (uint8_t)w;
-            else if (eb == 2) ((uint16_t*)dst)[i] = (uint16_t)w;
-            else dst[i] = w;
-          }
+          for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
         }
         for (uint32_t k = 0; k < E->bm_count; ++k) {
           const CONSTANT BatchBitmap* B = bms + E->bm_begin + k;

@@ -238,9 +238,10 @@ struct BatchCol {              // 64 bytes: a column one entry reads
   uint32_t leaf_begin;         // its leaf tests: DevInstr array, slot field set
   uint32_t leaf_count;
   // Lookup table (narrow columns): its first tab_count leaves are bits
-  // 0 .. tab_count-1 of entry min(x - tab_lo, tab_n), at LDS word offset
-  // tab_word or, for a table too large for LDS, in device memory at gtab;
-  // entry tab_n is zero.  Entries are tab_entry_bytes(tab_count) wide.
+  // 0 .. tab_count-1 of entry min(x - tab_lo, tab_n); entry tab_n is zero.
+  // Entries are tab_entry_bytes(tab_count) wide.  The table is built in
+  // device memory at gtab; one that fits LDS is copied to LDS word offset
+  // tab_word when a workgroup starts the pass and read there.
   // tab_word == kNoLds and gtab == nullptr: no table.
   uint32_t tab_word;
   uint32_t tab_count;
