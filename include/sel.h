@@ -395,9 +395,10 @@ double sel_independence_estimate(uint64_t nrows, uint32_t n, const uint64_t* cou
  * pending programs is cut into rounds_per_cycle chunks (fewer if a chunk
  * would exceed chunk_rows rows), and a round is one batched launch over the
  * current chunk of every such table for every program attached to it, so
- * every table completes a cycle in the same number of rounds.  A program attaches at the next round and is done
- * after one revolution over its table, so requests arriving while others are
- * on the GPU share their scans.  A request is admitted (FIFO) when its
+ * every table completes a cycle in the same number of rounds.  A program
+ * attaches at the next round and is done after one revolution over its
+ * table, so requests arriving while others are on the GPU share their
+ * scans.  A request is admitted (FIFO) when its
  * device footprint (accumulators, program code, and for a push-down the
  * result mask, tile counts and its id capacity) fits the budget beside the
  * admitted ones; push-downs run on their own stream, overlapping the rounds.
@@ -411,7 +412,7 @@ typedef struct sel_server_config {
   uint64_t chunk_rows;         /* most rows per cooperative-scan chunk (0 = no cap) */
   uint32_t max_programs;       /* programs in flight (<= 4096; 0 = 4096) */
   uint32_t rounds_in_flight;   /* rounds queued on the device (1..4; 0 = 1) */
-  uint32_t rounds_per_cycle;   /* chunks per table (0 = 4) */
+  uint32_t rounds_per_cycle;   /* chunks per table (0 = 3) */
   uint32_t pad;
 } sel_server_config;
 

@@ -131,7 +131,7 @@ namespace {
 // Rows per chunk of a table: 1/rounds_per_cycle of it, capped by chunk_rows,
 // whole tiles.
 uint64_t chunk_rows_of(const sel_server* s, uint64_t nrows) {
-  const uint64_t r = s->cfg.rounds_per_cycle ? s->cfg.rounds_per_cycle : 4;
+  const uint64_t r = s->cfg.rounds_per_cycle ? s->cfg.rounds_per_cycle : 3;
   uint64_t c = (nrows + r - 1) / r;
   if (s->cfg.chunk_rows) c = std::min<uint64_t>(c, s->cfg.chunk_rows);
   c = std::max<uint64_t>(c, 1);
