@@ -382,6 +382,28 @@ def bench_estimate_error(ctx, small, fact_dt, log):
     }
 
 
+def bench_autotune(ctx, dt, tree, small, log):
+    """The launch-shape tuner (workgroup size and count, per kernel, program
+    class and table size) on the step's scans and on the 64-program batch,
+    beside the default shapes measured above.  It runs last: the tuned
+    shapes stay on the context."""
+    import datagen
+    from paper_1806_08384_amd import sel
+    prog = ctx.program(dt, tree)
+    out = {}
+    for name, mask in (("k_scan<M_MASK>", True), ("k_scan<M_COUNT>", False)):
+        (block, grid), ms = ctx.autotune(dt, prog, with_mask=mask, reps=5)
+        out[name] = {"block": block, "grid": grid, "tuned_kernel_ms": ms}
+        log(f"autotune {name}: block {block}, grid {grid}, {ms:.3f} ms")
+    if small is not None:
+        dts = list(small) + [dt]
+        pairs = [(dts[t], ctx.program(dts[t], tr)) for t, tr in datagen.cfg3_programs()]
+        (block, grid), ms = ctx.autotune_batch(pairs, reps=3)
+        out["k_batch (64 programs, eager call)"] = {"block": block, "grid": grid, "tuned_call_ms": ms}
+        log(f"autotune batch: block {block}, grid {grid}, {ms:.3f} ms")
+    return out
+
+
 def bench_select_pushdown(ctx, small, fact_dt, star, log, reps=10):
     """Algorithm 1's whole decision (size queue, probe skipped, exact count,
     limit, ids of each pushed relation) on two queries: the star schema
@@ -819,6 +841,8 @@ def main():
         out["select_pushdown"] = bench_select_pushdown(ctx, small, dt, star, log)
     if not args.no_serve and small is not None and star is not None:
         out["serving"] = bench_serve(ctx, small, dt, star, threads, log, args.serve_seconds)
+    if not args.no_extras:
+        out["autotune"] = bench_autotune(ctx, dt, tree, small, log)
     if args.copy_probe_mb:
         nb = args.copy_probe_mb << 20
         a = torch.empty(nb, dtype=torch.uint8, device="cuda")

@@ -112,8 +112,9 @@ uint64_t tune_key(int kind, uint32_t cls, uint64_t ntiles) {
 
 // Launch shape of a scan over ntiles wave tiles: a fixed shape if the
 // caller set one, else the tuned shape of this (kernel, program class,
-// size) if the tuner recorded one, else 16 resident waves per CU (more
-// measured slower on the 300M-row scan).
+// size) if the tuner recorded one, else 12 resident waves per CU (the
+// tuner's choice for the 300M-row fact-table scan: 16 or more measured
+// slower).
 void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
                 uint32_t& block) {
   block = ctx->launch.block;
@@ -135,7 +136,7 @@ void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t&
       occ = 1;
     }
     if (occ < 1) occ = 1;
-    const int per_cu = std::min(occ, (int)(16 * kWave / block));
+    const int per_cu = std::min(occ, (int)(kScanWavesPerCu / (block / kWave)));
     g = (uint64_t)per_cu * ctx->num_cus;
   }
   const uint32_t wpb = block / kWave;

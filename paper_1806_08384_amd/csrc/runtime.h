@@ -76,6 +76,8 @@ class Arena {
 };
 
 constexpr size_t kArenaBytes = 8u << 20;
+// Resident waves per CU of an untuned scan launch.
+constexpr int kScanWavesPerCu = 12;
 constexpr size_t kStageBytes = 1u << 20;
 }  // namespace selrt
 
