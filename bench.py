@@ -243,7 +243,7 @@ def bench_star(ctx, fact_rows, threads, log, cpu=False):
         cpu_star = {"rows": fact_rows, "threads": threads, "rows_per_s": fact_rows / dt,
                     "wall_s": dt, "star_count": oc}
     del fact
-    bitmaps, nbits, dim_ms = [], [], []
+    bitmaps, nbits, dim_ms, dim_counts = [], [], [], []
     for d, p in zip(ddims, preds):
         prog = ctx.program(d, p)
         bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
@@ -252,6 +252,7 @@ def bench_star(ctx, fact_rows, threads, log, cpu=False):
         bitmaps.append(bm)
         nbits.append(d.nrows)
         dim_ms.append(ms)
+        dim_counts.append(c)
     fk = [0, 1, 2, 3]
     for _ in range(3):
         c = ctx.star_count(dfact, fk, bitmaps, nbits)
@@ -273,6 +274,11 @@ def bench_star(ctx, fact_rows, threads, log, cpu=False):
         "star_GBps": bytes_ / (kms / 1e3) / 1e9,
         "star_frac_of_peak": bytes_ / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
     }
+    # the join order the exact dimension counts give (Ch.1 sec.1.1 formula)
+    order, cost, inter = sel.star_plan(fact_rows, nbits, dim_counts)
+    res["join_plan"] = {"dim_selected_rows": dim_counts, "order": order,
+                        "intermediate_rows": inter, "formula_final_rows": inter[-1],
+                        "exact_star_count": c, "intermediate_sum": cost}
     if cpu_star is not None:
         assert cpu_star["star_count"] == c, (cpu_star["star_count"], c)
         res["cpu_oracle"] = cpu_star

@@ -385,6 +385,32 @@ sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_pro
  * the n factors of (counts[k] / nrows), in double; 0 when nrows is 0. */
 double sel_independence_estimate(uint64_t nrows, uint32_t n, const uint64_t* counts);
 
+/* ---- join sizes from exact selection counts (Ch.1 sec.1.1) -------------- */
+
+/* The size of R join S on attribute A by the simplified formula of Ch.1
+ * sec.1.1: |R| |S| / max(V(R,A), V(S,A)), with V the number of distinct
+ * values of A; 0 when both distinct counts are 0. */
+double sel_join_size(double r_rows, double s_rows, double v_r, double v_s);
+
+/* A left-deep plan over a star: the fact table's selection (fact_rows rows)
+ * joined with its dimensions in `order` (a permutation of 0..ndims-1).
+ * Dimension d has dim_rows[d] distinct keys, all referenced by the fact
+ * table's foreign key (so V of the key is dim_rows[d] on both sides), and
+ * sel_rows[d] rows (and keys) after its own selection -- the exact counts
+ * this library computes.  Each join is sized by sel_join_size; inter (host,
+ * ndims, may be NULL) receives the size after each join, and the return
+ * value is their sum (the plan's intermediate rows), or -1 for bad input
+ * (ndims 0 or > 64, NULL arrays, an order that is not a permutation). */
+double sel_star_plan_cost(double fact_rows, uint32_t ndims, const double* dim_rows,
+                          const double* sel_rows, const uint32_t* order, double* inter);
+
+/* The left-deep order of least sel_star_plan_cost: the dimensions by
+ * ascending retained fraction sel_rows[d] / dim_rows[d] (equal fractions in
+ * index order), written to order (host, ndims); *cost receives its cost.
+ * SEL_E_INVALID for bad input. */
+sel_status sel_star_plan_order(double fact_rows, uint32_t ndims, const double* dim_rows,
+                               const double* sel_rows, uint32_t* order, double* cost);
+
 /* ---- serving: continuous batching of estimate requests ------------------ */
 
 /* A server keeps the tables resident (they are the caller's) and answers

@@ -15,6 +15,8 @@ Every function here restates the thesis' definitions (Shin 2018):
   star_count-- fact rows whose foreign keys all hit those key sets
   gather    -- Ch.3 sec.3.3: the materialised sigma(R) carries the columns
                the query projects, read at its row ids
+  join_size, star_plan_cost, best_star_plan -- Ch.1 sec.1.1: the join-size
+               formula and the cheapest left-deep order of a star query
   factor_counts, independence_estimate, q_error -- Ch.1 sec.1.1: the
                counts of a selection's conjuncts, the product estimate that
                assumes them independent, and its error against the count
@@ -251,6 +253,36 @@ def q_error(estimate: float, exact: int) -> float:
     """max(estimate / exact, exact / estimate), both taken as at least 1 row."""
     e, x = max(float(estimate), 1.0), max(float(exact), 1.0)
     return max(e / x, x / e)
+
+
+def join_size(r_rows, s_rows, v_r, v_s) -> float:
+    """|R join S| on A = |R| |S| / max(V(R, A), V(S, A)), the simplified
+    formula of Ch.1 sec.1.1 (V: distinct values of A)."""
+    v = max(v_r, v_s)
+    return r_rows * s_rows / v if v > 0 else 0.0
+
+
+def star_plan_cost(fact_rows, dim_rows, sel_rows, order):
+    """A left-deep plan joining the fact selection with the dimensions in
+    `order`; the fact side holds every key of a dimension, the selected
+    dimension sel_rows[d] of them.  (sum of intermediate sizes, sizes)."""
+    cur, inter = float(fact_rows), []
+    for d in order:
+        cur = join_size(cur, sel_rows[d], dim_rows[d], sel_rows[d])
+        inter.append(cur)
+    return sum(inter), inter
+
+
+def best_star_plan(fact_rows, dim_rows, sel_rows):
+    """The cheapest left-deep order by trying every permutation (the first
+    in lexicographic order among equal costs).  (order, cost)."""
+    import itertools
+    best = None
+    for perm in itertools.permutations(range(len(dim_rows))):
+        c, _ = star_plan_cost(fact_rows, dim_rows, sel_rows, perm)
+        if best is None or c < best[1]:
+            best = (list(perm), c)
+    return best
 
 
 def gather(table, ids, cols):

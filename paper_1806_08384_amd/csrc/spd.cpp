@@ -5,7 +5,8 @@
 // true, maxSize): its exact count, compared with maxSize = R.size *
 // PUSH_DOWN_MAX_SELECTIVITY, then either the materialised sigma(R) or a
 // reverted push-down.  Host logic only; every count and every id list comes
-// from sel_pushdown_rowids.
+// from sel_pushdown_rowids.  Also the join-size formula of Ch.1 sec.1.1
+// that those exact counts feed, for ordering a star query's joins.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -62,3 +63,48 @@ sel_status sel_select_pushdown(sel_ctx* ctx, uint32_t n, const sel_spd_relation*
   }
   return SEL_OK;
 }
+
+// ---- join sizes from exact selection counts (Ch.1 sec.1.1) ---------------
+
+double sel_join_size(double r_rows, double s_rows, double v_r, double v_s) {
+  const double v = std::max(v_r, v_s);
+  return v > 0.0 ? r_rows * s_rows / v : 0.0;
+}
+
+double sel_star_plan_cost(double fact_rows, uint32_t ndims, const double* dim_rows,
+                          const double* sel_rows, const uint32_t* order, double* inter) {
+  if (ndims == 0 || ndims > 64 || !dim_rows || !sel_rows || !order) return -1.0;
+  uint64_t seen = 0;
+  for (uint32_t k = 0; k < ndims; ++k) {
+    if (order[k] >= ndims || (seen >> order[k]) & 1u) return -1.0;
+    seen |= 1ull << order[k];
+  }
+  // the intermediate keeps one row per fact row whose key survives: the
+  // fact side holds dim_rows[d] distinct keys, the selected dimension
+  // sel_rows[d] of them
+  double cur = fact_rows, total = 0.0;
+  for (uint32_t k = 0; k < ndims; ++k) {
+    const uint32_t d = order[k];
+    cur = sel_join_size(cur, sel_rows[d], dim_rows[d], sel_rows[d]);
+    if (inter) inter[k] = cur;
+    total += cur;
+  }
+  return total;
+}
+
+sel_status sel_star_plan_order(double fact_rows, uint32_t ndims, const double* dim_rows,
+                               const double* sel_rows, uint32_t* order, double* cost) {
+  if (ndims == 0 || ndims > 64 || !dim_rows || !sel_rows || !order) return SEL_E_INVALID;
+  for (uint32_t d = 0; d < ndims; ++d)
+    if (!(dim_rows[d] > 0.0) || !(sel_rows[d] >= 0.0) || sel_rows[d] > dim_rows[d]) return SEL_E_INVALID;
+  // each join multiplies the running size by the dimension's retained
+  // fraction, so the sum of the running sizes is least when the smallest
+  // fractions come first
+  for (uint32_t d = 0; d < ndims; ++d) order[d] = d;
+  std::stable_sort(order, order + ndims, [&](uint32_t a, uint32_t b) {
+    return sel_rows[a] / dim_rows[a] < sel_rows[b] / dim_rows[b];
+  });
+  if (cost) *cost = sel_star_plan_cost(fact_rows, ndims, dim_rows, sel_rows, order, nullptr);
+  return SEL_OK;
+}
+

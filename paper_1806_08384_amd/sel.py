@@ -146,6 +146,12 @@ sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(
 sel_count_batch = _sig("sel_count_batch", _i32, _vp, _u32, _P(_vp), _P(_vp), _P(_u64))
 sel_factor_counts = _sig("sel_factor_counts", _i32, _vp, _vp, _vp, _u32, _P(_u64), _P(_u32), _P(_u64))
 sel_independence_estimate = _sig("sel_independence_estimate", ctypes.c_double, _u64, _u32, _P(_u64))
+sel_join_size = _sig("sel_join_size", ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                     ctypes.c_double, ctypes.c_double)
+sel_star_plan_cost = _sig("sel_star_plan_cost", ctypes.c_double, ctypes.c_double, _u32,
+                          _P(ctypes.c_double), _P(ctypes.c_double), _P(_u32), _P(ctypes.c_double))
+sel_star_plan_order = _sig("sel_star_plan_order", _i32, ctypes.c_double, _u32, _P(ctypes.c_double),
+                           _P(ctypes.c_double), _P(_u32), _P(ctypes.c_double))
 sel_gather = _sig("sel_gather", _i32, _vp, _vp, _vp, _u64, _u32, _P(_u32), _P(_vp), _P(_vp))
 sel_select_pushdown = _sig("sel_select_pushdown", _i32, _vp, _u32, _P(sel_spd_relation), _u64,
                            ctypes.c_double, _P(sel_spd_result))
@@ -267,6 +273,32 @@ def check_raw(nrows, cols, code, pool: bytes):
 
 
 # ---- object wrappers -------------------------------------------------------------
+
+def join_size(r_rows, s_rows, v_r, v_s) -> float:
+    return float(sel_join_size(r_rows, s_rows, v_r, v_s))
+
+
+def star_plan(fact_rows, dim_rows, sel_rows, order=None):
+    """(order, cost, intermediate sizes) of a left-deep star plan: the given
+    order, or the library's cheapest one."""
+    n = len(dim_rows)
+    dr = (ctypes.c_double * max(1, n))(*dim_rows)
+    sr = (ctypes.c_double * max(1, n))(*sel_rows)
+    od = (ctypes.c_uint32 * max(1, n))()
+    if order is None:
+        cost = ctypes.c_double(0)
+        st = sel_star_plan_order(fact_rows, n, dr, sr, od, ctypes.byref(cost))
+        if st != SEL_OK:
+            raise SelError(st, "bad star plan input")
+    else:
+        for k, d in enumerate(order):
+            od[k] = d
+    inter = (ctypes.c_double * max(1, n))()
+    c = float(sel_star_plan_cost(fact_rows, n, dr, sr, od, inter))
+    if c < 0:
+        raise SelError(SEL_E_INVALID, "bad star plan input")
+    return [int(od[k]) for k in range(n)], c, [float(inter[k]) for k in range(n)]
+
 
 class Context:
     """A libsel context bound to a device and a HIP stream (default: torch's

@@ -142,3 +142,30 @@ def test_factor_counts_match_oracle(sel, ctx):
     c, fc = ctx.factor_counts(df, ctx.program(df, tree))
     wc, wfc = oracle.factor_counts(f, tree, threads=16)
     assert c == wc and len(fc) == 4 and sorted(fc) == sorted(wfc)
+
+
+def test_star_plan_from_exact_counts(sel, ctx):
+    """The join order of a star query from the GPU's exact dimension counts
+    equals the oracle's cheapest order from its own counts, and the formula's
+    final size lands near the exact star count (independent uniform keys)."""
+    say("star plan: generating")
+    dims = datagen.star_dims()
+    fact = datagen.star_fact(10_000_000, threads=16)
+    preds = datagen.star_dim_predicates()
+    ddims = [sel.device_table(ctx, d) for d in dims]
+    dfact = sel.device_table(ctx, fact)
+    counts, bms = [], []
+    for d, dd, p in zip(dims, ddims, preds):
+        c = ctx.count(dd, ctx.program(dd, p))
+        assert c == oracle.Oracle(d).count(p)
+        counts.append(c)
+        bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+        st, c2 = ctx.pushdown_keybitmap(dd, 0, 0, ctx.program(dd, p), bm, d.nrows)
+        assert st == sel.SEL_OK and c2 == c
+        bms.append(bm)
+    rows = [d.nrows for d in dims]
+    order, cost, inter = sel.star_plan(fact.nrows, rows, counts)
+    want_order, want_cost = oracle.best_star_plan(fact.nrows, rows, counts)
+    assert order == want_order and cost == pytest.approx(want_cost, rel=1e-12)
+    exact = ctx.star_count(dfact, [0, 1, 2, 3], bms, rows)
+    assert exact > 0 and 1 / 1.5 < inter[-1] / exact < 1.5

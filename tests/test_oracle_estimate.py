@@ -74,3 +74,31 @@ def test_repeated_conjunct_and_flattening():
     assert abs(oracle.q_error(est, c) - 109 / 1.99) < 1e-6
     assert oracle.and_factors(("or", leaf, leaf)) == [("or", leaf, leaf)]
     assert oracle.q_error(0, 0) == 1.0
+
+
+def test_join_formula_on_the_worked_example():
+    """Ch.1 sec.1.1: with the estimated |sigma(R)| the plan (sigma(R) join S)
+    join T looks cheapest (0.9 M against the 5 M of S join T); with the true
+    count its first join holds 100.2 M rows, 20 times the other plan's."""
+    g = golden()
+    R, S, T = g["relation_rows_R"], g["relation_rows_S"], g["relation_rows_T"]
+    # S.A and T.B are primary keys: V(S, A) = |S|, V(T, B) = |T|, and the
+    # referencing sides hold at most that many distinct values
+    est_first = oracle.join_size(g["estimated_rows"], S, S, S)
+    other_first = oracle.join_size(S, T, T, T)
+    assert est_first == 900_000 and other_first == 5_000_000
+    true_first = oracle.join_size(g["true_rows"], S, S, S)
+    assert true_first == 100_200_000
+    assert round(true_first / other_first) == g["plan_ratio"]
+    assert R > S > T
+
+
+def test_star_plan_by_hand():
+    # fractions 0.5, 0.1, 0.3 of 1000, 100, 10 keys; 1e6 fact rows: the
+    # cheapest order keeps the smallest fractions first
+    dims, sels = [1000, 100, 10], [500, 10, 3]
+    order, cost = oracle.best_star_plan(1e6, dims, sels)
+    assert order == [1, 2, 0]
+    c, inter = oracle.star_plan_cost(1e6, dims, sels, order)
+    assert inter == [1e5, 3e4, 1.5e4] and c == cost == 1.45e5
+    assert oracle.star_plan_cost(1e6, dims, sels, [0, 2, 1])[0] == 5e5 + 1.5e5 + 1.5e4
