@@ -567,13 +567,9 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   a.tile_counts = counts;
   st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK);
   if (st != SEL_OK) return st;
-  uint64_t count = 0;
-  st = read_out(ctx, &count, nullptr);
-  if (st != SEL_OK) return st;
-  *out_count = count;
-  if (count > max_rows) return SEL_OVER_LIMIT;   // Algorithm 1: throw, revert
-  if (count > cap) return SEL_E_CAPACITY;
-  if (count == 0) return SEL_OK;
+  // the scan of tile counts and the compaction are enqueued at once; the
+  // compaction reads the published count and writes nothing if it exceeds
+  // max_rows or cap, so one wait at the end gives the outcome
   {
     TimedLaunch tl(ctx, SEL_K_SCAN);
     int e = sel_launch_scan_tiles(counts, offsets, chunk_sums, chunk_offs, ntiles, ctx->stream);
@@ -587,17 +583,24 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   c.ntiles = ntiles;
   c.out = d_out;
   c.cap = cap;
+  c.total = ctx->dout;
+  c.limit = std::min(max_rows, cap);
   // one wave per tile: compaction is latency-bound, so every tile gets a
   // wave of its own rather than a grid-stride loop
   const uint32_t block = 256;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((ntiles + 15) / 16, 1u << 20);
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((ntiles + 15) / 16, 1u << 20));
   {
     TimedLaunch tl(ctx, SEL_K_COMPACT);
     int e = sel_launch_compact(c, grid, block, ctx->stream);
     tl.done();
     if (e) return hip_err(ctx, (hipError_t)e, "compaction launch");
   }
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  uint64_t count = 0;
+  st = read_out(ctx, &count, nullptr);   // waits for the compaction too
+  if (st != SEL_OK) return st;
+  *out_count = count;
+  if (count > max_rows) return SEL_OVER_LIMIT;   // Algorithm 1: throw, revert
+  if (count > cap) return SEL_E_CAPACITY;
   return SEL_OK;
 }
 

@@ -580,6 +580,10 @@ __device__ __forceinline__ void compact_tile(uint32_t w, uint64_t base, uint64_t
 }
 
 __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
+  // the limit check of Algorithm 1 on the device: an empty or over-limit
+  // selection writes no id, so the host learns the outcome with one wait
+  const uint64_t total = *a.total;
+  if (total == 0 || total > a.limit) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t step = (uint64_t)gridDim.x * nw * kCompactTiles;

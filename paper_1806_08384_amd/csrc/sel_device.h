@@ -105,6 +105,10 @@ struct CompactArgs {
   uint64_t ntiles;
   uint32_t* out;
   uint64_t cap;
+  // the count the mask pass published; the compaction writes nothing when
+  // it is 0 or above `limit` (Algorithm 1's maxSize, or the capacity)
+  const unsigned long long* total;
+  uint64_t limit;
 };
 
 // Projected columns of a materialised sigma(R): value k of each output
