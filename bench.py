@@ -73,7 +73,7 @@ def percentile(xs, q):
 
 
 def cpu_baseline(table, tree, threads):
-    """The oracle as it stands, on the machine's host cores, over the same table
+    """The oracle as it stands, on this machine's host cores, over the same table
     (all rows, row ranges split over `threads` threads)."""
     import oracle
     orc = oracle.Oracle(table)
@@ -695,7 +695,7 @@ def main():
                          "copy kernel of known size, to calibrate HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
