@@ -512,8 +512,20 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
         if (op == D_NOT || op == D_ISUNK) two = false;
       }
       if (two) bp.nops |= kTwoValued;
+      // a conjunction of TRUE words (a first word, then words ANDed in):
+      // store the words' LDS offsets so the kernel needs no decoding
+      bool and_list = two && !pr.first.empty();
+      for (size_t k = 0; k < pr.first.size() && and_list; ++k) {
+        const uint32_t op = pr.first[k] & 0xFFu;
+        and_list = k == 0 ? (op == B_ACC || op == D_RANGE) : (op == B_AND_LEAF || op == B_AND_ACC);
+      }
+      if (and_list) {
+        bp.nops = (uint32_t)pr.first.size() | kAndList;
+        for (uint32_t w : pr.first) ops.push_back(((w >> 8) & 0xFFFu) * (uint32_t)kWave);
+      } else {
+        ops.insert(ops.end(), pr.first.begin(), pr.first.end());
+      }
       bp.acc_index = pr.second;
-      ops.insert(ops.end(), pr.first.begin(), pr.first.end());
       progs.push_back(bp);
     }
     entries.push_back(e);

@@ -1239,8 +1239,18 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
         if (k + q >= pn) break;
         const CONSTANT BatchProg* P = progs + pb + k + q;
         const uint32_t nops = P->nops;
-        T[q] = (nops & kTwoValued ? run_ops2((const CONSTANT uint32_t*)P->ops, nops & ~kTwoValued, wl, lane)
-                                  : run_ops((const CONSTANT uint32_t*)P->ops, nops, wl, lane)) & inr;
+        const CONSTANT uint32_t* ops = (const CONSTANT uint32_t*)P->ops;
+        uint32_t t;
+        if (nops & kAndList) {   // a conjunction of TRUE words at these offsets
+          const uint32_t n = nops & ~kAndList;
+          t = wl[ops[0] + lane];
+          for (uint32_t j = 1; j < n; ++j) t &= wl[ops[j] + lane];
+        } else if (nops & kTwoValued) {
+          t = run_ops2(ops, nops & ~kTwoValued, wl, lane);
+        } else {
+          t = run_ops(ops, nops, wl, lane);
+        }
+        T[q] = t & inr;
       }
       const uint32_t c2 = wave_sum(__builtin_popcount(T[0]) | (__builtin_popcount(T[1]) << 16));
       if (lane == 0 && c2) {

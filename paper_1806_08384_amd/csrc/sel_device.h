@@ -273,11 +273,16 @@ struct TableBuild {            // 48 bytes
 
 struct BatchProg {             // 16 bytes
   const uint32_t* ops;         // batch_op words, postfix
-  uint32_t nops;               // | kTwoValued: no NOT and no IS UNKNOWN (TRUE words suffice)
+  uint32_t nops;               // | kTwoValued: no NOT and no IS UNKNOWN (TRUE words suffice);
+                               // | kAndList (see below)
   uint32_t acc_index;          // accumulator line this program adds into
 };
 
 constexpr uint32_t kTwoValued = 0x80000000u;
+// | kAndList: the program is a conjunction of TRUE words (its accumulator,
+// OR words, leaves) and evaluates to none but TRUE words; its ops array
+// then holds the LDS word offsets (slot * 64) of the words to AND.
+constexpr uint32_t kAndList = 0x40000000u;
 constexpr int kBatchMaxProgs = 1024;
 constexpr int kBatchAccStride = 16;   // u64 per accumulator: one 128-byte line each
 
