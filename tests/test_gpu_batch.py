@@ -335,3 +335,53 @@ def test_batch_full_size(sel, ctx):
     assert got_graph == want
     del dts, pairs
     torch.cuda.empty_cache()
+
+
+def test_batch_conjunction_shapes(sel, ctx):
+    """Conjunctions that take every fast path of the batch planner, on a
+    table whose columns all have NULLs: direct factors (into the program's
+    accumulator, bitmap ones guarded), OR groups of narrow tests (into one
+    word), int64 leaves and OR groups with an int64 leaf (slots), evaluated
+    as lists of TRUE words; and the same shapes under NOT, which keeps the
+    three-valued interpreter.  Counts equal the oracle, eager and replayed."""
+    rng = np.random.default_rng(42_000)
+    n = 150_011
+    t = datagen.Table("shapes", n)
+    for name, ty, lo, hi in (("a", "i8", -50, 50), ("b", "i16", -3000, 3000),
+                             ("c", "i32", 0, 20_000), ("d", "i64", -10**9, 10**9),
+                             ("e", "i32", 0, 4_000)):
+        v, nn = _nulls(rng, n, 0.08)
+        t.columns.append(datagen.Column(name, ty, rng.integers(lo, hi, n).astype(
+            {"i8": np.int8, "i16": np.int16, "i32": np.int32, "i64": np.int64}[ty]),
+            valid=v, null_count=nn, dict_card=4_000 if name == "e" else 0))
+
+    def leaf(col):
+        if col == 0:
+            x = int(rng.integers(-50, 40))
+            return ("between", 0, x, x + int(rng.integers(1, 60)))
+        if col == 1:
+            return ("cmp", 1, str(rng.choice(["<", ">=", "<>"])), int(rng.integers(-3000, 3000)))
+        if col == 2:
+            return ("in", 2, tuple(int(v) for v in rng.choice(20_000, 40, replace=False)))
+        if col == 3:
+            return ("cmp", 3, str(rng.choice([">=", "<"])), int(rng.integers(-10**9, 10**9)))
+        w = rng.integers(0, 2**32, 125, dtype=np.uint32) & rng.integers(0, 2**32, 125, dtype=np.uint32)
+        return ("codeset", 4, 4_000, w)
+
+    trees = []
+    for k in range(40):
+        factors = [leaf(int(rng.integers(0, 5))) for _ in range(int(rng.integers(1, 4)))]
+        factors.append(("or",) + tuple(leaf(int(c)) for c in rng.choice([0, 1, 2, 4], 2, replace=False)))
+        if k % 2:
+            factors.append(("or", leaf(3), leaf(int(rng.integers(0, 3)))))
+        tree = ("and",) + tuple(factors)
+        trees.append(("not", tree) if k % 5 == 4 else tree)
+    dt = sel.device_table(ctx, t)
+    pairs = [(dt, ctx.program(dt, tree)) for tree in trees]
+    orc = oracle.Oracle(t)
+    want = [orc.count(tree) for tree in trees]
+    assert ctx.count_batch(pairs) == want
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
