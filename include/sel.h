@@ -544,7 +544,8 @@ uint32_t sel_tune_entries(const sel_ctx* ctx);
  * per kernel kind.  Reading the totals synchronises the stream. */
 typedef enum sel_kernel_kind {
   SEL_K_COUNT = 0,       /* fused evaluate + count                      */
-  SEL_K_MASK = 1,        /* evaluate + count + result mask + tile counts */
+  SEL_K_MASK = 1,        /* evaluate + count + packed result mask,
+                            tile lane maps and tile counts              */
   SEL_K_SCAN = 2,        /* exclusive scan of tile counts               */
   SEL_K_COMPACT = 3,     /* mask -> ascending row ids                   */
   SEL_K_KEYBITMAP = 4,   /* dimension key bitmap build                  */

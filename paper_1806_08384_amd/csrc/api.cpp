@@ -548,7 +548,8 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   const size_t mask_bytes = (size_t)ntiles * kWave * 4;
   const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
   const size_t chunk_bytes = 2048 * 4;
-  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * chunk_bytes);
+  const size_t lanes_bytes = ((size_t)ntiles * 8 + 255) & ~size_t(255);
+  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * chunk_bytes + lanes_bytes);
   if (st != SEL_OK) return st;
   char* sp = (char*)ctx->scratch;
   uint32_t* mask = (uint32_t*)sp;
@@ -556,6 +557,7 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   uint32_t* offsets = (uint32_t*)(sp + mask_bytes + counts_bytes);
   uint32_t* chunk_sums = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes);
   uint32_t* chunk_offs = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes + chunk_bytes);
+  uint64_t* lanes = (uint64_t*)(sp + mask_bytes + 2 * counts_bytes + 2 * chunk_bytes);
   ScanArgs a{};
   a.prog = prog->dcode;
   a.nins = prog->nins;
@@ -564,6 +566,7 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   a.ntiles = ntiles;
   a.out = ctx->dout;
   a.mask = mask;
+  a.tile_lanes = lanes;
   a.tile_counts = counts;
   st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK);
   if (st != SEL_OK) return st;
@@ -578,6 +581,7 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   }
   CompactArgs c{};
   c.mask = mask;
+  c.tile_lanes = lanes;
   c.offsets = offsets;
   c.chunk_offs = chunk_offs;
   c.ntiles = ntiles;

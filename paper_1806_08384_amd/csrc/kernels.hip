@@ -414,12 +414,15 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   }
   uint32_t cnt = 0, oor = 0;
   // M_MASK: result words of the last 8 tiles, written together with
-  // nontemporal stores (fewer, fuller store bursts interleaved with the loads)
+  // nontemporal stores (fewer, fuller store bursts interleaved with the
+  // loads).  Only words holding a TRUE row are written, packed at the front
+  // of their tile's slot: at low selectivity most words are zero, and the
+  // writes, not their bytes' share of the traffic, slow the scan.
   uint32_t pend[8];
-  uint64_t ptile[8];
+  uint64_t pidx[8];
   int np = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) { pend[k] = 0; ptile[k] = 0; }
+  for (int k = 0; k < 8; ++k) { pend[k] = 0; pidx[k] = 0; }
   for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
     const uint64_t tb = tile * kTileRows;
     uint32_t T;
@@ -430,17 +433,26 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
     }
     cnt += __builtin_popcount(T);
     if constexpr (MODE == M_MASK) {
+      // lanes with a TRUE row; a lane's word goes to the rank of its lane
+      // among them
+      const uint64_t nz = __ballot(T != 0u);
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (k == np) { pend[k] = T; ptile[k] = tile; }
+        if (k == np) { pend[k] = T; pidx[k] = tile * kWave + pos; }
       ++np;
       if (np == 8) {
 #pragma unroll
-        for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(pend[k], &a.mask[ptile[k] * kWave + lane]);
+        for (int k = 0; k < 8; ++k)
+          if (pend[k]) __builtin_nontemporal_store(pend[k], &a.mask[pidx[k]]);
         np = 0;
       }
       const uint32_t tc = wave_sum(__builtin_popcount(T));
-      if (lane == 0) a.tile_counts[tile] = tc;
+      if (lane == 0) {
+        a.tile_counts[tile] = tc;
+        a.tile_lanes[tile] = nz;
+      }
     } else if constexpr (MODE == M_KEYBITMAP) {
       uint32_t m = T;
       while (m) {
@@ -458,7 +470,7 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   if constexpr (MODE == M_MASK) {
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (k < np) __builtin_nontemporal_store(pend[k], &a.mask[ptile[k] * kWave + lane]);
+      if (k < np && pend[k]) __builtin_nontemporal_store(pend[k], &a.mask[pidx[k]]);
   }
   finish(a.slot, a.out, cnt, oor, MODE == M_KEYBITMAP);
 }
@@ -591,17 +603,23 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
        t0 < a.ntiles; t0 += step) {
     uint32_t w[kCompactTiles];
     uint32_t off[kCompactTiles], coff[kCompactTiles];
+    uint64_t nz[kCompactTiles];
 #pragma unroll
     for (int k = 0; k < kCompactTiles; ++k) {
       const uint64_t tile = t0 + k;
       const bool in = tile < a.ntiles;
-      w[k] = in ? a.mask[tile * kWave + lane] : 0u;
+      // the lanes whose word the mask pass wrote, and each one's rank
+      // among them: its place in the tile's packed words
+      nz[k] = in ? uni64(a.tile_lanes[tile]) : 0ull;
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz[k] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nz[k], 0u));
+      w[k] = (nz[k] >> lane) & 1u ? a.mask[tile * kWave + pos] : 0u;
       off[k] = in ? a.offsets[tile] : 0u;
       coff[k] = in ? a.chunk_offs[tile >> 10] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kCompactTiles; ++k) {
-      if (__ballot(w[k] != 0u) == 0ull) continue;  // no TRUE row in the tile
+      if (nz[k] == 0ull) continue;  // no TRUE row in the tile
       compact_tile(w[k], (uint64_t)uni(coff[k]) + uni(off[k]), t0 + k, lane, a.out, a.cap);
     }
   }
@@ -893,17 +911,30 @@ __device__ __forceinline__ void tab_leaves(const Seg& r, const CONSTANT BatchCol
       T[b] = tab[d < n ? d : n];
     }
   } else {
-    const GLOBAL E* tab = gptr<E>(C->gtab);
-    uint32_t need = ~0u;
+    // 32-bit byte offsets from the table's uniform base (device tables
+    // are at most 32 MB)
+    const GLOBAL char* tab = gptr<char>(C->gtab);
     if (C->tab_guarded) {
-      // rows some table leaf needs: the union of the leaves' guards
-      need = 0;
+      // rows no table leaf needs (the complement of the union of the
+      // leaves' guards) read the zero entry n: with g all ones on such a
+      // row, min(d | g, n) is n, and on the others it is min(d, n)
+      uint32_t need = 0;
       for (uint32_t i = 0; i < m; ++i) need |= acc_need(tl[i].slot, wl, lane);
-    }
+      const uint32_t skip = ~need;
 #pragma unroll
-    for (int b = 0; b < 32; ++b) {
-      const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
-      T[b] = tab[d < n && ((need >> b) & 1u) ? d : n];
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+        const uint32_t g = (uint32_t)((int32_t)(skip << (31 - b)) >> 31);
+        const uint32_t k = min(d | g, n);
+        T[b] = *(const GLOBAL E*)(tab + k * (uint32_t)sizeof(E));
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 32; ++b) {
+        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - L32;
+        const uint32_t k = min(d, n);
+        T[b] = *(const GLOBAL E*)(tab + k * (uint32_t)sizeof(E));
+      }
     }
   }
   // row b's entry holds leaf i in bit i; transposed, T[i] holds leaf i's

@@ -82,8 +82,12 @@ struct ScanArgs {
   uint64_t ntiles;
   DevSlot* slot;
   unsigned long long* out;     // out[0] = count, out[1] = out-of-range keys
-  uint32_t* mask;              // M_MASK: one word per lane per tile
-  uint32_t* tile_counts;       // M_MASK: TRUE rows per tile
+  // M_MASK: per tile, the result words that hold a TRUE row, packed at the
+  // front of the tile's 64-word slot in lane order (the rest of the slot is
+  // not written); the lanes they belong to; and the tile's TRUE rows
+  uint32_t* mask;
+  uint64_t* tile_lanes;
+  uint32_t* tile_counts;
   // M_KEYBITMAP
   const void* key_data;
   uint32_t key_type;
@@ -99,7 +103,8 @@ struct ScanArgs {
 constexpr uint32_t kScanStageWords = 4096;
 
 struct CompactArgs {
-  const uint32_t* mask;
+  const uint32_t* mask;        // packed nonzero result words (see ScanArgs)
+  const uint64_t* tile_lanes;  // the lanes they belong to
   const uint32_t* offsets;     // exclusive prefix of tile counts within a chunk
   const uint32_t* chunk_offs;  // exclusive prefix of chunk (1024 tiles) totals
   uint64_t ntiles;

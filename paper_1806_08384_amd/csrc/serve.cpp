@@ -143,7 +143,8 @@ uint64_t footprint_of(const sel_server* s, const Request& r) {
   for (const sel_program* p : r.progs) f += p->nins * sizeof(DevInstr);
   if (r.has_pd) {
     const uint64_t nt = ntiles_of(r.pd_table->nrows);
-    f += nt * kWave * 4 + 2 * nt * 4 + r.pd_cap * 4;  // mask, tile counts, offsets, ids
+    // mask, tile lane maps, tile counts, offsets, ids
+    f += nt * kWave * 4 + nt * 8 + 2 * nt * 4 + r.pd_cap * 4;
   }
   return f;
 }
