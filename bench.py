@@ -742,8 +742,13 @@ def main():
 
     bpr = prog.bytes_per_row                       # referenced columns + validity
     ntiles = (n + 2047) // 2048
-    mask_bytes = ntiles * 64 * 4
-    mask_kernel_bytes = n * bpr + mask_bytes + ntiles * 4
+    # the mask pass writes the result words that hold a TRUE row (lane L of
+    # a 2048-row tile holds rows 256 j + 4 L + i), and 12 B per tile (count
+    # and lane map); the words are counted from the ids the step returned
+    idv = ids[:cnt].to(torch.int64) & 0xFFFFFFFF
+    mask_words = int(torch.unique((idv // 2048) * 64 + (idv % 256) // 4).numel())
+    del idv
+    mask_kernel_bytes = n * bpr + 4 * mask_words + ntiles * 12
     mask_avg_s = ms[sel.K_MASK] / max(1, launches[sel.K_MASK]) / 1e3
     compact_avg_s = ms[sel.K_COMPACT] / max(1, launches[sel.K_COMPACT]) / 1e3
     scan_avg_s = ms[sel.K_SCAN] / max(1, launches[sel.K_SCAN]) / 1e3
@@ -797,6 +802,7 @@ def main():
             "traffic": measured_traffic("k_scan<1>"),
             "avg_kernel_ms": mask_avg_s * 1e3,
             "algorithmic_bytes_per_launch": mask_kernel_bytes,
+            "mask_words_written": mask_words,
         },
         "count_query": {
             "kernel": "k_scan<M_COUNT>",
