@@ -819,12 +819,21 @@ __device__ __forceinline__ uint32_t seg_leaf(const Seg& r, uint32_t op, CInstr I
         P = (P << 1) + ((bm[k >> 5] >> (k & 31)) & 1u);
       }
     } else {
+      // eight rows at a time: their LDS reads are all issued before the
+      // first bit is taken, so one wait covers eight round trips
       const uint32_t lo32 = (uint32_t)lo;
 #pragma unroll
-      for (int b = nb - 1; b >= 0; --b) {
-        const uint32_t d = (uint32_t)seg_get<TY>(r, b) - lo32;
-        const uint32_t k = d < z ? d : z;
-        P = (P << 1) + ((bm[k >> 5] >> (k & 31)) & 1u);
+      for (int g = nb - 8; g >= 0; g -= 8) {
+        uint32_t k[8], w[8];
+#pragma unroll
+        for (int q = 7; q >= 0; --q) {
+          const uint32_t d = (uint32_t)seg_get<TY>(r, g + q) - lo32;
+          k[q] = d < z ? d : z;
+        }
+#pragma unroll
+        for (int q = 7; q >= 0; --q) w[q] = bm[k[q] >> 5];
+#pragma unroll
+        for (int q = 7; q >= 0; --q) P = (P << 1) + ((w[q] >> (k[q] & 31)) & 1u);
       }
     }
   } else if (op == D_RANGE) {
