@@ -70,6 +70,39 @@ def test_ragged_sizes_random_programs(sel, ctx, n):
         check_tree(sel, ctx, dt, orc, tree)
 
 
+def test_mask_lane_patterns(sel, ctx):
+    """Row-id materialisation where the TRUE rows sit in chosen lanes of each
+    2048-row tile (lane L of a tile holds rows 256 j + 4 L + i): only the
+    first or the last lane, alternate lanes, the upper half, every lane, no
+    lane, and a mix that changes from tile to tile (first and last lane,
+    a whole tile, one row of lane 31, an empty tile), on a ragged table.
+    The mask pass writes only a tile's words that hold a TRUE row, packed in
+    lane order, and the compaction places each by its lane's rank."""
+    n = 2048 * 37 + 777
+    r = np.arange(n, dtype=np.int64)
+    t = datagen.Table("lanes", n)
+    t.columns.append(datagen.Column("lane", "i8", ((r % 256) // 4).astype(np.int8)))
+    t.columns.append(datagen.Column("tmod", "i8", ((r // 2048) % 4).astype(np.int8)))
+    t.columns.append(datagen.Column("step", "i8", ((r % 2048) // 256).astype(np.int8)))
+    t.columns.append(datagen.Column("i", "i8", (r % 4).astype(np.int8)))
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    trees = [
+        ("cmp", 0, "=", 63),
+        ("cmp", 0, "=", 0),
+        ("in", 0, tuple(range(0, 64, 2))),
+        ("and", ("cmp", 0, ">=", 32), ("cmp", 1, "<>", 2)),
+        ("cmp", 0, ">=", 0),
+        ("cmp", 0, ">", 63),
+        ("or", ("and", ("cmp", 1, "=", 0), ("in", 0, (0, 63))),
+               ("cmp", 1, "=", 1),
+               ("and", ("cmp", 1, "=", 2), ("cmp", 0, "=", 31), ("cmp", 2, "=", 7), ("cmp", 3, "=", 3))),
+    ]
+    for tree in trees:
+        say(f"lane pattern {tree}")
+        check_tree(sel, ctx, dt, orc, tree)
+
+
 def test_random_programs_small_ranges(sel, ctx):
     """Values in a small range so that comparisons split rows evenly."""
     rng = np.random.default_rng(77)
