@@ -99,8 +99,10 @@ struct ScanArgs {
 };
 
 // Single-program scans stage the program's small bitmaps (in program order,
-// up to this many words) in LDS; lookups into them skip the memory system.
-constexpr uint32_t kScanStageWords = 4096;
+// up to this many words: 32 KB per workgroup, so that a 200 k-key dimension's
+// bitmap fits beside two smaller ones) in LDS; lookups into them skip the
+// memory system.
+constexpr uint32_t kScanStageWords = 8192;
 
 struct CompactArgs {
   const uint32_t* mask;        // packed nonzero result words (see ScanArgs)
