@@ -6,7 +6,7 @@ import pytest
 import datagen
 import oracle
 from tests import sqlite_ref
-from tests.gpu_common import say
+from tests.gpu_common import UINT64_MAX, as_u32, ids_tensor, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -136,6 +136,12 @@ def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
     assert bb in (64, 128, 256, 512, 768) and bg > 0
     assert ctx.tune_entries >= 3
     assert ctx.count(*pairs[-1]) == want[-1]
+    # the tuned mask-pass shape still gives the oracle's ids
+    t, tree = progs[-1]
+    out = ids_tensor(want[-1], torch)
+    st, cnt = ctx.pushdown_rowids(*pairs[-1], UINT64_MAX, out)
+    assert (st, cnt) == (sel.SEL_OK, want[-1])
+    np.testing.assert_array_equal(as_u32(out)[:cnt], oracle.Oracle(tables[t]).rowids(tree))
     assert ctx.count_batch(pairs) == want
     path = tmp_path / "tune.txt"
     ctx.tune_save(path)
