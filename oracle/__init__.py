@@ -75,6 +75,8 @@ def load(path: str | None = None):
     L.oc_count.restype = u64
     L.oc_rowids.argtypes = [vp, vp, u64, vp, u64]
     L.oc_rowids.restype = u64
+    L.oc_rowids_mt.argtypes = [vp, vp, u64, vp, u64, ctypes.c_int]
+    L.oc_rowids_mt.restype = u64
     L.oc_pushdown.argtypes = [vp, vp, u64, u64, vp, u64, vp]
     L.oc_pushdown.restype = ctypes.c_int
     L.oc_keybitmap.argtypes = [vp, vp, u64, i32, i64, vp, u64, vp]
@@ -174,12 +176,19 @@ class Oracle:
         e, keep = self._expr(tree)
         return int(self.lib.oc_count(ctypes.byref(e), self._cols, self.table.nrows, threads))
 
-    def rowids(self, tree) -> np.ndarray:
+    def rowids(self, tree, threads: int = 1) -> np.ndarray:
+        """Ascending ids of the TRUE rows; threads > 1 splits the rows into
+        contiguous ranges (oc_rowids_mt), one thread each."""
         e, keep = self._expr(tree)
         n = self.table.nrows
-        c = int(self.lib.oc_rowids(ctypes.byref(e), self._cols, n, None, 0))
+        if threads == 1:
+            c = int(self.lib.oc_rowids(ctypes.byref(e), self._cols, n, None, 0))
+            out = np.empty(c, dtype=np.uint32)
+            self.lib.oc_rowids(ctypes.byref(e), self._cols, n, out.ctypes.data, c)
+            return out
+        c = int(self.lib.oc_rowids_mt(ctypes.byref(e), self._cols, n, None, 0, threads))
         out = np.empty(c, dtype=np.uint32)
-        self.lib.oc_rowids(ctypes.byref(e), self._cols, n, out.ctypes.data, c)
+        self.lib.oc_rowids_mt(ctypes.byref(e), self._cols, n, out.ctypes.data, c, threads)
         return out
 
     def pushdown(self, tree, max_rows: int, cap: int):

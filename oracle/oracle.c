@@ -236,6 +236,72 @@ uint64_t oc_rowids(const oc_expr* e, const oc_col* cols, uint64_t nrows,
   return c;
 }
 
+/* The same ids with the rows split into contiguous ranges over nthreads
+ * threads (<= 0: one per online core): each range is counted, the counts give
+ * each range its first output position, and each range then writes its ids
+ * there.  Ranges are in row order, so the concatenation is ascending and
+ * equal to oc_rowids' list.  Writes at most cap ids; returns the total. */
+typedef struct rowid_job {
+  const oc_expr* e;
+  const oc_col* cols;
+  uint64_t lo, hi, count, first;
+  uint32_t* out;
+  uint64_t cap;
+} rowid_job;
+
+static void* rowid_count_range(void* arg) {
+  rowid_job* j = (rowid_job*)arg;
+  uint64_t c = 0;
+  for (uint64_t i = j->lo; i < j->hi; i++)
+    if (eval(j->e, j->cols, j->e->root, i) == OC_T) c++;
+  j->count = c;
+  return NULL;
+}
+
+static void* rowid_write_range(void* arg) {
+  rowid_job* j = (rowid_job*)arg;
+  uint64_t pos = j->first;
+  for (uint64_t i = j->lo; i < j->hi; i++) {
+    if (eval(j->e, j->cols, j->e->root, i) == OC_T) {
+      if (pos < j->cap) j->out[pos] = (uint32_t)i;
+      pos++;
+    }
+  }
+  return NULL;
+}
+
+uint64_t oc_rowids_mt(const oc_expr* e, const oc_col* cols, uint64_t nrows,
+                      uint32_t* out, uint64_t cap, int nthreads) {
+  int nt = resolve_threads(nthreads);
+  if ((uint64_t)nt > nrows) nt = nrows > 0 ? (int)nrows : 1;
+  rowid_job* jobs = (rowid_job*)calloc((size_t)nt, sizeof(rowid_job));
+  pthread_t* th = (pthread_t*)calloc((size_t)nt, sizeof(pthread_t));
+  for (int t = 0; t < nt; t++) {
+    jobs[t].e = e;
+    jobs[t].cols = cols;
+    jobs[t].lo = nrows * (uint64_t)t / (uint64_t)nt;
+    jobs[t].hi = nrows * (uint64_t)(t + 1) / (uint64_t)nt;
+    jobs[t].out = out;
+    jobs[t].cap = cap;
+  }
+  for (int t = 1; t < nt; t++) pthread_create(&th[t], NULL, rowid_count_range, &jobs[t]);
+  rowid_count_range(&jobs[0]);
+  for (int t = 1; t < nt; t++) pthread_join(th[t], NULL);
+  uint64_t total = 0;
+  for (int t = 0; t < nt; t++) {
+    jobs[t].first = total;
+    total += jobs[t].count;
+  }
+  if (out != NULL && cap > 0) {
+    for (int t = 1; t < nt; t++) pthread_create(&th[t], NULL, rowid_write_range, &jobs[t]);
+    rowid_write_range(&jobs[0]);
+    for (int t = 1; t < nt; t++) pthread_join(th[t], NULL);
+  }
+  free(jobs);
+  free(th);
+  return total;
+}
+
 /* Algorithm 1: count first; a count above max_rows aborts (status 1, nothing
  * written); a count above the caller's capacity is status 2 (nothing
  * written); otherwise the ascending ids are written (status 0). */

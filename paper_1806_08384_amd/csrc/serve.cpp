@@ -290,6 +290,14 @@ bool launch_round(sel_server* s) {
       ts.cur = (ts.cur + 1) % ts.nchunks;
       s->shared_rounds += shared ? 1 : 0;
     }
+    // a table with no program attached keeps no state: its chunk geometry
+    // is taken afresh from the table when a program next attaches, so a
+    // table destroyed and another created at the same address is never
+    // scanned with the old one's row count
+    for (auto it = s->tables.begin(); it != s->tables.end();) {
+      if (it->second.progs.empty()) it = s->tables.erase(it);
+      else ++it;
+    }
     if (ngroups == 0) {
       rs.members.clear();
       return false;

@@ -87,8 +87,12 @@ def check_sqlite(lib_path=None, seeds=range(12), n=400):
             if c != int((want == 2).sum()) or c != sqlite_ref.count(db, tree):
                 fails.append(f"sqlite count seed {s}")
             ids = o.rowids(tree)
-            if not np.array_equal(ids, sqlite_ref.rowids(db, tree)):
+            want_ids = sqlite_ref.rowids(db, tree)
+            if not np.array_equal(ids, want_ids):
                 fails.append(f"sqlite rowids seed {s}")
+            # the row-range split: ranges of 28-29 rows, most holding some ids
+            if not np.array_equal(o.rowids(tree, threads=7), want_ids):
+                fails.append(f"sqlite rowids over 7 row ranges seed {s}")
     return fails
 
 
@@ -181,6 +185,8 @@ def check_invariants(lib_path=None, n=30000, seeds=range(4)):
                 fails.append(f"row ids ascending, len = count, seed {s}")
             if o.count(p, threads=5) != cp:
                 fails.append(f"threaded count seed {s}")
+            if not np.array_equal(o.rowids(p, threads=5), ids):
+                fails.append(f"threaded row ids seed {s}")
     return fails
 
 
@@ -246,6 +252,8 @@ def check_star(lib_path=None, seeds=range(3)):
         fpred = ("cmp", 2, ">=", 4)
         for pred in (None, fpred):
             got = fo.star_count([0, 1], bitmaps, nbits, pred)
+            # the same count with the fact rows split into ranges over threads
+            split = [fo.star_count([0, 1], bitmaps, nbits, pred, threads=k) for k in (5, 16)]
             import sqlite3
             db = sqlite3.connect(":memory:")
             db.execute("CREATE TABLE f (fk0 INTEGER, fk1 INTEGER, m INTEGER)")
@@ -265,6 +273,9 @@ def check_star(lib_path=None, seeds=range(3)):
             want = int(db.execute(sql).fetchone()[0])
             if got != want:
                 fails.append(f"star count seed {s} pred {pred}: got {got} want {want}")
+            for k, c in zip((5, 16), split):
+                if c != want:
+                    fails.append(f"star count over {k} row ranges seed {s} pred {pred}: got {c} want {want}")
             # bits past nbits in the last word are outside the set
             padded = [b.copy() for b in bitmaps]
             for b, nb in zip(padded, nbits):

@@ -6,7 +6,7 @@ import pytest
 import datagen
 import oracle
 from tests import sqlite_ref
-from tests.gpu_common import UINT64_MAX, as_u32, ids_tensor, say, slice_table
+from tests.gpu_common import UINT64_MAX, as_u32, ids_tensor, say
 
 pytestmark = pytest.mark.gpu
 
@@ -269,8 +269,8 @@ def test_keybitmap_edges(sel, ctx):
 
 def test_cfg2_full_size(sel, ctx):
     """cfg2 at its full 300M rows in the default launch shape: exact count
-    against the threaded oracle; row ids checked whole for properties and
-    against the oracle on sampled row ranges."""
+    and the whole ascending row-id arrays (1.62M ids, and 270M ids of a 90 %
+    date range) against the oracle over 16 row ranges."""
     say("cfg2 full: generating 300M rows")
     t = datagen.cfg2()
     dt = sel.device_table(ctx, t)
@@ -287,15 +287,8 @@ def test_cfg2_full_size(sel, ctx):
     st, cnt = ctx.pushdown_rowids(dt, prog, UINT64_MAX, out)
     assert (st, cnt) == (sel.SEL_OK, want)
     ids = as_u32(out)[:cnt].astype(np.int64)
-    assert np.all(np.diff(ids) > 0)
-    rng = np.random.default_rng(3)
-    for k in range(6):
-        lo = int(rng.integers(0, t.nrows - 3_000_000)) // 32 * 32
-        hi = lo + 2_000_000 + int(rng.integers(0, 1000))
-        sub = slice_table(t, lo, hi)
-        want_ids = oracle.Oracle(sub).rowids(tree).astype(np.int64) + lo
-        got_ids = ids[(ids >= lo) & (ids < hi)]
-        np.testing.assert_array_equal(got_ids, want_ids)
+    say("cfg2 full: oracle row ids over 16 row ranges")
+    np.testing.assert_array_equal(ids, orc.rowids(tree, threads=16).astype(np.int64))
     # the selection's projected columns (date, qty, price with NULLs, s25)
     # gathered at its ids, against numpy indexing of the host table
     cols = [0, 1, 3, 5]
@@ -321,13 +314,77 @@ def test_cfg2_full_size(sel, ctx):
     st, cnt = ctx.pushdown_rowids(dt, prog, want, out)
     assert (st, cnt) == (sel.SEL_OK, want)
     ids = as_u32(out)[:cnt]
-    assert np.all(ids[1:] > ids[:-1])
-    for k in range(4):
-        lo = int(rng.integers(0, t.nrows - 3_000_000)) // 32 * 32
-        hi = lo + 1_000_000 + int(rng.integers(0, 1000))
-        sub = slice_table(t, lo, hi)
-        want_ids = oracle.Oracle(sub).rowids(wide).astype(np.int64) + lo
-        a, b = np.searchsorted(ids, [lo, hi])
-        np.testing.assert_array_equal(ids[a:b].astype(np.int64), want_ids)
-    del dt, out, ids
+    say("cfg2 full: oracle row ids of the 90 % range over 16 row ranges")
+    want_ids = orc.rowids(wide, threads=16)
+    np.testing.assert_array_equal(ids, want_ids)
+    del dt, out, ids, want_ids
+    torch.cuda.empty_cache()
+
+
+def test_star_full_dimensions(sel, ctx):
+    """The star probe at the star workload's own dimension sizes (2556 / 30k
+    / 200k / 3.2M keys: 29 KB of bitmaps staged in LDS beside the 400 KB one
+    read through the caches) over 20M fact rows: key bitmaps word for word,
+    the star count with and without the fact predicate, on every subset of
+    two dimensions, and star programs through sel_count and sel_count_batch,
+    all against the oracle."""
+    sizes = datagen.CFG4_DIM_ROWS
+    assert tuple(sizes) == (2556, 30_000, 200_000, 3_200_000)
+    say("star full dims: generating dimensions and 20M fact rows")
+    dims, preds, fact = star_setup(sel, ctx, 20_000_003, sizes)
+    bitmaps_gpu, bitmaps_cpu, nbits = [], [], []
+    ddims = []
+    for t, p in zip(dims, preds):
+        dt = sel.device_table(ctx, t)
+        ddims.append(dt)
+        bm = torch.full(((t.nrows + 31) // 32,), -1, dtype=torch.int32, device="cuda")
+        st, cnt = ctx.pushdown_keybitmap(dt, 0, 0, ctx.program(dt, p), bm, t.nrows)
+        ost, ocnt, owords = oracle.Oracle(t).keybitmap(p, 0, 0, t.nrows)
+        assert st == sel.SEL_OK and ost == 0 and cnt == ocnt
+        np.testing.assert_array_equal(as_u32(bm), owords)
+        bitmaps_gpu.append(bm)
+        bitmaps_cpu.append(owords)
+        nbits.append(t.nrows)
+    dfact = sel.device_table(ctx, fact)
+    ofact = oracle.Oracle(fact)
+    fp = datagen.star_fact_predicate()
+    fprog = ctx.program(dfact, fp)
+    say("star full dims: star counts")
+    every = [0, 1, 2, 3]
+    want = ofact.star_count(every, bitmaps_cpu, nbits, threads=16)
+    assert ctx.star_count(dfact, every, bitmaps_gpu, nbits) == want
+    want_fp = ofact.star_count(every, bitmaps_cpu, nbits, fp, threads=16)
+    assert ctx.star_count(dfact, every, bitmaps_gpu, nbits, fprog) == want_fp
+    for a in range(4):
+        for b in range(a + 1, 4):
+            sub = [a, b]
+            assert ctx.star_count(dfact, sub, [bitmaps_gpu[a], bitmaps_gpu[b]],
+                                  [nbits[a], nbits[b]]) == \
+                ofact.star_count(sub, [bitmaps_cpu[a], bitmaps_cpu[b]], [nbits[a], nbits[b]],
+                                 threads=16), sub
+    say("star full dims: star programs, plain and batched")
+    progs = [ctx.star_program(dfact, every, bitmaps_gpu, nbits),
+             ctx.star_program(dfact, every, bitmaps_gpu, nbits, fprog)]
+    wants = [want, want_fp]
+    keep = []
+    for k, combo in enumerate(datagen.star_dim_programs(11, 6, dims)):
+        bms_gpu, bms_cpu = [], []
+        for d, dt, p in zip(dims, ddims, combo):
+            bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
+            st, _ = ctx.pushdown_keybitmap(dt, 0, 0, ctx.program(dt, p), bm, d.nrows)
+            assert st == sel.SEL_OK
+            ost, _, owords = oracle.Oracle(d).keybitmap(p, 0, 0, d.nrows)
+            assert ost == 0
+            np.testing.assert_array_equal(as_u32(bm), owords)
+            bms_gpu.append(bm)
+            bms_cpu.append(owords)
+        keep.append(bms_gpu)
+        pred = fprog if k % 2 else None
+        progs.append(ctx.star_program(dfact, every, bms_gpu, nbits, pred))
+        wants.append(ofact.star_count(every, bms_cpu, nbits, fp if pred is not None else None,
+                                      threads=16))
+    pairs = [(dfact, p) for p in progs]
+    assert [ctx.count(*p) for p in pairs] == wants
+    assert ctx.count_batch(pairs) == wants
+    del dfact, ddims, bitmaps_gpu, keep, progs, pairs
     torch.cuda.empty_cache()

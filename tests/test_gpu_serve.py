@@ -1,7 +1,8 @@
 """GPU: the serving loop (continuous batching with cooperative scans).
-Every request's results in a mixed, overlapping stream equal its results
-alone (counts exact, row ids bit-identical), and admission by device
-footprint holds requests back or rejects them without failing."""
+Every request's results in a mixed, overlapping stream equal the oracle's
+(counts exact, row ids bit-identical) and so its results alone, and
+admission by device footprint holds requests back or rejects them without
+failing."""
 import threading
 import time
 
@@ -35,42 +36,50 @@ def ctx(sel):
 @pytest.fixture(scope="module")
 def world(sel, ctx):
     """Five resident tables (a uniform int32 table, three fact-schema tables
-    and a star fact table with four dimensions) and a program pool each."""
+    and a star fact table with four dimensions) and a program pool each.
+    `want` holds the oracle's count of every pool program; `alone` the
+    library's plain count of it, which must equal it."""
     say("serve: building tables and pools")
     host = [datagen.cfg1(200_000, seed=7),
             datagen.lineorder_like("t1", 300_000, 32),
             datagen.lineorder_like("t2", 1_000_003, 33),
             datagen.lineorder_like("t3", 3_000_000, 2)]
-    dims = datagen.star_dims(seed=42, sizes=(2556, 3000, 20_000, 32_000))
-    fact = datagen.star_fact(2_000_000, dim_rows=(2556, 3000, 20_000, 32_000))
+    dim_rows = (2556, 3000, 20_000, 32_000)
+    dims = datagen.star_dims(seed=42, sizes=dim_rows)
+    fact = datagen.star_fact(2_000_000, dim_rows=dim_rows)
     dts = [sel.device_table(ctx, t) for t in host]
     dfact = sel.device_table(ctx, fact)
     ddims = [sel.device_table(ctx, d) for d in dims]
-    pools = [[ctx.program(dts[0], t) for t in datagen.uniform3_programs(11, 16)]]
+    trees = [datagen.uniform3_programs(11, 16)]
     for k in (1, 2, 3):
-        trees = [tree for _, tree in datagen.cfg3_programs(seed=100 + k, per_table=16, ntables=1)]
-        pools.append([ctx.program(dts[k], t) for t in trees])
-    star_pool, keep = [], []
+        trees.append([tree for _, tree in datagen.cfg3_programs(seed=100 + k, per_table=16,
+                                                                ntables=1)])
+    pools = [[ctx.program(dts[k], t) for t in trees[k]] for k in range(4)]
+    orcs = [oracle.Oracle(t) for t in host]
+    want = [[orcs[k].count(t, threads=8) for t in trees[k]] for k in range(4)]
+    star_pool, star_want, keep = [], [], []
+    ofact = oracle.Oracle(fact)
     for combo in datagen.star_dim_programs(9, 8, dims):
-        bms, nbits = [], []
-        for d, p in zip(ddims, combo):
+        bms, bms_cpu, nbits = [], [], []
+        for d, hd, p in zip(ddims, dims, combo):
             bm = torch.empty((d.nrows + 31) // 32, dtype=torch.int32, device="cuda")
             st, _ = ctx.pushdown_keybitmap(d, 0, 0, ctx.program(d, p), bm, d.nrows)
             assert st == sel.SEL_OK
+            ost, _, owords = oracle.Oracle(hd).keybitmap(p, 0, 0, hd.nrows)
+            assert ost == 0
             bms.append(bm)
+            bms_cpu.append(owords)
             nbits.append(d.nrows)
         keep.append(bms)
         star_pool.append(ctx.star_program(dfact, [0, 1, 2, 3], bms, nbits))
+        star_want.append(ofact.star_count([0, 1, 2, 3], bms_cpu, nbits, threads=8))
     pools.append(star_pool)
+    want.append(star_want)
     tables = dts + [dfact]
     alone = [[ctx.count(tables[k], p) for p in pool] for k, pool in enumerate(pools)]
-    # the star programs equal the star count call, and (a sample) the oracle
-    assert alone[4][0] == ctx.star_count(dfact, [0, 1, 2, 3], keep[0],
-                                         [d.nrows for d in ddims])
-    o3 = oracle.Oracle(host[3])
-    trees3 = [tree for _, tree in datagen.cfg3_programs(seed=103, per_table=16, ntables=1)]
-    assert [o3.count(t, threads=8) for t in trees3[:4]] == alone[3][:4]
-    return dict(tables=tables, pools=pools, alone=alone, keep=keep, host=host)
+    assert alone == want
+    return dict(tables=tables, pools=pools, alone=alone, want=want, keep=keep, host=host,
+                trees=trees, orcs=orcs)
 
 
 def run_trace(sel, ctx, world, trace, srv, time_scale=1.0):
@@ -122,16 +131,23 @@ def test_mix_equals_alone(sel, ctx, world):
     srv = ctx.server(chunk_rows=1 << 18, hbm_budget_bytes=1 << 30)
     res = run_trace(sel, ctx, world, trace, srv)
     stats = srv.stats()
-    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    tables, want = world["tables"], world["want"]
+    checked = 0
     for (t, items, pd), (counts, st, pdc, lat, out) in zip(trace, res):
-        assert counts == [alone[tb][pi] for tb, pi in items]
+        assert counts == [want[tb][pi] for tb, pi in items]
         if pd is not None:
             tb, pi = pd
             mx = sel.max_rows(tables[tb].nrows, 0.05)
-            want = torch.full((max(1, mx),), -1, dtype=torch.int32, device="cuda")
-            wst, wcnt = ctx.pushdown_rowids(tables[tb], pools[tb][pi], mx, want)
-            assert (st, pdc) == (wst, wcnt)
-            assert torch.equal(out, want)     # ids, or untouched when over the limit
+            ost, ocnt, oids = world["orcs"][tb].pushdown(world["trees"][tb][pi], mx,
+                                                         max(1, mx))
+            assert (st, pdc) == ({0: sel.SEL_OK, 1: sel.SEL_OVER_LIMIT}[ost], ocnt)
+            got = out.cpu().numpy().view(np.uint32)
+            if ost == 0:
+                np.testing.assert_array_equal(got[:ocnt], oids)
+                got = got[ocnt:]
+            assert np.all(got == 0xFFFFFFFF)   # nothing past the ids, nothing over the limit
+            checked += 1
+    say(f"serve: {checked} push-downs checked against the oracle")
     assert stats["completed"] == len(trace)
     # work of different requests overlapped: shared scans, several admitted
     assert stats["shared_rounds"] > 0 and stats["max_admitted"] > 1
@@ -140,7 +156,7 @@ def test_mix_equals_alone(sel, ctx, world):
 
 
 def test_single_request_alone(sel, ctx, world):
-    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    tables, pools, alone = world["tables"], world["pools"], world["want"]
     srv = ctx.server()
     for tb in range(5):
         tk = srv.submit([(tables[tb], pools[tb][1])])
@@ -158,7 +174,7 @@ def test_single_request_alone(sel, ctx, world):
 def test_admission_by_footprint(sel, ctx, world):
     """A tiny budget: a request larger than the budget is rejected; requests
     that fit alone but not together wait for each other; all finish."""
-    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    tables, pools, alone = world["tables"], world["pools"], world["want"]
     srv = ctx.server(hbm_budget_bytes=12_000, chunk_rows=1 << 18)
     out = torch.empty(1000, dtype=torch.int32, device="cuda")
     with pytest.raises(sel.SelError) as ei:
@@ -182,7 +198,7 @@ def test_admission_by_footprint(sel, ctx, world):
 def test_chunk_sizes_agree(sel, ctx, world):
     """The same requests with one chunk per table and with many chunks
     (equal chunks per table, and chunks capped by a row count)."""
-    tables, pools, alone = world["tables"], world["pools"], world["alone"]
+    tables, pools, alone = world["tables"], world["pools"], world["want"]
     trace = datagen.serving_trace(seed=8, rate=2000.0, duration=0.03,
                                   pool_sizes=(16, 16, 16, 16, 8), pushdown_rate=0.0)
     for cycle, chunk in ((1, 0), (8, 0), (3, 1 << 16), (1000, 2048)):
@@ -191,3 +207,24 @@ def test_chunk_sizes_agree(sel, ctx, world):
         for (t, items, pd), (counts, *_rest) in zip(trace, res):
             assert counts == [alone[tb][pi] for tb, pi in items], (cycle, chunk)
         srv.destroy()
+
+
+def test_table_recreated_at_same_address(sel, ctx):
+    """A table destroyed while the server lives and a larger one created in
+    its place (the allocator usually hands back the same address): the
+    server scans the new table's rows, not the old geometry."""
+    small = datagen.lineorder_like("s", 100_003, 61)
+    big = datagen.lineorder_like("b", 1_500_001, 62)
+    tree = ("between", 0, 100, 1900)
+    srv = ctx.server(rounds_per_cycle=3)
+    addrs = []
+    for host in (small, big, small):
+        dt = sel.device_table(ctx, host)
+        addrs.append(dt.h.value)
+        prog = ctx.program(dt, tree)
+        counts, st, pdc, lat = srv.wait(srv.submit([(dt, prog)]))
+        assert counts == [oracle.Oracle(host).count(tree, threads=8)], host.name
+        prog.destroy()
+        dt.destroy()
+    say(f"serve: table addresses {[hex(a) for a in addrs]}")
+    srv.destroy()

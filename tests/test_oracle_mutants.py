@@ -36,6 +36,10 @@ MUTANTS = {
     "keybitmap_offset": ("uint64_t b = (uint64_t)(k - key_min);", "uint64_t b = (uint64_t)k;"),
     "thread_split_gap": ("jobs[t].hi = nrows * (uint64_t)(t + 1) / (uint64_t)nt;",
                          "jobs[t].hi = nrows * (uint64_t)(t + 1) / (uint64_t)nt - (t + 1 < nt);"),
+    "star_split_gap": ("nrows * (uint64_t)(t + 1) / (uint64_t)nt, 0};",
+                       "nrows * (uint64_t)(t + 1) / (uint64_t)nt - (t + 1 < nt), 0};"),
+    "rowids_split_gap": ("jobs[t].cap = cap;", "jobs[t].cap = cap;\n    if (t + 1 < nt) jobs[t].hi -= 1;"),
+    "rowids_split_first": ("jobs[t].first = total;", "jobs[t].first = total + (t > 0);"),
 }
 
 
