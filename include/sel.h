@@ -231,6 +231,26 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table,
                                uint32_t* d_out, uint64_t cap,
                                uint64_t* out_count);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc after start-up):
+ * the same push-down, with the same arguments, statuses and results as
+ * sel_pushdown_rowids, whose kernels it shares, but its workspace (packed
+ * mask words, tile counts and offsets, chunk sums and offsets, tile lane
+ * maps: about N/8 + 16*N/2048 bytes plus 16 KB) is a fixed 64 MiB array
+ * that the library holds on each device it runs on until the process ends.
+ * The call allocates nothing and creates no timing events (its kernels are
+ * not counted by sel_ctx_read_timing).  A table whose workspace would
+ * exceed 64 MiB (more than about 505 M rows) gives SEL_E_INVALID with the
+ * sizes in sel_last_error, before any launch.  Every call on one device
+ * shares that device's array: calls that overlap on one device (several
+ * contexts or host threads) race and must be serialised by the caller.
+ * Nothing in the array needs clearing: each call writes every word it reads
+ * before reading it. */
+sel_status sel_pushdown_rowids_noalloc(sel_ctx* ctx, const sel_table* table,
+                                       const sel_program* prog, uint64_t max_rows,
+                                       uint32_t* d_out, uint64_t cap,
+                                       uint64_t* out_count);
+
 /* Push the selection down on a dimension relation: zero d_bitmap[0 ..
  * ceil(nbits/32)) and set bit (key - key_min) for every row whose predicate
  * is TRUE, where key is column `key_col` (an int32 or int64 column without

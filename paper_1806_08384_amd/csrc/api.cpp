@@ -81,7 +81,7 @@ EventPair take_events(sel_ctx* ctx) {
   return p;
 }
 
-TimedLaunch::TimedLaunch(sel_ctx* c, int k) : ctx(c), kind(k), on(c->timing) {
+TimedLaunch::TimedLaunch(sel_ctx* c, int k, bool timed) : ctx(c), kind(k), on(c->timing && timed) {
   if (on) {
     ev = take_events(ctx);
     (void)hipEventRecord(ev.a, ctx->stream);
@@ -157,11 +157,11 @@ bool check_prog(sel_ctx* ctx, const sel_table* t, const sel_program* p) {
   return true;
 }
 
-sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, ScanArgs& a, int kind) {
+sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, ScanArgs& a, int kind, bool timed) {
   uint32_t grid, block;
   scan_shape(ctx, mode, cls, a.ntiles, grid, block);
   a.slot = ctx->slot;
-  TimedLaunch tl(ctx, kind);
+  TimedLaunch tl(ctx, kind, timed);
   int e = sel_launch_scan(mode, a, grid, block, ctx->stream);
   tl.done();
   if (e != 0) return hip_err(ctx, (hipError_t)e, "scan kernel launch");
@@ -214,6 +214,75 @@ sel_status check_columns(sel_ctx* ctx, uint64_t nrows, uint32_t ncols, const sel
     if (((uintptr_t)cols[k].valid) % 4 != 0)
       return set_err(ctx, SEL_E_INVALID, "column " + std::to_string(k) + ": validity not 4-byte aligned");
   }
+  return SEL_OK;
+}
+
+// The row-id push-down over the workspace at sp (the context's grow-only
+// scratch, or the fixed array of the call that allocates nothing).  Every
+// word the kernels read there is written earlier in the same call: the mask
+// pass writes each tile's count and lane map and the mask words those maps
+// name, the tile scan writes every offset and chunk value the compaction
+// reads.  So nothing needs clearing between calls.
+sel_status pushdown_rowids_with(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                                uint64_t max_rows, uint32_t* d_out, uint64_t cap,
+                                uint64_t* out_count, char* sp, bool timed) {
+  const uint64_t ntiles = ntiles_of(table->nrows);
+  const RowidScratch L(ntiles);
+  const size_t mask_bytes = L.mask, counts_bytes = L.counts, chunk_bytes = L.chunk;
+  sel_status st;
+  uint32_t* mask = (uint32_t*)sp;
+  uint32_t* counts = (uint32_t*)(sp + mask_bytes);
+  uint32_t* offsets = (uint32_t*)(sp + mask_bytes + counts_bytes);
+  uint32_t* chunk_sums = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes);
+  uint32_t* chunk_offs = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes + chunk_bytes);
+  uint64_t* lanes = (uint64_t*)(sp + mask_bytes + 2 * counts_bytes + 2 * chunk_bytes);
+  ScanArgs a{};
+  a.prog = prog->dcode;
+  a.nins = prog->nins;
+  set_stage(a, prog);
+  a.nrows = table->nrows;
+  a.ntiles = ntiles;
+  a.out = ctx->dout;
+  a.mask = mask;
+  a.tile_lanes = lanes;
+  a.tile_counts = counts;
+  st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK, timed);
+  if (st != SEL_OK) return st;
+  // the scan of tile counts and the compaction are enqueued at once; the
+  // compaction reads the published count and writes nothing if it exceeds
+  // max_rows or cap, so one wait at the end gives the outcome
+  {
+    TimedLaunch tl(ctx, SEL_K_SCAN, timed);
+    int e = sel_launch_scan_tiles(counts, offsets, chunk_sums, chunk_offs, ntiles, ctx->stream);
+    tl.done();
+    if (e) return hip_err(ctx, (hipError_t)e, "tile scan launch");
+  }
+  CompactArgs c{};
+  c.mask = mask;
+  c.tile_lanes = lanes;
+  c.offsets = offsets;
+  c.chunk_offs = chunk_offs;
+  c.ntiles = ntiles;
+  c.out = d_out;
+  c.cap = cap;
+  c.total = ctx->dout;
+  c.limit = std::min(max_rows, cap);
+  // one wave per tile: compaction is latency-bound, so every tile gets a
+  // wave of its own rather than a grid-stride loop
+  const uint32_t block = 256;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((ntiles + 15) / 16, 1u << 20));
+  {
+    TimedLaunch tl(ctx, SEL_K_COMPACT, timed);
+    int e = sel_launch_compact(c, grid, block, ctx->stream);
+    tl.done();
+    if (e) return hip_err(ctx, (hipError_t)e, "compaction launch");
+  }
+  uint64_t count = 0;
+  st = read_out(ctx, &count, nullptr);   // waits for the compaction too
+  if (st != SEL_OK) return st;
+  *out_count = count;
+  if (count > max_rows) return SEL_OVER_LIMIT;   // Algorithm 1: throw, revert
+  if (count > cap) return SEL_E_CAPACITY;
   return SEL_OK;
 }
 
@@ -285,6 +354,8 @@ sel_status sel_ctx_create(int device, void* hip_stream, sel_ctx** out) {
     DevInstr t{};
     t.op = D_TRUE;
     if ((e = hipMemcpy(ctx->dtrue, &t, sizeof t, hipMemcpyHostToDevice)) != hipSuccess) { where = "hipMemcpy(ctx)"; break; }
+    // the device address of the fixed workspace, with this device current
+    if ((e = (hipError_t)sel_noalloc_scratch(device, &ctx->fixed_scratch)) != hipSuccess) { where = "hipGetSymbolAddress(scratch)"; break; }
   } while (0);
   if (e != hipSuccess) {
     sel_status st = hip_err(nullptr, e, where);
@@ -544,68 +615,28 @@ sel_status sel_pushdown_rowids(sel_ctx* ctx, const sel_table* table, const sel_p
   if (!check_prog(ctx, table, prog)) return SEL_E_INVALID;
   if (!d_out && cap > 0) return set_err(ctx, SEL_E_INVALID, "d_out is NULL with cap > 0");
   DeviceGuard g(ctx->device);
-  const uint64_t ntiles = ntiles_of(table->nrows);
-  const size_t mask_bytes = (size_t)ntiles * kWave * 4;
-  const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
-  const size_t chunk_bytes = 2048 * 4;
-  const size_t lanes_bytes = ((size_t)ntiles * 8 + 255) & ~size_t(255);
-  sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * chunk_bytes + lanes_bytes);
+  sel_status st = ensure_scratch(ctx, RowidScratch(ntiles_of(table->nrows)).total());
   if (st != SEL_OK) return st;
-  char* sp = (char*)ctx->scratch;
-  uint32_t* mask = (uint32_t*)sp;
-  uint32_t* counts = (uint32_t*)(sp + mask_bytes);
-  uint32_t* offsets = (uint32_t*)(sp + mask_bytes + counts_bytes);
-  uint32_t* chunk_sums = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes);
-  uint32_t* chunk_offs = (uint32_t*)(sp + mask_bytes + 2 * counts_bytes + chunk_bytes);
-  uint64_t* lanes = (uint64_t*)(sp + mask_bytes + 2 * counts_bytes + 2 * chunk_bytes);
-  ScanArgs a{};
-  a.prog = prog->dcode;
-  a.nins = prog->nins;
-  set_stage(a, prog);
-  a.nrows = table->nrows;
-  a.ntiles = ntiles;
-  a.out = ctx->dout;
-  a.mask = mask;
-  a.tile_lanes = lanes;
-  a.tile_counts = counts;
-  st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK);
-  if (st != SEL_OK) return st;
-  // the scan of tile counts and the compaction are enqueued at once; the
-  // compaction reads the published count and writes nothing if it exceeds
-  // max_rows or cap, so one wait at the end gives the outcome
-  {
-    TimedLaunch tl(ctx, SEL_K_SCAN);
-    int e = sel_launch_scan_tiles(counts, offsets, chunk_sums, chunk_offs, ntiles, ctx->stream);
-    tl.done();
-    if (e) return hip_err(ctx, (hipError_t)e, "tile scan launch");
-  }
-  CompactArgs c{};
-  c.mask = mask;
-  c.tile_lanes = lanes;
-  c.offsets = offsets;
-  c.chunk_offs = chunk_offs;
-  c.ntiles = ntiles;
-  c.out = d_out;
-  c.cap = cap;
-  c.total = ctx->dout;
-  c.limit = std::min(max_rows, cap);
-  // one wave per tile: compaction is latency-bound, so every tile gets a
-  // wave of its own rather than a grid-stride loop
-  const uint32_t block = 256;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((ntiles + 15) / 16, 1u << 20));
-  {
-    TimedLaunch tl(ctx, SEL_K_COMPACT);
-    int e = sel_launch_compact(c, grid, block, ctx->stream);
-    tl.done();
-    if (e) return hip_err(ctx, (hipError_t)e, "compaction launch");
-  }
-  uint64_t count = 0;
-  st = read_out(ctx, &count, nullptr);   // waits for the compaction too
-  if (st != SEL_OK) return st;
-  *out_count = count;
-  if (count > max_rows) return SEL_OVER_LIMIT;   // Algorithm 1: throw, revert
-  if (count > cap) return SEL_E_CAPACITY;
-  return SEL_OK;
+  return pushdown_rowids_with(ctx, table, prog, max_rows, d_out, cap, out_count,
+                              (char*)ctx->scratch, true);
+}
+
+sel_status sel_pushdown_rowids_noalloc(sel_ctx* ctx, const sel_table* table,
+                                       const sel_program* prog, uint64_t max_rows,
+                                       uint32_t* d_out, uint64_t cap, uint64_t* out_count) {
+  if (!out_count) return set_err(ctx, SEL_E_INVALID, "out_count is NULL");
+  if (!check_prog(ctx, table, prog)) return SEL_E_INVALID;
+  if (!d_out && cap > 0) return set_err(ctx, SEL_E_INVALID, "d_out is NULL with cap > 0");
+  const size_t need = RowidScratch(ntiles_of(table->nrows)).total();
+  if (need > kNoAllocScratchBytes)
+    return set_err(ctx, SEL_E_INVALID,
+                   "table of " + std::to_string(table->nrows) + " rows needs " + std::to_string(need) +
+                       " bytes of workspace, more than the fixed " +
+                       std::to_string(kNoAllocScratchBytes) + " (use sel_pushdown_rowids)");
+  if (!ctx->fixed_scratch) return set_err(ctx, SEL_E_DEVICE, "fixed workspace not set up");
+  DeviceGuard g(ctx->device);
+  return pushdown_rowids_with(ctx, table, prog, max_rows, d_out, cap, out_count,
+                              (char*)ctx->fixed_scratch, false);
 }
 
 sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t key_col,

@@ -104,14 +104,12 @@ sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program*
   a.out = ctx->dout;
   a.slot = ctx->slot;
   if (with_mask) {
-    const size_t mask_bytes = (size_t)ntiles * kWave * 4;
-    const size_t counts_bytes = ((size_t)ntiles * 4 + 255) & ~size_t(255);
-    const size_t lanes_bytes = ((size_t)ntiles * 8 + 255) & ~size_t(255);
-    sel_status st = ensure_scratch(ctx, mask_bytes + 2 * counts_bytes + 2 * 2048 * 4 + lanes_bytes);
+    const RowidScratch L(ntiles);
+    sel_status st = ensure_scratch(ctx, L.total());
     if (st != SEL_OK) return st;
     a.mask = (uint32_t*)ctx->scratch;
-    a.tile_counts = (uint32_t*)((char*)ctx->scratch + mask_bytes);
-    a.tile_lanes = (uint64_t*)((char*)ctx->scratch + mask_bytes + 2 * counts_bytes + 2 * 2048 * 4);
+    a.tile_counts = (uint32_t*)((char*)ctx->scratch + L.mask);
+    a.tile_lanes = (uint64_t*)((char*)ctx->scratch + L.mask + 2 * L.counts + 2 * L.chunk);
   }
   Candidate b{256, 0};
   double ms = 0;

@@ -21,6 +21,9 @@
 // scalar; only the leaf tests touch per-row data.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "sel_device.h"
 
 using namespace sel;
@@ -1372,6 +1375,29 @@ __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
 }
 
 }  // namespace
+
+// Workspace of sel_pushdown_rowids_noalloc: a fixed array in each device's
+// copy of the code object, for callers that cannot allocate device memory.
+// In host code `scratch` names a host-side stand-in, not a device address;
+// kernels receive the address that sel_noalloc_scratch looked up for the
+// current device.
+static __device__ __align__(256) uint8_t scratch[sel::kNoAllocScratchBytes];
+
+int sel_noalloc_scratch(int device, void** ptr) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> address of its array
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (p == nullptr) return (int)hipErrorInvalidSymbol;
+    it = addr.emplace(device, p).first;
+  }
+  *ptr = it->second;
+  return 0;
+}
 
 int sel_launch_scan(int mode, const ScanArgs& a, uint32_t grid, uint32_t block, void* stream) {
   hipStream_t s = (hipStream_t)stream;

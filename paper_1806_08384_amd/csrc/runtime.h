@@ -102,6 +102,8 @@ struct sel_ctx {
   unsigned long long* hbatch = nullptr;    // pinned host, kBatchMaxProgs counts
   selrt::Arena arena;
   void* scratch = nullptr;                 // device, grow-only
+  void* fixed_scratch = nullptr;           // device, the library's fixed
+                                           // workspace on this device
   size_t scratch_bytes = 0;
 
   sel_launch launch{256, 0};
@@ -177,7 +179,26 @@ inline uint32_t batch_class(uint32_t nprogs) {
 }
 void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
                 uint32_t& block);
-sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int kind);
+sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int kind,
+                    bool timed = true);
+
+// Byte layout of the row-id path's workspace for a table of ntiles tiles:
+// the packed mask words, tile counts, tile offsets, chunk sums, chunk
+// offsets and tile lane maps, in that order.
+struct RowidScratch {
+  size_t mask, counts, chunk, lanes;
+  explicit RowidScratch(uint64_t ntiles)
+      : mask((size_t)ntiles * sel::kWave * 4),
+        counts(((size_t)ntiles * 4 + 255) & ~size_t(255)),
+        chunk(2048 * 4),
+        lanes(((size_t)ntiles * 8 + 255) & ~size_t(255)) {}
+  size_t total() const { return mask + 2 * counts + 2 * chunk + lanes; }
+};
+// The push-down of sel_pushdown_rowids with its workspace at `sp` (at least
+// RowidScratch(ntiles).total() bytes of device memory); arguments checked.
+sel_status pushdown_rowids_with(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
+                                uint64_t max_rows, uint32_t* d_out, uint64_t cap,
+                                uint64_t* out_count, char* sp, bool timed);
 
 // Descriptors of one leaf-major batched launch (k_batch).  add() appends
 // passes over rows [row_begin, row_end) of a table for a list of programs;
@@ -255,7 +276,8 @@ struct TimedLaunch {
   int kind;
   EventPair ev{};
   bool on;
-  TimedLaunch(sel_ctx* c, int k);
+  // timed = false: never (the calls that must not create events)
+  TimedLaunch(sel_ctx* c, int k, bool timed = true);
   void done();
 };
 

@@ -20,6 +20,11 @@ constexpr int kSteps = 8;
 constexpr int kTileRows = kWave * kRowsPerStep * kSteps;  // 2048
 constexpr int kMaxDepth = 8;
 
+// Bytes of the fixed device workspace of the push-down that allocates
+// nothing (mask words, tile counts and offsets, chunk sums and offsets,
+// tile lane maps): 64 MiB, enough for tables of about 505 M rows.
+constexpr unsigned long long kNoAllocScratchBytes = 64ull << 20;
+
 enum DevType : uint32_t { T_I8 = 1, T_I16 = 2, T_I32 = 3, T_I64 = 4 };
 
 // Device opcodes (the lowered program).
@@ -318,6 +323,9 @@ struct BatchArgs {
 
 // Launchers implemented in kernels.hip (return hipError_t as int).
 extern "C++" {
+// Address on `device` (which must be current) of the fixed workspace of
+// sel_pushdown_rowids_noalloc, looked up once per device.
+int sel_noalloc_scratch(int device, void** ptr);
 int sel_launch_scan(int mode, const sel::ScanArgs& a, uint32_t grid, uint32_t block, void* stream);
 int sel_launch_scan_tiles(const uint32_t* counts, uint32_t* offsets, uint32_t* chunk_sums,
                           uint32_t* chunk_offs, uint64_t n, void* stream);

@@ -139,6 +139,8 @@ sel_count = _sig("sel_count", _i32, _vp, _vp, _vp, _P(_u64))
 sel_count_async = _sig("sel_count_async", _i32, _vp, _vp, _vp, _vp)
 sel_max_rows = _sig("sel_max_rows", _u64, _u64, ctypes.c_double)
 sel_pushdown_rowids = _sig("sel_pushdown_rowids", _i32, _vp, _vp, _vp, _u64, _vp, _u64, _P(_u64))
+sel_pushdown_rowids_noalloc = _sig("sel_pushdown_rowids_noalloc", _i32, _vp, _vp, _vp, _u64, _vp, _u64,
+                                   _P(_u64))
 sel_pushdown_keybitmap = _sig("sel_pushdown_keybitmap", _i32, _vp, _vp, _u32, _i64, _vp, _vp, _u64,
                               _P(_u64))
 sel_star_count = _sig("sel_star_count", _i32, _vp, _vp, _vp, _u32, _P(_u32), _P(_vp), _P(_u64),
@@ -370,6 +372,17 @@ class Context:
             cap = 0 if out_tensor is None else out_tensor.numel()
         ptr = None if out_tensor is None else out_tensor.data_ptr()
         st = sel_pushdown_rowids(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
+        self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
+        return st, int(out.value)
+
+    def pushdown_rowids_noalloc(self, table, prog, max_rows: int, out_tensor, cap=None):
+        """pushdown_rowids over the library's fixed device workspace: the
+        call allocates nothing.  Returns (status, count)."""
+        out = _u64(0)
+        if cap is None:
+            cap = 0 if out_tensor is None else out_tensor.numel()
+        ptr = None if out_tensor is None else out_tensor.data_ptr()
+        st = sel_pushdown_rowids_noalloc(self.h, table.h, prog.h, max_rows, ptr, cap, ctypes.byref(out))
         self.check(st, ok=(SEL_OK, SEL_OVER_LIMIT, SEL_E_CAPACITY))
         return st, int(out.value)
 
