@@ -36,10 +36,11 @@ TYPE_RANGE = {t: (int(np.iinfo(d).min), int(np.iinfo(d).max)) for t, d in NP_DTY
 
 
 def lib():
-    """Load libdatagen.so (built by datagen/build.py)."""
+    """Load libdatagen.so (built by datagen/build.py; the environment
+    variable SEL_DATAGEN_LIB names another build, e.g. a sanitizer build)."""
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "libdatagen.so")
+        path = os.environ.get("SEL_DATAGEN_LIB") or os.path.join(_HERE, "libdatagen.so")
         if not os.path.exists(path):
             from . import build as _b
             _b.build()

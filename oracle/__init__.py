@@ -59,8 +59,9 @@ class _Col(ctypes.Structure):
 
 
 def load(path: str | None = None):
-    """Load liboracle.so (or a given build of oracle.c)."""
-    path = path or os.path.join(_HERE, "liboracle.so")
+    """Load liboracle.so (or a given build of oracle.c; the environment
+    variable SEL_ORACLE_LIB names another build, e.g. a sanitizer build)."""
+    path = path or os.environ.get("SEL_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
     if path in _LIBS:
         return _LIBS[path]
     if not os.path.exists(path):
