@@ -193,8 +193,29 @@ def bench_batch(ctx, fact_dt, threads, log):
     t_sync, r1 = _timed(plain_sync, reps)
     t_async, r2 = _timed(plain_async, reps)
     t_eager, r3 = _timed(eager, reps)
+    ctx.read_timing(reset=True)
     t_graph, r4 = _timed(b.run, reps)
+    bms, bl = ctx.read_timing(reset=True)
+    graph_kernel_ms = bms[sel.K_BATCH] / max(1, bl[sel.K_BATCH])
     assert r1 == want and r2 == want and r3 == want and r4 == want, "batch counts differ"
+    # algorithmic bytes of one launch: each table's rows times the union of
+    # the columns its programs read (values, plus 1/8 B for the validity
+    # bits of a nullable column)
+    all_tables = list(small) + [None]
+    union_bpr = []
+    for ti in range(4):
+        cols_used = set()
+        for t, tree in progs:
+            if t == ti:
+                cols_used |= datagen.tree_columns(tree)
+        if ti < 3:
+            cols = all_tables[ti].columns
+        else:
+            cols = datagen.lineorder_like("schema", 1, 0).columns
+        union_bpr.append(sum(datagen.WIDTH[cols[c].type] + (0.125 if cols[c].valid is not None else 0.0)
+                             for c in cols_used))
+    rows = [small[0].nrows, small[1].nrows, small[2].nrows, fact_dt.nrows]
+    batch_bytes = sum(r * u for r, u in zip(rows, union_bpr))
     # bytes: plain reads each program's columns; the batch reads each table's
     # union of referenced columns once from HBM
     plain_bytes = sum(t.nrows * p.bytes_per_row for t, p in pairs)
@@ -210,6 +231,18 @@ def bench_batch(ctx, fact_dt, threads, log):
         "speedup_vs_best_plain": best_plain / t_graph,
         "plain_bytes": plain_bytes,
         "counts_equal": True,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_luts + k_lbatch (and k_batch for programs outside conjunctive form), "
+                      "graph replay",
+            "algorithmic_bytes_per_launch": batch_bytes,
+            "union_bytes_per_row": union_bpr,
+            "avg_graph_ms": graph_kernel_ms,
+            "achieved": batch_bytes / graph_kernel_ms / 1e6,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": batch_bytes / graph_kernel_ms / 1e6 / HBM_PEAK_GBS,
+        },
     }
     b.destroy()
     for t, p in pairs:
@@ -574,6 +607,13 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
         "round_host_ms_mean": stats["round_host_ms"] / max(1, stats["rounds"]),
         "gpu_busy_fraction": (stats["round_gpu_ms"] / (stats["elapsed_s"] * 1e3)
                               if stats["elapsed_s"] else None),
+        # per round: the chunk rows of each table times the columns its
+        # programs read, over the round's device time
+        "round_bytes_mean": stats["round_bytes"] / max(1, stats["rounds"]),
+        "round_GBps": (stats["round_bytes"] / stats["round_gpu_ms"] / 1e6
+                       if stats["round_gpu_ms"] else None),
+        "round_frac_of_peak": (stats["round_bytes"] / stats["round_gpu_ms"] / 1e6 / HBM_PEAK_GBS
+                               if stats["round_gpu_ms"] else None),
         "by_largest_table_rows": {
             str(k): {"requests": len(v), "p50_ms": percentile(sorted(v), 50),
                      "p99_ms": percentile(sorted(v), 99)}

@@ -495,6 +495,10 @@ typedef struct sel_server_stats {
   uint64_t round_groups;               /* distinct programs summed over rounds */
   double round_gpu_ms;                 /* device time of the rounds, summed */
   double round_host_ms;                /* host time planning and launching them */
+  double round_bytes;                  /* bytes the rounds read, summed: per table
+                                          and round, the chunk's rows times the
+                                          element sizes of the columns its
+                                          programs test (+1/8 per validity bitmap) */
 } sel_server_stats;
 
 /* Start a server (two worker threads, its own streams and a push-down

@@ -15,8 +15,8 @@ LIB = os.path.join(HERE, "libsel.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "api.cpp", "compile.cpp", "batch.cpp", "batchplan.cpp", "autotune.cpp", "serve.cpp",
-           "spd.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "compile.cpp", "batch.cpp", "batchplan.cpp", "lutplan.cpp", "autotune.cpp",
+           "serve.cpp", "spd.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}"]
 # device code: gfx950 only; packed fp32 VALU ops stay disabled (no float

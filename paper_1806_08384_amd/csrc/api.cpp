@@ -534,6 +534,8 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
     return cst;
   }
   p->host_code = L.code;
+  p->host_blob = L.blob;
+  p->blob_dev = blob_base;
   double bpr = 0.0;
   for (uint32_t c : L.columns) bpr += type_bytes(ci[c].type);
   bpr += (double)L.valid_columns.size() / 8.0;
@@ -853,6 +855,10 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
   p->bytes_per_row = bpr;
   p->tune_class = tune_class_of(bpr, p->nins);
   p->host_code = code;
+  if (fact_pred) {   // the fact predicate's constants, for host-side planning
+    p->host_blob = fact_pred->host_blob;
+    p->blob_dev = fact_pred->blob_dev;
+  }
   p->text = "STAR\n";
   std::vector<BatchBitmap> stage;
   p->stage_words = plan_scan_stage(code, stage);

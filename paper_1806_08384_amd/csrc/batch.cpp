@@ -36,6 +36,8 @@ struct sel_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   BatchArgs args{};                           // as captured
+  LutArgs largs{};                            // as captured
+  uint32_t lut_grid = 0, lut_block = 0, lut_lds = 0;
   uint32_t grid = 0, block = 256, lds = 0;
 };
 
@@ -59,6 +61,9 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
       distinct.push_back(tables[i]);
   }
   bp.clear();
+  // the lookup-table kernel when every table is short (see BatchPlan::add)
+  bp.allow_lut = true;
+  for (const sel_table* t : distinct) bp.allow_lut &= t->nrows <= kLutMaxRows;
   std::vector<const sel_program*> ps;
   std::vector<uint32_t> acc;
   for (const sel_table* t : distinct) {
@@ -71,6 +76,7 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
     }
     bp.add(t, 0, t->nrows, ps.data(), acc.data(), (uint32_t)ps.size());
   }
+  bp.num_cus = ctx->num_cus;
   return SEL_OK;
 }
 
@@ -173,7 +179,7 @@ sel_status rebuild(sel_batch* b) {
   sel_status st = plan_batch(ctx, b->n, b->tabs.data(), b->slot_prog.data(), b->plan);
   if (st != SEL_OK) return st;
   const size_t need = up256(b->plan.bytes());
-  const size_t need_gtab = up256(b->plan.gtab_words * 4);
+  const size_t need_gtab = up256(b->plan.gtab_total() * 4);
   if (need > b->desc_cap || need_gtab > b->gtab_cap) {
     if (b->dev) {
       (void)hipStreamSynchronize(b->stream);
@@ -203,10 +209,19 @@ sel_status rebuild(sel_batch* b) {
   batch_shape(ctx, b->n, b->plan, grid, block);
   const uint32_t lds = b->plan.lds_bytes(block);
   const uint32_t nbuilds = (uint32_t)b->plan.builds.size();
+  uint32_t lgrid = 0, lblock = 0;
+  if (!b->plan.lut.empty()) b->plan.lut_shape(lgrid, lblock);
+  const uint32_t llds = b->plan.lut.empty() ? 0u : b->plan.lut.lds_bytes();
   if (b->exec && std::memcmp(&a, &b->args, sizeof a) == 0 && grid == b->grid && block == b->block &&
       lds == b->lds && d_builds == b->d_builds && nbuilds == b->nbuilds &&
-      b->plan.table_entries == b->table_entries)
+      b->plan.table_entries == b->table_entries &&
+      std::memcmp(&b->plan.largs, &b->largs, sizeof b->largs) == 0 && lgrid == b->lut_grid &&
+      lblock == b->lut_block && llds == b->lut_lds)
     return SEL_OK;
+  b->largs = b->plan.largs;
+  b->lut_grid = lgrid;
+  b->lut_block = lblock;
+  b->lut_lds = llds;
   b->args = a;
   b->grid = grid;
   b->block = block;
@@ -233,7 +248,7 @@ sel_status sel_count_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tab
   // workspace in the context's batch area: descriptors, then accumulators,
   // counts and the slot
   const size_t desc = up256(bp.bytes());
-  const size_t bytes = desc + tail_bytes(n) + up256(bp.gtab_words * 4);
+  const size_t bytes = desc + tail_bytes(n) + up256(bp.gtab_total() * 4);
   if (bytes > ctx->batch_bytes) {
     if (ctx->batch_mem) {
       (void)hipStreamSynchronize(ctx->stream);
@@ -385,6 +400,8 @@ sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_pro
     f.table = table;
     f.host_code.assign(prog->host_code.begin() + ranges[k].first,
                        prog->host_code.begin() + ranges[k].second);
+    f.host_blob = prog->host_blob;
+    f.blob_dev = prog->blob_dev;
     f.nins = (uint32_t)f.host_code.size();
     progs.push_back(&f);
   }

@@ -8,6 +8,7 @@
 // program's combinators over the resulting truth words held in LDS slots.
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <tuple>
@@ -430,6 +431,8 @@ std::vector<std::pair<size_t, size_t>> and_factors(const std::vector<DevInstr>& 
 }
 
 void BatchPlan::clear() {
+  lut.clear();
+  largs = LutArgs{};
   entries.clear();
   cols.clear();
   leaves.clear();
@@ -445,8 +448,35 @@ void BatchPlan::clear() {
 }
 
 void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
-                    const sel_program* const* prg, const uint32_t* acc, uint32_t n) {
-  if (row_end <= row_begin || n == 0) return;
+                    const sel_program* const* prg_all, const uint32_t* acc_all, uint32_t n_all) {
+  if (row_end <= row_begin || n_all == 0) return;
+  // The lookup-table kernel takes the programs it can express when the
+  // caller allows it (every chunk of the launch at most kLutMaxRows rows:
+  // there its single lookup per column and row beats the leaf-major kernel,
+  // whose fixed costs per launch and pass dominate; over longer chunks the
+  // leaf-major kernel keeps more loads in flight per wave, and a launch that
+  // mixed both would run them one after the other).  The environment
+  // variable SEL_BATCH_KERNEL forces either kernel ("lut": every
+  // expressible program, "leaf": none).
+  std::vector<const sel_program*> prg_v;
+  std::vector<uint32_t> acc_v;
+  const char* mode = std::getenv("SEL_BATCH_KERNEL");
+  const bool force_lut = mode && std::strcmp(mode, "lut") == 0;
+  // half the rows per lane per segment in the lookup-table kernel
+  if (const char* fr = std::getenv("SEL_LUT_FEWER_ROWS")) lut_fewer_rows = std::atoi(fr) != 0 ? 1u : 0u;
+  if ((mode && std::strcmp(mode, "leaf") == 0) || (!force_lut && !allow_lut)) {
+    prg_v.assign(prg_all, prg_all + n_all);
+    acc_v.assign(acc_all, acc_all + n_all);
+  } else {
+    for (uint32_t i : lut.add(t, row_begin, row_end, prg_all, acc_all, n_all)) {
+      prg_v.push_back(prg_all[i]);
+      acc_v.push_back(acc_all[i]);
+    }
+  }
+  const sel_program* const* prg = prg_v.data();
+  const uint32_t* acc = acc_v.data();
+  const uint32_t n = (uint32_t)prg_v.size();
+  if (n == 0) return;
   const uint64_t tiles = (row_end - row_begin + kTileRows - 1) / kTileRows;
   auto flush = [&](Pass& ps) {
     if (ps.progs.empty()) return;
@@ -563,15 +593,19 @@ namespace {
 size_t up(size_t x) { return (x + 255) & ~size_t(255); }
 }  // namespace
 
-size_t BatchPlan::bytes() const {
-  size_t o = up(entries.size() * sizeof(BatchTable));
-  o = up(o + cols.size() * sizeof(BatchCol));
-  o = up(o + leaves.size() * sizeof(DevInstr));
-  o = up(o + progs.size() * sizeof(BatchProg));
-  o = up(o + ops.size() * sizeof(uint32_t));
-  o = up(o + bms.size() * sizeof(BatchBitmap));
-  return up(o + builds.size() * sizeof(TableBuild));
+namespace {
+size_t leaf_bytes(const BatchPlan& p) {
+  size_t o = up(p.entries.size() * sizeof(BatchTable));
+  o = up(o + p.cols.size() * sizeof(BatchCol));
+  o = up(o + p.leaves.size() * sizeof(DevInstr));
+  o = up(o + p.progs.size() * sizeof(BatchProg));
+  o = up(o + p.ops.size() * sizeof(uint32_t));
+  o = up(o + p.bms.size() * sizeof(BatchBitmap));
+  return up(o + p.builds.size() * sizeof(TableBuild));
 }
+}  // namespace
+
+size_t BatchPlan::bytes() const { return leaf_bytes(*this) + (lut.empty() ? 0 : lut.bytes()); }
 
 void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a,
                       const TableBuild** d_builds) const {
@@ -581,7 +615,11 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
   const size_t o_ops = up(o_progs + progs.size() * sizeof(BatchProg));
   const size_t o_bms = up(o_ops + ops.size() * sizeof(uint32_t));
   const size_t o_builds = up(o_bms + bms.size() * sizeof(BatchBitmap));
-  std::memset(host, 0, bytes());
+  std::memset(host, 0, leaf_bytes(*this));
+  if (!lut.empty()) {
+    const size_t lo = leaf_bytes(*this);
+    lut.write(host + lo, dev + lo, gtab_dev + gtab_words, largs);
+  }
   if (!entries.empty()) std::memcpy(host, entries.data(), entries.size() * sizeof(BatchTable));
   BatchCol* hc = (BatchCol*)(host + o_cols);
   for (size_t k = 0; k < cols.size(); ++k) {
@@ -615,8 +653,44 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
   a.acc_words = acc_words();
 }
 
+void BatchPlan::lut_shape(uint32_t& grid, uint32_t& block) const {
+  block = lut_block ? lut_block : kLutBlock;
+  uint64_t g = lut_grid;
+  if (g == 0) {
+    int occ = 1;
+    if (sel_lbatch_occupancy(1, lut_fewer_rows, block, lut.lds_bytes(), &occ) != 0 || occ < 1) occ = 1;
+    g = (uint64_t)occ * num_cus;
+  }
+  const uint64_t need = std::max<uint64_t>(1, lut.total_tiles / (block / kWave));
+  grid = (uint32_t)std::min(g, need);
+}
+
 int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t grid, uint32_t block,
                       void* stream) const {
+  const bool leaf = !entries.empty() || lut.empty();
+  if (!lut.empty()) {
+    LutArgs la = largs;
+    la.acc = a.acc;
+    la.out = a.out;
+    la.slot = a.slot;
+    la.done = a.done;
+    // the last launch moves the finished lines out: k_batch if it runs
+    int e = sel_launch_luts(la, stream);
+    if (e) return e;
+    uint32_t lg, lb;
+    lut_shape(lg, lb);
+    // one launch per accumulator width present; each takes its own passes
+    bool present[5] = {false, false, false, false, false};
+    for (const LutPass& p : lut.passes) present[p.dwords] = true;
+    const uint32_t last = present[4] ? 4u : present[2] ? 2u : 1u;
+    for (uint32_t d : {1u, 2u, 4u}) {
+      if (!present[d]) continue;
+      la.ndone = !leaf && d == last ? a.ndone : 0u;
+      e = sel_launch_lbatch(la, d, lut_fewer_rows, lg, lb, lut.lds_bytes(), stream);
+      if (e) return e;
+    }
+  }
+  if (!leaf) return 0;
   if (!builds.empty()) {
     const int e = sel_launch_tables(d_builds, (uint32_t)builds.size(), table_entries, stream);
     if (e) return e;
@@ -627,6 +701,24 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
 uint32_t plan_scan_stage(const std::vector<DevInstr>& code, std::vector<BatchBitmap>& out) {
   out.clear();
   uint32_t words = 0;
+  // sorted IN lists first (searched in LDS: log2(n) reads per row), at
+  // even word offsets for their int64 values
+  for (const DevInstr& I : code) {
+    if (I.op != D_INLIST || I.n == 0 || out.size() == kMaxStage) continue;
+    bool seen = false;
+    for (const BatchBitmap& b : out) seen |= b.src == (const uint32_t*)I.aux;
+    if (seen) continue;
+    const uint32_t w = 2 * I.n;
+    const uint32_t at = (words + 1) & ~1u;
+    if (at + w + 1 > kScanStageWords) continue;
+    BatchBitmap b{};
+    b.src = (const uint32_t*)I.aux;
+    b.words = w;
+    b.last_mask = ~0u;
+    b.lds_word = at;
+    out.push_back(b);
+    words = at + w + 1;
+  }
   for (const DevInstr& I : code) {
     if (I.op != D_BITMAP || I.span == 0 || out.size() == kMaxStage) continue;
     if (I.type != T_I64 &&

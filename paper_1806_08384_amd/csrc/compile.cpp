@@ -159,6 +159,8 @@ struct Builder {
     n.ins.data = cols[col].data;
     n.ins.valid = cols[col].valid;
     n.ins.n = (uint32_t)v.size();
+    n.ins.lo = mn;   // the list's window [lo, lo + span]
+    n.ins.span = (uint64_t)mx - (uint64_t)mn;
     n.aux.resize(v.size() * 8);
     std::memcpy(n.aux.data(), v.data(), n.aux.size());
     n.col = col;

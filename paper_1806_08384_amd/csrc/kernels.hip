@@ -30,6 +30,8 @@ using namespace sel;
 
 typedef int32_t v2i __attribute__((ext_vector_type(2)));
 typedef int32_t v4i __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 // Pointers read from memory are generic to the compiler; casting them to
 // the global (1) or constant (4) address space gives global_load / s_load
@@ -186,6 +188,65 @@ __device__ __forceinline__ uint32_t inrange_bits(uint64_t tb, uint32_t lane, uin
   return m;
 }
 
+// IN-list test of a lane's 32 rows against a sorted list of n values (in
+// LDS or device memory): wide loads of the column as for a range test, then
+// a branch-free lower bound that moves the eight rows of two steps one
+// search step at a time, so that their list reads are in flight together.
+template <int TY, bool FULL, class List>
+__device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, uint32_t lane,
+                                                uint64_t nrows, List list, uint32_t n, uint32_t need) {
+  uint32_t P = 0;
+#pragma unroll 1
+  for (int q = 3; q >= 0; --q) {   // bits 8q .. 8q + 7: steps 2q, 2q + 1
+    int64_t x[8];
+    if constexpr (FULL) {
+#pragma unroll
+      for (int js = 0; js < 2; ++js) {
+        const int j = 2 * q + js;
+        if constexpr (TY == T_I8) {
+          const uint32_t w = __builtin_nontemporal_load(gptr<uint32_t>((const int8_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int8_t)(w >> (8 * i));
+        } else if constexpr (TY == T_I16) {
+          const v2i w = __builtin_nontemporal_load(gptr<v2i>((const int16_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int16_t)((uint32_t)w[i >> 1] >> (16 * (i & 1)));
+        } else if constexpr (TY == T_I32) {
+          const v4i w = __builtin_nontemporal_load(gptr<v4i>((const int32_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)w[i];
+        } else {
+          const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * j;
+          const v4i w0 = __builtin_nontemporal_load(p), w1 = __builtin_nontemporal_load(p + 1);
+          x[4 * js + 0] = (int64_t)(((uint64_t)(uint32_t)w0[1] << 32) | (uint32_t)w0[0]);
+          x[4 * js + 1] = (int64_t)(((uint64_t)(uint32_t)w0[3] << 32) | (uint32_t)w0[2]);
+          x[4 * js + 2] = (int64_t)(((uint64_t)(uint32_t)w1[1] << 32) | (uint32_t)w1[0]);
+          x[4 * js + 3] = (int64_t)(((uint64_t)(uint32_t)w1[3] << 32) | (uint32_t)w1[2]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint64_t row = row_of(tb, lane, 8 * q + k);
+        x[k] = row < nrows ? (int64_t)load_elem<TY>(data, row) : 0;
+      }
+    }
+    uint32_t base[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) base[k] = 0;
+    for (uint32_t len = n; len > 1;) {
+      const uint32_t half = len >> 1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) base[k] = list[base[k] + half] <= x[k] ? base[k] + half : base[k];
+      len -= half;
+    }
+#pragma unroll
+    for (int k = 7; k >= 0; --k)
+      P = (P << 1) + (uint32_t)(((need >> (8 * q + k)) & 1u) && list[base[k]] == x[k]);
+  }
+  return P;
+}
+
 // ---------------------------------------------------------------- leaves --
 template <int TY, bool FULL>
 __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
@@ -193,6 +254,14 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
   const void* data = I->data;
   const int64_t lo = I->lo;
   const uint64_t span = I->span;
+  if (op == D_INLIST) {
+    // the list's LDS copy if the scan staged it
+    for (uint32_t k = 0; k < sv.n; ++k)
+      if (sv.list[k].src == (const uint32_t*)I->aux)
+        return inlist_bits<TY, FULL>(data, tb, lane, nrows, (const int64_t*)(sv.lds + sv.list[k].lds_word),
+                                     I->n, need);
+    return inlist_bits<TY, FULL>(data, tb, lane, nrows, gptr<int64_t>(I->aux), I->n, need);
+  }
   if (op == D_BITMAP && sv.n) {
     uint32_t off = kNoLds, z = 0;
     for (uint32_t k = 0; k < sv.n; ++k) {
@@ -255,20 +324,8 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
         return ok & ((bits[k >> 5] >> (k & 31)) & 1u);
       });
     }
-  } else {  // D_INLIST: branch-free lower bound over a sorted list
-    // a long sparse list (rare): rows one at a time, loop kept rolled
-    const GLOBAL int64_t* list = gptr<int64_t>(I->aux);
-    const uint32_t n = I->n;
-    return pred_bits<TY, false>(data, tb, lane, nrows, [=](auto x, int b) -> uint32_t {
-      const int64_t xx = (int64_t)x;
-      uint32_t base = 0, len = n;
-      while (len > 1) {
-        const uint32_t half = len >> 1;
-        base = list[base + half] <= xx ? base + half : base;
-        len -= half;
-      }
-      return ((need >> b) & 1u) & (list[base] == xx ? 1u : 0u);
-    });
+  } else {  // D_INLIST, handled above
+    return 0u;
   }
 }
 
@@ -957,6 +1014,24 @@ __device__ __forceinline__ void tab_leaves(const Seg& r, const CONSTANT BatchCol
     if ((uint32_t)i < m) put_leaf(wl, lane, tl[i].slot, T[i]);
 }
 
+// A sparse IN-list leaf of the batched kernel: rows one at a time (its
+// registers are spent on the column pipeline), loop kept rolled.
+template <int TY>
+__device__ __noinline__ uint32_t inlist_rows(CInstr I, uint64_t tb, uint32_t lane, uint64_t nrows) {
+  const GLOBAL int64_t* list = gptr<int64_t>(I->aux);
+  const uint32_t n = I->n;
+  return pred_bits<TY, false>(I->data, tb, lane, nrows, [=](auto x, int) -> uint32_t {
+    const int64_t xx = (int64_t)x;
+    uint32_t base = 0, len = n;
+    while (len > 1) {
+      const uint32_t half = len >> 1;
+      base = list[base + half] <= xx ? base + half : base;
+      len -= half;
+    }
+    return list[base] == xx ? 1u : 0u;
+  });
+}
+
 // Every leaf of one segment; truth words go to the wave's slots.  An int64
 // column's upper half (h = 0) writes bits 16..31, its lower half completes
 // them.  Sparse value lists take the element path once, with the last
@@ -973,8 +1048,7 @@ __device__ __forceinline__ void seg_leaves(const Seg& r, const CONSTANT BatchCol
     CInstr I = leaves + lb + k;
     const uint32_t op = I->op;
     if (op == D_INLIST) {
-      if (TY != T_I64 || h == 1)
-        put_leaf(wl, lane, I->slot, leaf_pred<TY, false>(op, I, tb, lane, tb + kTileRows, ~0u, StageView{}));
+      if (TY != T_I64 || h == 1) put_leaf(wl, lane, I->slot, inlist_rows<TY>(I, tb, lane, tb + kTileRows));
       continue;
     }
     const uint32_t P = seg_leaf<TY>(r, op, I, bmlds, wl, lane, TY == T_I64 && h == 0 ? 16 : 0);
@@ -1369,6 +1443,701 @@ __global__ void __launch_bounds__(256) k_tables(const TableBuild* __restrict__ t
   }
 }
 
+// ------------------------------------------ batched count, column tables --
+// A program of a pass owns one bit of each word of a row's accumulator (its
+// single-column clauses that failed, and one word per clause spanning
+// columns); a column ORs into it the entry of its value in its lookup table,
+// so one lookup serves every program of the pass on that column.
+
+// Truth of a literal (a leaf test, possibly negated) on a row: `nonnull`
+// says whether the row's value is present, `inwin` whether x lies in the
+// window of the column's value tests (outside it every value test is FALSE).
+__device__ __forceinline__ bool lit_true(const DevInstr& L, bool nonnull, bool inwin, int64_t x) {
+  const bool neg = (L.flags & kLitNeg) != 0u;
+  switch (L.op) {
+    case D_NN_TRUE: return nonnull && !neg;
+    case D_NN_FALSE: return nonnull && neg;
+    case D_ISNULL: return nonnull ? neg : !neg;
+    case D_NOTNULL: return nonnull ? !neg : neg;
+    default: break;
+  }
+  if (!nonnull) return false;   // a value test on NULL is UNKNOWN, negated or not
+  bool v = false;
+  if (inwin) {
+    const uint64_t d = (uint64_t)x - (uint64_t)L.lo;
+    if (L.op == D_RANGE) {
+      v = d <= L.span;
+    } else if (L.op == D_BITMAP) {
+      v = d < L.span && ((((const uint32_t*)L.aux)[d >> 5] >> (d & 31)) & 1u);
+    } else {  // D_INLIST: lower bound in the sorted list
+      const int64_t* list = (const int64_t*)L.aux;
+      uint32_t base = 0, len = L.n;
+      while (len > 1) {
+        const uint32_t half = len >> 1;
+        base = list[base + half] <= x ? base + half : base;
+        len -= half;
+      }
+      v = list[base] == x;
+    }
+  }
+  return v != neg;
+}
+
+// The bits the atoms [ab, ab + an) set for one row (dwords w0 .. w3).
+__device__ __forceinline__ void atoms_eval(const LutAtom* atoms, const DevInstr* lits, uint32_t ab,
+                                           uint32_t an, bool nonnull, bool inwin, int64_t x,
+                                           uint32_t& w0, uint32_t& w1, uint32_t& w2, uint32_t& w3) {
+  for (uint32_t k = 0; k < an; ++k) {
+    const LutAtom A = atoms[ab + k];
+    bool any = false;
+    for (uint32_t l = 0; l < A.lit_count && !any; ++l) any = lit_true(lits[A.lit_begin + l], nonnull, inwin, x);
+    if (any != (A.kind == LA_SAT)) continue;
+    const uint32_t m = 1u << (A.bit & 31);
+    switch (A.bit >> 5) {
+      case 0: w0 |= m; break;
+      case 1: w1 |= m; break;
+      case 2: w2 |= m; break;
+      default: w3 |= m; break;
+    }
+  }
+}
+
+// Lookup tables of a launch, in device memory (one thread per entry).
+__global__ void __launch_bounds__(256) k_luts(LutArgs a) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.nentries; e += stride) {
+    uint32_t lo = 0, hi = a.nbuilds;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (a.builds[mid].entry_begin <= e) lo = mid; else hi = mid;
+    }
+    const LutBuild& B = a.builds[lo];
+    const LutCol& C = a.cols[B.col];
+    const uint32_t i = (uint32_t)(e - B.entry_begin);
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    bool zero = false, nonnull = true, inwin = true;
+    int64_t x = 0;
+    if (C.kind == LK_DIRECT) {
+      // 0: below the window, 1..n: values lo.., n+1: above, n+2: NULL, n+3: zero
+      if (i == 0 || i == C.n + 1) inwin = false;
+      else if (i == C.n + 2) nonnull = false;
+      else if (i == C.n + 3) zero = true;
+      else x = C.lo + (int64_t)(i - 1);
+    } else if (C.kind == LK_RANK) {
+      // 0..n: by rank, n+1: NULL, n+2: zero
+      if (i == C.n + 1) nonnull = false;
+      else if (i == C.n + 2) zero = true;
+      else x = a.reps[B.reps + i];
+    } else {  // LK_VALID: 0 non-NULL, 1 NULL
+      nonnull = i == 0;
+      inwin = false;
+    }
+    if (!zero) atoms_eval(a.atoms, a.lits, C.atom_begin, C.atom_count, nonnull, inwin, x, w0, w1, w2, w3);
+    uint32_t* dst = B.dst + (uint64_t)i * B.dwords;
+    dst[0] = w0;
+    if (B.dwords > 1) dst[1] = w1;
+    if (B.dwords > 2) {
+      dst[2] = w2;
+      dst[3] = w3;
+    }
+  }
+}
+
+// Values of one lane's rows of one column in an item: NR rows (NR/4 steps
+// of the tile's row mapping), at most 32 dwords: a segment's R rows of a
+// narrow column, or up to 16 rows of an int64 column (two items per 32-row
+// segment).
+struct LSeg { v4i w[8]; };
+
+template <int TY>
+__device__ __forceinline__ auto lget(const LSeg& r, int s, int i) {
+  if constexpr (TY == T_I8) {
+    return (int32_t)(int8_t)((uint32_t)r.w[s][0] >> (8 * i));
+  } else if constexpr (TY == T_I16) {
+    return (int32_t)(int16_t)((uint32_t)r.w[s][i >> 1] >> (16 * (i & 1)));
+  } else if constexpr (TY == T_I32) {
+    return (int32_t)r.w[s][i];
+  } else {
+    const v4i& q = r.w[2 * s + (i >> 1)];
+    const int k = 2 * (i & 1);
+    return (int64_t)(((uint64_t)(uint32_t)q[k + 1] << 32) | (uint32_t)q[k]);
+  }
+}
+
+// Buffer resource over rows [tb, min(tb + 2048, nrows)) of a column of
+// `width`-byte values: 32-bit offsets from the tile's start, and a read past
+// the table's last row returns zero without touching memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* data, uint64_t tb, uint64_t nrows,
+                                                            uint32_t width) {
+  const uint64_t rows = nrows - tb < (uint64_t)kTileRows ? nrows - tb : (uint64_t)kTileRows;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)((const char*)data + tb * width), (short)0,
+                                           (int)(rows * width), 0x00020000);
+}
+
+constexpr int kNt = 2;   // buffer-load cache policy: nontemporal (streamed once)
+
+// Issue the loads of steps j0 .. j0 + S - 1 of a tile (S = R / 4, at most 4
+// for an int64 column): wide loads on a full tile; on the partial last tile
+// one load per row, rows past the table reading zero.
+template <int R>
+__device__ __forceinline__ void lseg_issue(LSeg& r, const CONSTANT LutCol* C, uint64_t tb, uint64_t nrows,
+                                           bool full, int j0, uint32_t lane) {
+  constexpr int S = R / 4;
+  const uint32_t ty = C->type;
+  const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
+  const __amdgpu_buffer_rsrc_t rs = tile_rsrc(C->data, tb, nrows, width);
+  if (!full) {
+    const int SS = ty == T_I64 ? (S < 4 ? S : 4) : S;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      if (s >= SS) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const uint32_t off = (256u * (uint32_t)(j0 + s) + 4u * lane + (uint32_t)i) * width;
+        if (ty == T_I8) {
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, 0, 0);
+          if (i == 0) r.w[s][0] = 0;
+          r.w[s][0] |= (int32_t)((v & 0xFFu) << (8 * i));
+        } else if (ty == T_I16) {
+          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
+          if ((i & 1) == 0) r.w[s][i >> 1] = 0;
+          r.w[s][i >> 1] |= (int32_t)((v & 0xFFFFu) << (16 * (i & 1)));
+        } else if (ty == T_I32) {
+          r.w[s][i] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
+        } else {
+          const v2u v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+          r.w[2 * s + (i >> 1)][2 * (i & 1)] = (int32_t)v[0];
+          r.w[2 * s + (i >> 1)][2 * (i & 1) + 1] = (int32_t)v[1];
+        }
+      }
+    }
+    return;
+  }
+  switch (ty) {
+    case T_I8: {
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        r.w[s][0] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(4u * lane + 256u * (uint32_t)(j0 + s)), 0, kNt);
+      break;
+    }
+    case T_I16: {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const v2u x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(8u * lane + 512u * (uint32_t)(j0 + s)), 0, kNt);
+        r.w[s][0] = (int32_t)x[0];
+        r.w[s][1] = (int32_t)x[1];
+      }
+      break;
+    }
+    case T_I32: {
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(16u * lane + 1024u * (uint32_t)(j0 + s)), 0, kNt);
+        r.w[s] = (v4i)x;
+      }
+      break;
+    }
+    default: {
+#pragma unroll
+      for (int s = 0; s < (S < 4 ? S : 4); ++s) {
+        const uint32_t o = 32u * lane + 2048u * (uint32_t)(j0 + s);
+        r.w[2 * s] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, (int)o, 0, kNt);
+        r.w[2 * s + 1] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 16u), 0, kNt);
+      }
+      break;
+    }
+  }
+}
+
+// Validity of the segment's rows: bit 4 s + i = row (step j0 + s, i) is not
+// NULL (0 past nrows).
+template <int R>
+__device__ __forceinline__ uint32_t lseg_valid(const uint32_t* valid, uint64_t tb, int j0, uint32_t lane,
+                                               uint64_t nrows, bool full) {
+  constexpr int S = R / 4;
+  const GLOBAL uint32_t* vw = gptr<uint32_t>(valid) + tb / 32 + (lane >> 3) + 8 * j0;
+  const uint32_t sh = 4 * (lane & 7);
+  uint32_t V = 0;
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    if (full || tb + 256u * (uint32_t)(j0 + s) + 4u * lane < nrows) V |= ((vw[8 * s] >> sh) & 0xFu) << (4 * s);
+  return V;
+}
+
+template <int D>
+__device__ __forceinline__ void ent_or(const uint32_t* tab, uint32_t idx, uint32_t (&acc)[D]) {
+  if constexpr (D == 1) {
+    acc[0] |= tab[idx];
+  } else if constexpr (D == 2) {
+    const v2u e = ((const v2u*)tab)[idx];
+    acc[0] |= e[0];
+    acc[1] |= e[1];
+  } else {
+    const v4u e = ((const v4u*)tab)[idx];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) acc[d] |= e[d];
+  }
+}
+
+// Entry idx of a device-memory table through a buffer resource: a 32-bit
+// offset per lane instead of a 64-bit address, and an offset past the
+// table reads zero.
+template <int D>
+__device__ __forceinline__ void gent_or(__amdgpu_buffer_rsrc_t tab, uint32_t idx, uint32_t (&acc)[D]) {
+  if constexpr (D == 1) {
+    acc[0] |= __builtin_amdgcn_raw_buffer_load_b32(tab, (int)(idx * 4u), 0, 0);
+  } else if constexpr (D == 2) {
+    const v2u e = __builtin_amdgcn_raw_buffer_load_b64(tab, (int)(idx * 8u), 0, 0);
+    acc[0] |= e[0];
+    acc[1] |= e[1];
+  } else {
+    const v4u e = __builtin_amdgcn_raw_buffer_load_b128(tab, (int)(idx * 16u), 0, 0);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) acc[d] |= e[d];
+  }
+}
+
+// Buffer resource of a device table of `entries` D-dword entries (gfx9
+// raw buffer: stride 0, bounds checked against the byte size).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const uint32_t* tab, uint32_t entries, uint32_t dwords) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)tab, (short)0, (int)(entries * dwords * 4u), 0x00020000);
+}
+
+// Table indices of an item's rows to entries, ORed into the accumulators of
+// segment rows OFF .. OFF + NR - 1: from LDS, or from device memory where a
+// guarded table is read only on rows some program of the pass can still
+// count (the others read the zero entry).
+template <int D, int R, int NR, int OFF>
+__device__ __forceinline__ void lookup_or(const CONSTANT LutCol* C, const uint32_t* lds, uint32_t (&idx)[NR],
+                                          uint32_t zero, const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
+  if (C->lds_word != kNoLds) {
+    const uint32_t* tab = lds + C->lds_word;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) ent_or<D>(tab, idx[r], acc[OFF + r]);
+  } else {
+    const __amdgpu_buffer_rsrc_t tab = table_rsrc(C->gtab, zero + 1, D);
+    if (C->guard) {
+      // a row some program can still count: a failure bit (word 0 of a
+      // dword) still clear
+      uint32_t am[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const uint32_t g = (P->fold[d] >> 8) & 0xFFu;
+        am[d] = g >= 32 ? ~0u : (1u << g) - 1u;
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        uint32_t alive = 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) alive |= ~acc[OFF + r][d] & am[d];
+        idx[r] = alive ? idx[r] : zero;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) gent_or<D>(tab, idx[r], acc[OFF + r]);
+  }
+}
+
+// One column on one item: every row's entry ORed into its accumulator.  V
+// holds the validity of the segment's R rows.
+template <int D, int R, int TY, int NR, int OFF>
+__device__ __forceinline__ void lut_col(const LSeg& seg, const CONSTANT LutCol* C,
+                                        const LutArgs& a, uint32_t V, const uint32_t* lds,
+                                        const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
+  constexpr int S = NR / 4;
+  const uint32_t kind = C->kind, n = C->n;
+  const bool nullable = C->valid != nullptr;
+  uint32_t idx[NR];
+  if (kind == LK_DIRECT) {
+    const int64_t lo = C->lo;
+    if constexpr (TY != T_I64) {
+      // clamp to [lo - 1, lo + n] (inside the type), then offset: entry 0
+      // below the window, n + 1 above it
+      constexpr int64_t tmin = TY == T_I8 ? INT8_MIN : TY == T_I16 ? INT16_MIN : INT32_MIN;
+      constexpr int64_t tmax = TY == T_I8 ? INT8_MAX : TY == T_I16 ? INT16_MAX : INT32_MAX;
+      const int32_t cl = (int32_t)(lo - 1 < tmin ? tmin : lo - 1);
+      const int32_t ch = (int32_t)(lo + (int64_t)n > tmax ? tmax : lo + (int64_t)n);
+      const uint32_t base = (uint32_t)(lo - 1);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int32_t x = lget<TY>(seg, s, i);
+          idx[4 * s + i] = (uint32_t)min(max(x, cl), ch) - base;
+        }
+    } else {
+      const int64_t cl = lo == INT64_MIN ? lo : lo - 1;
+      const int64_t ch = lo + (int64_t)n;   // the planned window ends below INT64_MAX
+      const uint64_t base = (uint64_t)lo - 1u;
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t x = lget<TY>(seg, s, i);
+          const int64_t m = x < cl ? cl : x > ch ? ch : x;
+          idx[4 * s + i] = (uint32_t)((uint64_t)m - base);
+        }
+    }
+    if (nullable) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) idx[r] = (V >> (OFF + r)) & 1u ? idx[r] : n + 2;
+    }
+    lookup_or<D, R, NR, OFF>(C, lds, idx, n + 3, P, acc);
+  } else {  // LK_RANK: the number of bounds at or below the value
+    const CONSTANT int64_t* b = (const CONSTANT int64_t*)a.bounds + C->first;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) idx[r] = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+      const int64_t bk = b[k];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if constexpr (TY != T_I64) idx[4 * s + i] += lget<TY>(seg, s, i) >= (int32_t)bk ? 1u : 0u;
+          else idx[4 * s + i] += lget<TY>(seg, s, i) >= bk ? 1u : 0u;
+        }
+    }
+    if (nullable) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) idx[r] = (V >> (OFF + r)) & 1u ? idx[r] : n + 1;
+    }
+    lookup_or<D, R, NR, OFF>(C, lds, idx, n + 2, P, acc);
+  }
+}
+
+// Per-lane carry-save counters of T bits: planes of weight 1, 2, 4, 8 and
+// a vertical counter of weight 16 * 2^k (at most 2047 per bit position
+// between reads).
+constexpr int kHsLevels = 7;
+struct Hs {
+  uint32_t ones, twos, fours, eights;
+  uint32_t h[kHsLevels];
+};
+
+__device__ __forceinline__ void csa(uint32_t& carry, uint32_t& sum, uint32_t a, uint32_t b, uint32_t c) {
+  const uint32_t u = a ^ b;
+  carry = (a & b) | (u & c);
+  sum = u ^ c;
+}
+
+__device__ __forceinline__ void hs_sixteens(Hs& s, uint32_t c) {
+#pragma unroll
+  for (int k = 0; k < kHsLevels; ++k) {
+    const uint32_t t = s.h[k] & c;
+    s.h[k] ^= c;
+    c = t;
+  }
+}
+
+// Add NW words (NW = 1, 2, 4 or a multiple of 8), each bit position counting 0 or 1.
+template <int NW>
+__device__ __forceinline__ void hs_add(Hs& s, const uint32_t* w) {
+  if constexpr (NW == 1) {
+    const uint32_t t = s.ones & w[0];
+    s.ones ^= w[0];
+    const uint32_t f = s.twos & t;
+    s.twos ^= t;
+    const uint32_t e = s.fours & f;
+    s.fours ^= f;
+    const uint32_t c = s.eights & e;
+    s.eights ^= e;
+    hs_sixteens(s, c);
+  } else if constexpr (NW > 8) {
+    static_assert(NW % 8 == 0, "blocks of eight words");
+#pragma unroll
+    for (int k = 0; k < NW; k += 8) hs_add<8>(s, w + k);
+  } else if constexpr (NW == 8) {
+    uint32_t ta, tb, fa, fb, e;
+    csa(ta, s.ones, s.ones, w[0], w[1]);
+    csa(tb, s.ones, s.ones, w[2], w[3]);
+    csa(fa, s.twos, s.twos, ta, tb);
+    csa(ta, s.ones, s.ones, w[4], w[5]);
+    csa(tb, s.ones, s.ones, w[6], w[7]);
+    csa(fb, s.twos, s.twos, ta, tb);
+    csa(e, s.fours, s.fours, fa, fb);
+    const uint32_t c = s.eights & e;
+    s.eights ^= e;
+    hs_sixteens(s, c);
+  } else if constexpr (NW == 4) {
+    uint32_t ta, tb, f;
+    csa(ta, s.ones, s.ones, w[0], w[1]);
+    csa(tb, s.ones, s.ones, w[2], w[3]);
+    csa(f, s.twos, s.twos, ta, tb);
+    const uint32_t e = s.fours & f;
+    s.fours ^= f;
+    const uint32_t c = s.eights & e;
+    s.eights ^= e;
+    hs_sixteens(s, c);
+  } else {
+    static_assert(NW == 2, "one, two, four or a multiple of eight words");
+    uint32_t t;
+    csa(t, s.ones, s.ones, w[0], w[1]);
+    const uint32_t f = s.twos & t;
+    s.twos ^= t;
+    const uint32_t e = s.fours & f;
+    s.fours ^= f;
+    const uint32_t c = s.eights & e;
+    s.eights ^= e;
+    hs_sixteens(s, c);
+  }
+}
+
+// Rows' accumulators to their T words (bit p: program p counts the row),
+// packed 32 / B rows to a word, into the counters.  Within dword d, word 0
+// is inverted and the b_d-bit words are ANDed together by folding.
+template <int D, int R>
+__device__ __forceinline__ void lut_count(uint32_t (&acc)[R][D], const CONSTANT LutPass* P, uint32_t inr,
+                                          Hs& hs) {
+  const uint32_t B = P->bits;
+  uint32_t nm[D], gm[D], ps[D], bw[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const uint32_t f = P->fold[d];
+    bw[d] = f & 0xFFu;
+    const uint32_t g = (f >> 8) & 0xFFu;
+    ps[d] = f >> 16;
+    nm[d] = bw[d] >= 32 ? ~0u : (1u << bw[d]) - 1u;
+    gm[d] = g >= 32 ? ~0u : (1u << g) - 1u;
+  }
+  uint32_t T[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    uint32_t res = 0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      uint32_t t = acc[r][d] ^ nm[d];
+      if (bw[d] <= 16) t &= t >> 16;
+      if (bw[d] <= 8) t &= t >> 8;
+      if (bw[d] <= 4) t &= t >> 4;
+      res |= (t & gm[d]) << ps[d];
+    }
+    T[r] = (inr >> r) & 1u ? res : 0u;
+  }
+  if (B == 32) {
+    hs_add<R>(hs, T);
+  } else if (B == 16) {
+    uint32_t w[R / 2];
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) w[k] = T[2 * k] | (T[2 * k + 1] << 16);
+    hs_add<R / 2>(hs, w);
+  } else {
+    uint32_t w[R / 4];
+#pragma unroll
+    for (int k = 0; k < R / 4; ++k)
+      w[k] = T[4 * k] | (T[4 * k + 1] << 8) | (T[4 * k + 2] << 16) | (T[4 * k + 3] << 24);
+    hs_add<R / 4>(hs, w);
+  }
+}
+
+// Reads the counters out (wave-wide bit counts per position), adds each
+// program's count to its LDS counter or accumulator line, and clears them.
+// Program p's rows are counted at bit positions p, p + B, ... of the words.
+__device__ __forceinline__ void hs_flush(Hs& s, const CONSTANT LutPass* P, unsigned long long* gacc,
+                         const uint32_t* acc_index, uint32_t* accl, uint32_t nacc, uint32_t lane) {
+  uint32_t planes[4 + kHsLevels] = {s.ones, s.twos, s.fours, s.eights};
+#pragma unroll
+  for (int k = 0; k < kHsLevels; ++k) planes[4 + k] = s.h[k];
+  uint32_t used = 0;   // planes with a bit set in some lane
+#pragma unroll
+  for (int k = 0; k < 4 + kHsLevels; ++k) used |= (__ballot(planes[k] != 0u) != 0ull ? 1u : 0u) << k;
+  const uint32_t B = P->bits, pb = P->prog_begin, pn = P->prog_count;
+  for (uint32_t p = 0; p < pn; ++p) {
+    uint32_t c = 0;
+    for (uint32_t q = p; q < 32; q += B) {
+#pragma unroll
+      for (int k = 0; k < 4 + kHsLevels; ++k)
+        if ((used >> k) & 1u) c += (uint32_t)__popcll(__ballot((planes[k] >> q) & 1u)) << k;
+    }
+    if (lane == 0 && c) {
+      if (pb + p < nacc) atomicAdd(&accl[pb + p], c);
+      else atomicAdd(&gacc[(uint64_t)acc_index[pb + p] * kBatchAccStride], (unsigned long long)c);
+    }
+  }
+  s = Hs{};
+}
+
+// Start of a segment: accumulators to the pass's initial value, the rows in
+// range (partial tile), and the columns that only null tests read (no
+// data), which come last in the pass.
+template <int D, int R>
+__device__ __forceinline__ void lut_start(const CONSTANT LutPass* P, const CONSTANT LutCol* cols,
+                                          uint64_t tb, bool full, int seg, uint32_t lane,
+                                          uint32_t (&acc)[R][D], uint32_t& inr) {
+  constexpr int S = R / 4;
+  const uint64_t nrows = P->nrows;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const uint32_t v = P->init[d];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r][d] = v;
+  }
+  inr = ~0u;
+  if (!full) {
+    inr = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      inr |= (uint32_t)(tb + 256u * (uint32_t)(seg * S + (r >> 2)) + 4u * lane + (uint32_t)(r & 3) < nrows) << r;
+  }
+  const uint32_t cb = P->col_begin, cn = P->col_count;
+  for (uint32_t c = P->ndata; c < cn; ++c) {
+    const CONSTANT LutCol* C = cols + cb + c;
+    const uint32_t V = lseg_valid<R>(C->valid, tb, seg * S, lane, nrows, full);
+    const CONSTANT uint32_t* e = (const CONSTANT uint32_t*)C->gtab;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const uint32_t e0 = e[d], e1 = e[D + d];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r][d] |= (V >> r) & 1u ? e0 : e1;
+    }
+  }
+}
+
+// Items of a segment: one per data column, two for an int64 column when a
+// segment has 32 rows (16 rows each).
+template <int R>
+__device__ __forceinline__ uint32_t parts_of(const CONSTANT LutCol* C) {
+  return R == 32 && C->type == T_I64 ? 2u : 1u;
+}
+
+template <int R>
+__device__ __forceinline__ void lut_issue(LSeg& buf, const CONSTANT LutPass* P,
+                                          const CONSTANT LutCol* cols, uint64_t tb, bool full,
+                                          uint32_t seg, uint32_t c, uint32_t part, uint32_t lane) {
+  const CONSTANT LutCol* C = cols + P->col_begin + c;
+  const int j0 = (int)(seg * (R / 4) + 4 * part);
+  lseg_issue<R>(buf, C, tb, P->nrows, full, j0, lane);
+}
+
+template <int D, int R>
+__device__ __forceinline__ void lut_step(const LSeg& buf, const CONSTANT LutPass* P,
+                                         const CONSTANT LutCol* cols, const LutArgs& a, uint64_t tb,
+                                         bool full, uint32_t seg, uint32_t c, uint32_t part,
+                                         uint32_t lane, const uint32_t* lds, uint32_t (&acc)[R][D],
+                                         uint32_t V) {
+  const CONSTANT LutCol* C = cols + P->col_begin + c;
+  switch (C->type) {
+    case T_I8: lut_col<D, R, T_I8, R, 0>(buf, C, a, V, lds, P, acc); break;
+    case T_I16: lut_col<D, R, T_I16, R, 0>(buf, C, a, V, lds, P, acc); break;
+    case T_I32: lut_col<D, R, T_I32, R, 0>(buf, C, a, V, lds, P, acc); break;
+    default:
+      if (part == 0) lut_col<D, R, T_I64, (R < 16 ? R : 16), 0>(buf, C, a, V, lds, P, acc);
+      else if constexpr (R == 32) lut_col<D, R, T_I64, 16, 16>(buf, C, a, V, lds, P, acc);
+      break;
+  }
+}
+
+// Every column of a pass on one tile: per segment of R rows, each column's
+// rows are loaded (all their loads in flight together, as one item) and
+// looked up; other waves hide the latency, as in the count scan.
+template <int D, int R>
+__device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTANT LutCol* cols,
+                                         const LutArgs& a, uint64_t tb, uint32_t lane,
+                                         const uint32_t* lds, Hs& hs) {
+  constexpr int NSEG = kSteps / (R / 4);
+  const uint32_t nd = P->ndata;   // columns with data
+  const bool full = tb + kTileRows <= P->nrows;
+  const CONSTANT LutCol* cb = cols + P->col_begin;
+  uint32_t acc[R][D];
+  uint32_t inr;
+  for (int seg = 0; seg < NSEG; ++seg) {
+    lut_start<D, R>(P, cols, tb, full, seg, lane, acc, inr);
+    for (uint32_t c = 0; c < nd; ++c) {
+      const CONSTANT LutCol* C = cb + c;
+      const uint32_t V = C->valid ? lseg_valid<R>(C->valid, tb, seg * (R / 4), lane, P->nrows, full) : ~0u;
+      const uint32_t np = parts_of<R>(C);
+      for (uint32_t part = 0; part < np; ++part) {
+        LSeg x;
+        lut_issue<R>(x, P, cols, tb, full, (uint32_t)seg, c, part, lane);
+        lut_step<D, R>(x, P, cols, a, tb, full, (uint32_t)seg, c, part, lane, lds, acc, V);
+      }
+    }
+    lut_count<D, R>(acc, P, inr, hs);
+  }
+}
+
+// Per workgroup, per-program counts accumulate in LDS and go to the
+// accumulator lines at the end, as in k_batch; the last workgroup by ticket
+// moves the finished lines out.  The workgroup takes groups of nw tiles
+// (pass ranges are padded to kLutTileAlign), and copies a pass's LDS tables
+// from device memory when it moves to that pass.
+template <int D, int R>
+__global__ void __launch_bounds__(768) k_lbatch(LutArgs a) {
+  extern __shared__ uint32_t dyn[];
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t nw = blockDim.x >> 6;
+  const uint32_t nacc = a.acc_words;
+  uint32_t* accl = dyn;
+  uint32_t* lds = dyn + nacc;
+  for (uint32_t p = threadIdx.x; p < nacc; p += blockDim.x) accl[p] = 0;
+  __syncthreads();
+  const CONSTANT LutPass* passes = (const CONSTANT LutPass*)a.passes;
+  const CONSTANT LutCol* cols = (const CONSTANT LutCol*)a.cols;
+  const uint64_t ngroups = a.total_tiles / nw;
+  uint32_t staged = 0xFFFFFFFFu;
+  const CONSTANT LutPass* P = nullptr;
+  Hs hs{};
+  uint32_t since = 0;
+  for (uint64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const uint64_t flat = g * nw + wave;
+    uint32_t lo = 0, hi = a.npasses;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (passes[mid].tile_begin <= flat) lo = mid; else hi = mid;
+    }
+    lo = uni(lo);
+    if (passes[lo].dwords != (uint32_t)D) continue;   // another launch's pass
+    if (lo != staged) {
+      if (P) {
+        hs_flush(hs, P, a.acc, a.acc_index, accl, nacc, lane);
+        since = 0;
+      }
+      P = passes + lo;
+      __syncthreads();
+      for (uint32_t c = 0; c < P->col_count; ++c) {
+        const CONSTANT LutCol* C = cols + P->col_begin + c;
+        if (C->lds_word == kNoLds) continue;
+        const uint32_t entries = C->kind == LK_DIRECT ? C->n + 4 : C->n + 3;
+        const uint32_t words = entries * P->dwords;
+        const GLOBAL uint32_t* src = gptr<uint32_t>(C->gtab);
+        uint32_t* dst = lds + C->lds_word;
+        for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+      }
+      __syncthreads();
+      staged = lo;
+    }
+    const uint64_t local = flat - P->tile_begin;
+    if (local >= P->ntiles) continue;   // padding
+    const uint64_t tb = P->row_begin + local * kTileRows;
+    lut_tile<D, R>(P, cols, a, tb, lane, lds, hs);
+    if (++since == kLutFlushTiles) {
+      hs_flush(hs, P, a.acc, a.acc_index, accl, nacc, lane);
+      since = 0;
+    }
+  }
+  if (P) hs_flush(hs, P, a.acc, a.acc_index, accl, nacc, lane);
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < nacc && p < a.nprogs; p += blockDim.x)
+    if (accl[p]) atomicAdd(&a.acc[(uint64_t)a.acc_index[p] * kBatchAccStride], (unsigned long long)accl[p]);
+  __threadfence();
+  __syncthreads();
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    const unsigned int ticket = atomicAdd(&a.slot->ticket, 1u);
+    last = ticket == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    for (uint32_t k = threadIdx.x; k < a.ndone; k += blockDim.x) {
+      const uint64_t line = a.done ? a.done[k] : k;
+      a.out[k] = atomicExch(&a.acc[line * kBatchAccStride], 0ull);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) atomicExch(&a.slot->ticket, 0u);
+  }
+}
+
 __global__ void k_fill(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -1467,4 +2236,38 @@ int sel_launch_batch(const BatchArgs& a, uint32_t grid, uint32_t block, uint32_t
 
 int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
   return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch, block, lds_bytes);
+}
+
+int sel_launch_luts(const LutArgs& a, void* stream) {
+  if (a.nbuilds == 0 || a.nentries == 0) return 0;
+  uint64_t blocks = (a.nentries + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_luts, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+// The lookup-table kernel for passes of `dwords` accumulator dwords per row,
+// with `rows` rows per lane per segment (the larger choice, or half of it).
+namespace {
+const void* lbatch_kernel(uint32_t dwords, bool fewer_rows) {
+  switch (dwords) {
+    case 1: return fewer_rows ? (const void*)k_lbatch<1, 8> : (const void*)k_lbatch<1, 16>;
+    case 2: return fewer_rows ? (const void*)k_lbatch<2, 4> : (const void*)k_lbatch<2, 8>;
+    default: return fewer_rows ? (const void*)k_lbatch<4, 4> : (const void*)k_lbatch<4, 8>;
+  }
+}
+}  // namespace
+
+int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t fewer_rows, uint32_t grid, uint32_t block,
+                      uint32_t lds_bytes, void* stream) {
+  LutArgs args = a;
+  void* kargs[] = {&args};
+  return (int)hipLaunchKernel(lbatch_kernel(dwords, fewer_rows != 0), dim3(grid), dim3(block), kargs, lds_bytes,
+                              (hipStream_t)stream);
+}
+
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t fewer_rows, uint32_t block, uint32_t lds_bytes,
+                         int* blocks_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lbatch_kernel(dwords, fewer_rows != 0),
+                                                           block, lds_bytes);
 }

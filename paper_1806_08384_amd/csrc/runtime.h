@@ -131,6 +131,8 @@ struct sel_program {
   bool own_alloc = false;           // or its own hipMalloc if the arena is full
   DevInstr* dcode = nullptr;
   std::vector<DevInstr> host_code;  // with device pointers (for star programs)
+  std::vector<uint8_t> host_blob;   // host copy of the constants (IN lists, bitmaps)
+  uintptr_t blob_dev = 0;           // their device address
   const sel::BatchBitmap* dstage = nullptr;   // bitmaps a scan stages in LDS
   uint32_t nstage = 0, stage_words = 0;
   uint32_t nins = 0;
@@ -200,12 +202,48 @@ sel_status pushdown_rowids_with(sel_ctx* ctx, const sel_table* table, const sel_
                                 uint64_t max_rows, uint32_t* d_out, uint64_t cap,
                                 uint64_t* out_count, char* sp, bool timed);
 
+// Descriptors of the batched count over per-column lookup tables of program
+// bits (k_luts, k_lbatch): passes of up to 32 programs in conjunctive form.
+struct LutPlan {
+  std::vector<sel::LutPass> passes;
+  std::vector<sel::LutCol> cols;       // gtab holds a word offset until written
+  std::vector<sel::LutAtom> atoms;
+  std::vector<DevInstr> lits;
+  std::vector<int64_t> bounds, reps;
+  std::vector<uint32_t> acc_index;     // per program: its accumulator line
+  std::vector<sel::LutBuild> builds;   // dst holds a word offset until written
+  uint64_t gtab_words = 0;             // tables in device memory, in words
+  uint64_t nentries = 0;
+  uint64_t total_tiles = 0;
+  uint32_t max_lds_words = 0;
+  void clear();
+  bool empty() const { return passes.empty(); }
+  // Passes over rows [row_begin, row_end) of t for the programs it can
+  // express; returns the indices (into prg) of the others.
+  std::vector<uint32_t> add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
+                            const sel_program* const* prg, const uint32_t* acc, uint32_t n);
+  size_t bytes() const;
+  void write(uint8_t* host, char* dev, uint32_t* gtab_dev, sel::LutArgs& a) const;
+  uint32_t acc_words() const {
+    return ((uint32_t)std::min<size_t>(acc_index.size(), (size_t)sel::kBatchMaxProgs) + 3u) & ~3u;
+  }
+  uint32_t lds_bytes() const { return 4u * (acc_words() + max_lds_words); }
+};
+
 // Descriptors of one leaf-major batched launch (k_batch).  add() appends
 // passes over rows [row_begin, row_end) of a table for a list of programs;
 // a pass holds as many programs as fit kBatchSlots LDS slots (deduplicated
 // leaf words plus validity words; a single larger program gets a pass of its
 // own), so each pass reads its columns once.
 struct BatchPlan {
+  // programs in conjunctive form go to the lookup-table kernel, the others
+  // to the leaf-major one; both add into the same accumulator lines
+  LutPlan lut;
+  bool allow_lut = false;                // set by the caller before add()
+  mutable sel::LutArgs largs{};          // as written
+  uint32_t num_cus = 256;
+  uint32_t lut_block = 0, lut_grid = 0;  // 0: the defaults
+  uint32_t lut_fewer_rows = 0;           // 1: half the rows per lane per segment
   std::vector<sel::BatchTable> entries;
   std::vector<sel::BatchCol> cols;
   std::vector<DevInstr> leaves;
@@ -214,7 +252,7 @@ struct BatchPlan {
   std::vector<sel::BatchBitmap> bms;
   std::vector<uint64_t> col_gtab;        // per column: word offset of its device table, or ~0
   std::vector<sel::TableBuild> builds;   // dst / leaves hold offsets until written
-  uint64_t gtab_words = 0;               // device-memory tables, in words
+  uint64_t gtab_words = 0;               // device-memory tables of k_batch, in words
   uint64_t table_entries = 0;            // entries k_tables writes
   uint64_t total_tiles = 0;
   uint32_t max_slots = 0;
@@ -224,15 +262,21 @@ struct BatchPlan {
   void add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
            const sel_program* const* progs, const uint32_t* acc, uint32_t n);
   size_t bytes() const;
+  // Device-memory tables of both kernels, in words.
+  uint64_t gtab_total() const { return gtab_words + lut.gtab_words; }
   // Image of the descriptors for device address `dev` into `host` (bytes()
-  // long), with the device tables at gtab_dev (gtab_words words); sets the
-  // descriptor pointers and counts of `a` and the device address of the
-  // table builds.
+  // long), with the device tables at gtab_dev (gtab_total() words); sets
+  // the descriptor pointers and counts of `a` (and of largs) and the device
+  // address of the table builds.
   void write(uint8_t* host, char* dev, uint32_t* gtab_dev, sel::BatchArgs& a,
              const sel::TableBuild** d_builds) const;
-  // Enqueue the table builds (if any) and the batch kernel.
+  // Enqueue the table builds (if any) and the batch kernels: the lookup-table
+  // kernel (its own launch shape) first, then k_batch (grid x block); the
+  // last of them moves the finished accumulator lines out.
   int launch(const sel::BatchArgs& a, const sel::TableBuild* d_builds, uint32_t grid,
              uint32_t block, void* stream) const;
+  // Launch shape of the lookup-table kernel.
+  void lut_shape(uint32_t& grid, uint32_t& block) const;
   uint32_t acc_words() const {
     return (uint32_t)std::min<size_t>(progs.size(), (size_t)sel::kBatchMaxProgs);
   }

@@ -319,6 +319,114 @@ struct BatchArgs {
   DevSlot* slot;
 };
 
+// ---- batched count over per-column lookup tables of program bits ---------
+// A pass holds up to 32 programs whose predicates are conjunctions of
+// clauses (ORs of possibly negated leaf tests and null tests): the CNF of
+// the program once NOTs are pushed down to the leaves (exact in three-valued
+// logic; a row counts when every clause is TRUE).  A row's accumulator is D
+// dwords (D = 1, 2 or 4); dword d holds the programs pos_d .. pos_d + G_d - 1
+// of the pass, in words of b_d bits (b_d = 32, 16, 8 or 4; G_d <= b_d):
+//   word 0 (NA):  bit g set when a clause of program pos_d + g whose
+//                 literals all test one column is FALSE or UNKNOWN;
+//   word k >= 1:  bit g set when that program's k-th clause spanning
+//                 several columns has a TRUE literal (bits of absent
+//                 clauses start at 1).
+// Every word is combined by OR over the pass's columns, so a column
+// contributes one D-dword entry per row: the bits its value (or NULL) sets.
+// Program pos_d + g counts the row when bit g of ~NA & word1 & word2 ... is
+// set (folded within the dword), and each row's program bits T are added
+// into per-lane carry-save bit-plane counters, read out every few dozen
+// tiles.
+enum LutKind : uint32_t {
+  LK_DIRECT = 0,   // entry min(max(x, lo-1), lo+n) - lo + 1; n+2 NULL, n+3 zero
+  LK_RANK = 1,     // entry #{k : x >= bound[k]} (n bounds); n+1 NULL, n+2 zero
+  LK_VALID = 2     // entry 0 non-NULL, entry 1 NULL (the column's data is not read)
+};
+
+// One bit a column sets: for a FAIL atom when none of its literals is TRUE
+// (a single-column clause), for a SAT atom when one is (that column's
+// literals of a multi-column clause).
+enum LutAtomKind : uint32_t { LA_FAIL = 0, LA_SAT = 1 };
+struct LutAtom {             // 16 bytes
+  uint32_t lit_begin;        // literals: DevInstr with flags = kLitNeg or 0
+  uint32_t lit_count;
+  uint32_t kind;             // LutAtomKind
+  uint32_t bit;              // bit index in the entry's D dwords (dword = bit / 32)
+};
+constexpr uint32_t kLitNeg = 1;   // DevInstr::flags of a negated literal
+
+struct LutCol {              // 64 bytes
+  const void* data;          // values (nullptr for LK_VALID)
+  const uint32_t* valid;     // validity words, nullptr: no NULLs
+  uint32_t type;             // DevType
+  uint32_t kind;             // LutKind
+  int64_t lo;                // LK_DIRECT: value of entry 1
+  uint32_t n;                // LK_DIRECT: window size; LK_RANK: bounds
+  uint32_t lds_word;         // table at this LDS word offset, or kNoLds (device memory)
+  const uint32_t* gtab;      // the table in device memory (built by k_luts)
+  uint32_t first;            // LK_RANK: first bound
+  uint32_t atom_count;       // atoms of the column (table build)
+  uint32_t atom_begin;
+  uint32_t guard;            // device table: rows no program still needs read the zero entry
+};
+
+struct LutPass {             // 112 bytes: one pass over a table or a chunk of it
+  uint64_t nrows;            // rows of the whole table
+  uint64_t tile_begin;       // first flat tile index (ranges padded to kLutTileAlign)
+  uint64_t row_begin;        // first row (a multiple of kTileRows)
+  uint64_t ntiles;
+  uint32_t col_begin, col_count;
+  uint32_t prog_begin, prog_count;   // programs own bits 0 .. prog_count-1
+  uint32_t bits;             // bits of T per row in the counters: 8, 16 or 32
+  uint32_t dwords;           // D
+  uint32_t lds_words;        // LDS words of the pass's staged tables
+  uint32_t pmask;            // bits of T that are programs
+  uint32_t init[4];          // accumulator start value per dword
+  uint32_t fold[4];          // per dword: b_d | G_d << 8 | pos_d << 16 (G_d = 0: unused)
+  uint32_t ndata;            // columns with data (the first ones); validity-only ones follow
+  uint32_t pad[3];
+};
+static_assert(sizeof(LutPass) == 112, "LutPass layout");
+
+// Table build: entry e of column `col` (e < nentries) at dst + e * dwords.
+struct LutBuild {            // 40 bytes
+  uint32_t* dst;
+  uint64_t entry_begin;      // in the launch's flat entry range
+  uint32_t col;              // into the LutCol array
+  uint32_t nentries;
+  uint32_t dwords;
+  uint32_t reps;             // LK_RANK: first representative value (int64 array)
+  uint32_t pad[2];
+};
+
+constexpr uint32_t kLutTileAlign = 48;   // waves of a workgroup: 1, 2, 3, 4, 6, 8, 12 or 16
+constexpr uint32_t kLutBlock = 768;      // default workgroup: twelve waves, one per CU (its LDS)
+constexpr uint64_t kLutMaxRows = 64ull << 20;   // longest chunk given to the lookup-table kernel
+constexpr uint32_t kLutFlushTiles = 48;  // tiles between reads of the bit-plane counters
+
+struct LutArgs {
+  const LutPass* passes;
+  const LutCol* cols;
+  const LutAtom* atoms;
+  const DevInstr* lits;
+  const int64_t* bounds;     // LK_RANK bounds (int64, ascending per column)
+  const int64_t* reps;       // LK_RANK representative values, one per rank
+  const uint32_t* acc_index; // per program of the launch: its accumulator line
+  const LutBuild* builds;
+  uint32_t npasses;
+  uint32_t nprogs;
+  uint32_t nbuilds;
+  uint32_t acc_words;        // LDS counters: min(nprogs, kBatchMaxProgs)
+  uint64_t nentries;         // table entries k_luts writes
+  uint64_t total_tiles;      // a multiple of kLutTileAlign
+  unsigned long long* acc;   // accumulator lines (kBatchAccStride u64 each)
+  const uint32_t* done;      // as BatchArgs
+  uint32_t ndone;
+  uint32_t pad;
+  unsigned long long* out;
+  DevSlot* slot;
+};
+
 }  // namespace sel
 
 // Launchers implemented in kernels.hip (return hipError_t as int).
@@ -338,4 +446,12 @@ int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu);
 int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, uint32_t lds_bytes,
                      void* stream);
 int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
+// Table builds, then the lookup-table batch kernel over the passes with
+// `dwords` accumulator dwords per row (16 rows per lane per segment with
+// one dword, 8 with two or four; half of that with fewer_rows).
+int sel_launch_luts(const sel::LutArgs& a, void* stream);
+int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t fewer_rows, uint32_t grid,
+                      uint32_t block, uint32_t lds_bytes, void* stream);
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t fewer_rows, uint32_t block, uint32_t lds_bytes,
+                         int* blocks_per_cu);
 }

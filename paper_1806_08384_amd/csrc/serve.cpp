@@ -21,6 +21,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -118,6 +119,7 @@ struct sel_server {
   uint64_t submitted = 0, completed = 0, rejected = 0, rounds = 0, round_programs = 0,
            shared_rounds = 0, round_groups = 0;
   double round_gpu_ms = 0, round_host_ms = 0;
+  double round_bytes = 0;                   // algorithmic bytes the rounds read
   uint32_t max_admitted = 0;
   std::vector<double> latencies;
   Clock::time_point t_first{}, t_last{};
@@ -242,6 +244,21 @@ bool wait_oldest(sel_server* s) {
   return true;
 }
 
+// Bytes per row the programs read together: the element size of every
+// column one of them tests, plus 1/8 for every validity bitmap one reads.
+double union_bytes_per_row(const std::vector<const sel_program*>& ps) {
+  std::set<const void*> data, valid;
+  double b = 0;
+  for (const sel_program* p : ps)
+    for (const DevInstr& I : p->host_code) {
+      const bool value = I.op == D_RANGE || I.op == D_BITMAP || I.op == D_INLIST;
+      if (value && I.data && data.insert(I.data).second) b += type_bytes(I.type);
+      if ((value || (I.op >= D_NN_TRUE && I.op <= D_NOTNULL)) && I.valid && valid.insert(I.valid).second)
+        b += 1.0 / 8.0;
+    }
+  return b;
+}
+
 // Build and launch one round; returns false if there was nothing to do.
 // Identical programs (the same compiled program on the same table) attached
 // by different requests are evaluated once per chunk; their chunk count is
@@ -251,12 +268,18 @@ bool launch_round(sel_server* s) {
   RoundSlot& rs = s->slots[s->next_slot];
   BatchPlan& bp = rs.plan;
   bp.clear();
+  bp.num_cus = s->ctx->num_cus;
   uint32_t ngroups = 0;
   std::vector<hipEvent_t> waits;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     std::vector<const sel_program*> gp;
     std::vector<uint32_t> gacc;
+    // the lookup-table kernel when every chunk of the round is short (see
+    // BatchPlan::add)
+    bp.allow_lut = true;
+    for (auto& kv : s->tables)
+      if (!kv.second.progs.empty()) bp.allow_lut &= kv.second.chunk_rows <= kLutMaxRows;
     for (auto& kv : s->tables) {
       TableState& ts = kv.second;
       if (ts.progs.empty()) continue;
@@ -284,6 +307,7 @@ bool launch_round(sel_server* s) {
       }
       // an empty chunk adds no tile; its programs still finish (count 0)
       bp.add(ts.table, row_begin, row_end, gp.data(), gacc.data(), (uint32_t)gp.size());
+      s->round_bytes += (double)(row_end - row_begin) * union_bytes_per_row(gp);
       ts.progs.erase(std::remove_if(ts.progs.begin(), ts.progs.end(),
                                     [](const Active& a) { return a.chunks_left == 0; }),
                      ts.progs.end());
@@ -314,7 +338,7 @@ bool launch_round(sel_server* s) {
   auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
   const size_t o_out = up(bp.bytes());
   const size_t o_gtab = up(o_out + (size_t)ngroups * 8);
-  const size_t need_dev = o_gtab + bp.gtab_words * 4;
+  const size_t need_dev = o_gtab + bp.gtab_total() * 4;
   if (need_dev > rs.dev_bytes) {
     if (rs.dev) (void)hipFree(rs.dev);
     rs.dev = nullptr;
@@ -619,6 +643,7 @@ sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset)
   out->round_groups = s->round_groups;
   out->round_gpu_ms = s->round_gpu_ms;
   out->round_host_ms = s->round_host_ms;
+  out->round_bytes = s->round_bytes;
   std::vector<double> v = s->latencies;
   if (!v.empty()) {
     std::sort(v.begin(), v.end());
@@ -638,6 +663,7 @@ sel_status sel_server_get_stats(sel_server* s, sel_server_stats* out, int reset)
     s->submitted = s->completed = s->rejected = s->rounds = s->round_programs = s->shared_rounds = 0;
     s->round_groups = 0;
     s->round_gpu_ms = s->round_host_ms = 0;
+    s->round_bytes = 0;
     s->max_admitted = s->admitted;
     s->latencies.clear();
     s->any = false;

@@ -101,7 +101,8 @@ class sel_server_stats(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("elapsed_s", ctypes.c_double), ("round_groups", ctypes.c_uint64),
-                ("round_gpu_ms", ctypes.c_double), ("round_host_ms", ctypes.c_double)]
+                ("round_gpu_ms", ctypes.c_double), ("round_host_ms", ctypes.c_double),
+                ("round_bytes", ctypes.c_double)]
 
 
 class sel_timing(ctypes.Structure):

@@ -1,5 +1,11 @@
 """GPU: batched counts (one persistent launch, eager and graph-replayed)
-equal the plain counts and the oracle, bit-exactly."""
+equal the plain counts and the oracle, bit-exactly.  Every test runs three
+times: with the lookup-table kernel taking every program in conjunctive
+form (SEL_BATCH_KERNEL=lut; the rest, e.g. with IS UNKNOWN, in the
+leaf-major kernel of the same launch), with the leaf-major kernel alone
+(SEL_BATCH_KERNEL=leaf), and with the default split by chunk length."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,6 +16,21 @@ from tests.gpu_common import UINT64_MAX, as_u32, ids_tensor, say
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True, params=["lut", "leaf", "default"])
+def batch_kernel(request):
+    old = os.environ.get("SEL_BATCH_KERNEL")
+    if request.param == "default":
+        os.environ.pop("SEL_BATCH_KERNEL", None)
+    else:
+        os.environ["SEL_BATCH_KERNEL"] = request.param
+    say(f"batch kernel: {request.param}")
+    yield request.param
+    if old is None:
+        os.environ.pop("SEL_BATCH_KERNEL", None)
+    else:
+        os.environ["SEL_BATCH_KERNEL"] = old
 
 
 @pytest.fixture(scope="module")

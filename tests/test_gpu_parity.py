@@ -114,6 +114,36 @@ def test_random_programs_small_ranges(sel, ctx):
         check_tree(sel, ctx, dt, orc, tree, ids=(k % 3 == 0))
 
 
+@pytest.mark.parametrize("k", [10, 100, 1000, 3000])
+def test_sparse_in_lists(sel, ctx, k):
+    """IN lists too sparse for a bitmap (the compiler keeps them as sorted
+    lists): k values drawn from the column plus as many absent ones, on an
+    int64 log-normal column with NULLs, an int32 and an int8 column, over a
+    ragged 1 000 003-row table; lists up to 4095 values are searched in the
+    scan's LDS copy, the 6000-value lists in device memory.
+    Counts and ids equal the oracle; alone, under NOT and inside an AND."""
+    say(f"sparse IN lists k={k}")
+    rng = np.random.default_rng(90_000 + k)
+    t = datagen.cfg2(n=1_000_003, seed=91)
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    price = t.col("price").data
+    date = t.col("date").data
+
+    def pick(col, absent_lo, absent_hi):
+        present = rng.choice(col, k, replace=False)
+        absent = rng.integers(absent_lo, absent_hi, k)
+        return tuple(int(v) for v in np.concatenate([present, absent]))
+
+    trees = [("in", 3, pick(price, 10**7, 10**8)),
+             ("not", ("in", 3, pick(price, -10**6, 0))),
+             ("in", 0, pick(date, 3000, 10**6)),
+             ("and", ("in", 3, pick(price, 10**7, 10**8)), ("between", 1, 5, 40)),
+             ("in", 1, tuple(int(v) for v in rng.integers(-128, 128, min(k, 200))))]
+    for tree in trees:
+        check_tree(sel, ctx, dt, orc, tree, ids=True)
+
+
 def test_kleene_single_rows(sel, ctx):
     """Every (a, b) in {T, U, F}^2 on one-row tables, through the GPU."""
     from tests.oracle_pins import GOLDEN, SYM, _leaf_table
