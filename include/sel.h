@@ -28,6 +28,9 @@
  *    alive while a table / program / call uses them).  Pointers named h_* or
  *    out_* without the d_ prefix are host pointers.
  *  - Column data must be 16-byte aligned; validity bitmaps 4-byte aligned.
+ *    Kernels may read (never write, never use) the bytes after a column's
+ *    last element up to the next 4-byte boundary, which lie in that
+ *    element's 16-byte-aligned block and so in the same memory page.
  *  - Synchronous calls return after results are on the host.  *_async
  *    calls only enqueue work on the context's stream.
  *  - A context is used by one host thread at a time.  Tables and programs

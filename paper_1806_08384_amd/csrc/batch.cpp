@@ -209,8 +209,15 @@ sel_status rebuild(sel_batch* b) {
   batch_shape(ctx, b->n, b->plan, grid, block);
   const uint32_t lds = b->plan.lds_bytes(block);
   const uint32_t nbuilds = (uint32_t)b->plan.builds.size();
+  // the lookup-table launch shapes (one per accumulator width)
   uint32_t lgrid = 0, lblock = 0;
-  if (!b->plan.lut.empty()) b->plan.lut_shape(lgrid, lblock);
+  if (!b->plan.lut.empty())
+    for (uint32_t d : {1u, 2u, 4u}) {
+      uint32_t g, bl;
+      b->plan.lut_shape(d, g, bl);
+      lgrid = lgrid * 31u + g;
+      lblock = lblock * 31u + bl;
+    }
   const uint32_t llds = b->plan.lut.empty() ? 0u : b->plan.lut.lds_bytes();
   if (b->exec && std::memcmp(&a, &b->args, sizeof a) == 0 && grid == b->grid && block == b->block &&
       lds == b->lds && d_builds == b->d_builds && nbuilds == b->nbuilds &&

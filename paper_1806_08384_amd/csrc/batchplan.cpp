@@ -7,6 +7,7 @@
 // pass and tile, tests every leaf on it from registers, and runs each
 // program's combinators over the resulting truth words held in LDS slots.
 #include <algorithm>
+#include <cstdio>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -447,6 +448,17 @@ void BatchPlan::clear() {
   max_slots = 0;
 }
 
+namespace {
+// SEL_TRACE_PLAN=1 prints every pass a batch plan makes to stderr.
+bool trace_plan() {
+  static const bool on = [] {
+    const char* v = std::getenv("SEL_TRACE_PLAN");
+    return v && std::atoi(v) != 0;
+  }();
+  return on;
+}
+}  // namespace
+
 void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
                     const sel_program* const* prg_all, const uint32_t* acc_all, uint32_t n_all) {
   if (row_end <= row_begin || n_all == 0) return;
@@ -462,13 +474,24 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
   std::vector<uint32_t> acc_v;
   const char* mode = std::getenv("SEL_BATCH_KERNEL");
   const bool force_lut = mode && std::strcmp(mode, "lut") == 0;
-  // half the rows per lane per segment in the lookup-table kernel
-  if (const char* fr = std::getenv("SEL_LUT_FEWER_ROWS")) lut_fewer_rows = std::atoi(fr) != 0 ? 1u : 0u;
   if ((mode && std::strcmp(mode, "leaf") == 0) || (!force_lut && !allow_lut)) {
     prg_v.assign(prg_all, prg_all + n_all);
     acc_v.assign(acc_all, acc_all + n_all);
   } else {
-    for (uint32_t i : lut.add(t, row_begin, row_end, prg_all, acc_all, n_all)) {
+    const size_t first_pass = lut.passes.size();
+    const std::vector<uint32_t> rej = lut.add(t, row_begin, row_end, prg_all, acc_all, n_all);
+    if (trace_plan())
+      for (size_t k = first_pass; k < lut.passes.size(); ++k) {
+        const LutPass& e = lut.passes[k];
+        uint32_t ldsc = 0;
+        for (uint32_t c = 0; c < e.col_count; ++c) ldsc += lut.cols[e.col_begin + c].lds_word != kNoLds;
+        std::fprintf(stderr,
+                     "sel plan: lut pass rows %llu+%llu programs %u columns %u (data %u, in LDS %u) "
+                     "dwords %u LDS words %u\n",
+                     (unsigned long long)e.row_begin, (unsigned long long)(row_end - row_begin), e.prog_count,
+                     e.col_count, e.ndata, ldsc, e.dwords, e.lds_words);
+      }
+    for (uint32_t i : rej) {
       prg_v.push_back(prg_all[i]);
       acc_v.push_back(acc_all[i]);
     }
@@ -578,6 +601,7 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
   for (uint32_t i = 0; i < n; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return key[x] < key[y]; });
   Pass ps;
+  const size_t first_entry = entries.size();
   for (uint32_t i : order) {
     // callers admit only programs that fit a pass of their own
     if (!ps.progs.empty() && ps.slots + ps.new_slots(prg[i]) > kBatchSlots) {
@@ -587,6 +611,11 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
     ps.add(prg[i], acc[i]);
   }
   flush(ps);
+  if (trace_plan())
+    for (size_t k = first_entry; k < entries.size(); ++k)
+      std::fprintf(stderr, "sel plan: leaf pass rows %llu+%llu programs %u columns %u tables %u slots %u\n",
+                   (unsigned long long)entries[k].row_begin, (unsigned long long)(row_end - row_begin),
+                   entries[k].prog_count, entries[k].col_count, entries[k].ntab, entries[k].slot_words / kWave);
 }
 
 namespace {
@@ -653,12 +682,15 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
   a.acc_words = acc_words();
 }
 
-void BatchPlan::lut_shape(uint32_t& grid, uint32_t& block) const {
-  block = lut_block ? lut_block : kLutBlock;
+void BatchPlan::lut_shape(uint32_t dwords, uint32_t& grid, uint32_t& block) const {
+  block = lut_block_for(dwords);
+  // an override applies when its waves divide the tile padding of a pass
+  if (lut_block && lut_block < block && lut_block % kWave == 0 && kLutTileAlign % (lut_block / kWave) == 0)
+    block = lut_block;
   uint64_t g = lut_grid;
   if (g == 0) {
     int occ = 1;
-    if (sel_lbatch_occupancy(1, lut_fewer_rows, block, lut.lds_bytes(), &occ) != 0 || occ < 1) occ = 1;
+    if (sel_lbatch_occupancy(dwords, block, lut.lds_bytes(), &occ) != 0 || occ < 1) occ = 1;
     g = (uint64_t)occ * num_cus;
   }
   const uint64_t need = std::max<uint64_t>(1, lut.total_tiles / (block / kWave));
@@ -677,8 +709,6 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
     // the last launch moves the finished lines out: k_batch if it runs
     int e = sel_launch_luts(la, stream);
     if (e) return e;
-    uint32_t lg, lb;
-    lut_shape(lg, lb);
     // one launch per accumulator width present; each takes its own passes
     bool present[5] = {false, false, false, false, false};
     for (const LutPass& p : lut.passes) present[p.dwords] = true;
@@ -686,7 +716,9 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
     for (uint32_t d : {1u, 2u, 4u}) {
       if (!present[d]) continue;
       la.ndone = !leaf && d == last ? a.ndone : 0u;
-      e = sel_launch_lbatch(la, d, lut_fewer_rows, lg, lb, lut.lds_bytes(), stream);
+      uint32_t lg, lb;
+      lut_shape(d, lg, lb);
+      e = sel_launch_lbatch(la, d, lg, lb, lut.lds_bytes(), stream);
       if (e) return e;
     }
   }

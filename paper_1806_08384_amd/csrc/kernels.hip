@@ -23,6 +23,8 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
+#include <utility>
 
 #include "sel_device.h"
 
@@ -1543,22 +1545,20 @@ __global__ void __launch_bounds__(256) k_luts(LutArgs a) {
   }
 }
 
-// Values of one lane's rows of one column in an item: NR rows (NR/4 steps
-// of the tile's row mapping), at most 32 dwords: a segment's R rows of a
-// narrow column, or up to 16 rows of an int64 column (two items per 32-row
-// segment).
-struct LSeg { v4i w[8]; };
-
+// Values of one lane's rows of one column in a segment: R = 8 rows (two
+// steps of the tile's row mapping) held from vector w[0]: step s of a narrow
+// column in w[s] (its leading components); of an int64 column, rows 0 and 1
+// of step s in w[s] and rows 2 and 3 in w[2 + s] (the next slot).
 template <int TY>
-__device__ __forceinline__ auto lget(const LSeg& r, int s, int i) {
+__device__ __forceinline__ auto lget(const v4i* w, int s, int i) {
   if constexpr (TY == T_I8) {
-    return (int32_t)(int8_t)((uint32_t)r.w[s][0] >> (8 * i));
+    return (int32_t)(int8_t)((uint32_t)w[s][0] >> (8 * i));
   } else if constexpr (TY == T_I16) {
-    return (int32_t)(int16_t)((uint32_t)r.w[s][i >> 1] >> (16 * (i & 1)));
+    return (int32_t)(int16_t)((uint32_t)w[s][i >> 1] >> (16 * (i & 1)));
   } else if constexpr (TY == T_I32) {
-    return (int32_t)r.w[s][i];
+    return (int32_t)w[s][i];
   } else {
-    const v4i& q = r.w[2 * s + (i >> 1)];
+    const v4i& q = w[2 * (i >> 1) + s];   // rows 2, 3 in the next slot
     const int k = 2 * (i & 1);
     return (int64_t)(((uint64_t)(uint32_t)q[k + 1] << 32) | (uint32_t)q[k]);
   }
@@ -1576,77 +1576,21 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void* data, ui
 
 constexpr int kNt = 2;   // buffer-load cache policy: nontemporal (streamed once)
 
-// Issue the loads of steps j0 .. j0 + S - 1 of a tile (S = R / 4, at most 4
-// for an int64 column): wide loads on a full tile; on the partial last tile
-// one load per row, rows past the table reading zero.
-template <int R>
-__device__ __forceinline__ void lseg_issue(LSeg& r, const CONSTANT LutCol* C, uint64_t tb, uint64_t nrows,
-                                           bool full, int j0, uint32_t lane) {
-  constexpr int S = R / 4;
-  const uint32_t ty = C->type;
-  const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
-  const __amdgpu_buffer_rsrc_t rs = tile_rsrc(C->data, tb, nrows, width);
-  if (!full) {
-    const int SS = ty == T_I64 ? (S < 4 ? S : 4) : S;
+// One register slot's loads for steps j0 .. j0 + S - 1: one 16-byte load
+// per step at the lane's first row, whatever the column's width, so that
+// every slot has the same shape and no slot's registers depend on a branch
+// (a branch would make the compiler wait for loads in flight).  A column
+// narrower than 4 bytes reads its neighbours' rows too (the same cache
+// lines); an int64 column takes two slots, the second one 16 bytes further.
+// The resource bounds the reads: past the table, or for an unused slot (no
+// bytes), they return zero without touching memory.
+template <int S>
+__device__ __forceinline__ void slot_issue(v4i* w, __amdgpu_buffer_rsrc_t rs, uint32_t width, int j0,
+                                           uint32_t lane) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      if (s >= SS) break;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const uint32_t off = (256u * (uint32_t)(j0 + s) + 4u * lane + (uint32_t)i) * width;
-        if (ty == T_I8) {
-          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b8(rs, (int)off, 0, 0);
-          if (i == 0) r.w[s][0] = 0;
-          r.w[s][0] |= (int32_t)((v & 0xFFu) << (8 * i));
-        } else if (ty == T_I16) {
-          const uint32_t v = __builtin_amdgcn_raw_buffer_load_b16(rs, (int)off, 0, 0);
-          if ((i & 1) == 0) r.w[s][i >> 1] = 0;
-          r.w[s][i >> 1] |= (int32_t)((v & 0xFFFFu) << (16 * (i & 1)));
-        } else if (ty == T_I32) {
-          r.w[s][i] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)off, 0, 0);
-        } else {
-          const v2u v = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
-          r.w[2 * s + (i >> 1)][2 * (i & 1)] = (int32_t)v[0];
-          r.w[2 * s + (i >> 1)][2 * (i & 1) + 1] = (int32_t)v[1];
-        }
-      }
-    }
-    return;
-  }
-  switch (ty) {
-    case T_I8: {
-#pragma unroll
-      for (int s = 0; s < S; ++s)
-        r.w[s][0] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)(4u * lane + 256u * (uint32_t)(j0 + s)), 0, kNt);
-      break;
-    }
-    case T_I16: {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const v2u x = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(8u * lane + 512u * (uint32_t)(j0 + s)), 0, kNt);
-        r.w[s][0] = (int32_t)x[0];
-        r.w[s][1] = (int32_t)x[1];
-      }
-      break;
-    }
-    case T_I32: {
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const v4u x = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(16u * lane + 1024u * (uint32_t)(j0 + s)), 0, kNt);
-        r.w[s] = (v4i)x;
-      }
-      break;
-    }
-    default: {
-#pragma unroll
-      for (int s = 0; s < (S < 4 ? S : 4); ++s) {
-        const uint32_t o = 32u * lane + 2048u * (uint32_t)(j0 + s);
-        r.w[2 * s] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, (int)o, 0, kNt);
-        r.w[2 * s + 1] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, (int)(o + 16u), 0, kNt);
-      }
-      break;
-    }
-  }
+  for (int s = 0; s < S; ++s)
+    w[s] = (v4i)__builtin_amdgcn_raw_buffer_load_b128(rs, (int)(width * (4u * lane + 256u * (uint32_t)(j0 + s))), 0,
+                                                      kNt);
 }
 
 // Validity of the segment's rows: bit 4 s + i = row (step j0 + s, i) is not
@@ -1663,6 +1607,8 @@ __device__ __forceinline__ uint32_t lseg_valid(const uint32_t* valid, uint64_t t
     if (full || tb + 256u * (uint32_t)(j0 + s) + 4u * lane < nrows) V |= ((vw[8 * s] >> sh) & 0xFu) << (4 * s);
   return V;
 }
+
+
 
 template <int D>
 __device__ __forceinline__ void ent_or(const uint32_t* tab, uint32_t idx, uint32_t (&acc)[D]) {
@@ -1741,7 +1687,7 @@ __device__ __forceinline__ void lookup_or(const CONSTANT LutCol* C, const uint32
 // One column on one item: every row's entry ORed into its accumulator.  V
 // holds the validity of the segment's R rows.
 template <int D, int R, int TY, int NR, int OFF>
-__device__ __forceinline__ void lut_col(const LSeg& seg, const CONSTANT LutCol* C,
+__device__ __forceinline__ void lut_col(const v4i* seg, const CONSTANT LutCol* C,
                                         const LutArgs& a, uint32_t V, const uint32_t* lds,
                                         const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
   constexpr int S = NR / 4;
@@ -1784,18 +1730,26 @@ __device__ __forceinline__ void lut_col(const LSeg& seg, const CONSTANT LutCol* 
     }
     lookup_or<D, R, NR, OFF>(C, lds, idx, n + 3, P, acc);
   } else {  // LK_RANK: the number of bounds at or below the value
+    // bounds in blocks of eight (the list is padded to whole blocks), one
+    // scalar load per block
     const CONSTANT int64_t* b = (const CONSTANT int64_t*)a.bounds + C->first;
 #pragma unroll
     for (int r = 0; r < NR; ++r) idx[r] = 0;
-    for (uint32_t k = 0; k < n; ++k) {
-      const int64_t bk = b[k];
+    for (uint32_t k0 = 0; k0 < n; k0 += 8) {
+      int64_t bb[8];
 #pragma unroll
-      for (int s = 0; s < S; ++s)
+      for (int j = 0; j < 8; ++j) bb[j] = b[k0 + j];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if constexpr (TY != T_I64) idx[4 * s + i] += lget<TY>(seg, s, i) >= (int32_t)bk ? 1u : 0u;
-          else idx[4 * s + i] += lget<TY>(seg, s, i) >= bk ? 1u : 0u;
-        }
+      for (int j = 0; j < 8; ++j) {
+        if (k0 + j >= n) break;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if constexpr (TY != T_I64) idx[4 * s + i] += lget<TY>(seg, s, i) >= (int32_t)bb[j] ? 1u : 0u;
+            else idx[4 * s + i] += lget<TY>(seg, s, i) >= bb[j] ? 1u : 0u;
+          }
+      }
     }
     if (nullable) {
 #pragma unroll
@@ -1992,65 +1946,87 @@ __device__ __forceinline__ void lut_start(const CONSTANT LutPass* P, const CONST
   }
 }
 
-// Items of a segment: one per data column, two for an int64 column when a
-// segment has 32 rows (16 rows each).
-template <int R>
-__device__ __forceinline__ uint32_t parts_of(const CONSTANT LutCol* C) {
-  return R == 32 && C->type == T_I64 ? 2u : 1u;
+// Calls f(integral_constant<int, k>) for k = 0 .. N-1, unrolled whatever
+// the size of f's body (slot indexes must stay compile-time constants for
+// the slots to live in registers).
+template <class F, int... K>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, K...>) {
+  (f(std::integral_constant<int, K>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int R>
-__device__ __forceinline__ void lut_issue(LSeg& buf, const CONSTANT LutPass* P,
-                                          const CONSTANT LutCol* cols, uint64_t tb, bool full,
-                                          uint32_t seg, uint32_t c, uint32_t part, uint32_t lane) {
-  const CONSTANT LutCol* C = cols + P->col_begin + c;
-  const int j0 = (int)(seg * (R / 4) + 4 * part);
-  lseg_issue<R>(buf, C, tb, P->nrows, full, j0, lane);
-}
-
-template <int D, int R>
-__device__ __forceinline__ void lut_step(const LSeg& buf, const CONSTANT LutPass* P,
-                                         const CONSTANT LutCol* cols, const LutArgs& a, uint64_t tb,
-                                         bool full, uint32_t seg, uint32_t c, uint32_t part,
-                                         uint32_t lane, const uint32_t* lds, uint32_t (&acc)[R][D],
-                                         uint32_t V) {
-  const CONSTANT LutCol* C = cols + P->col_begin + c;
-  switch (C->type) {
-    case T_I8: lut_col<D, R, T_I8, R, 0>(buf, C, a, V, lds, P, acc); break;
-    case T_I16: lut_col<D, R, T_I16, R, 0>(buf, C, a, V, lds, P, acc); break;
-    case T_I32: lut_col<D, R, T_I32, R, 0>(buf, C, a, V, lds, P, acc); break;
-    default:
-      if (part == 0) lut_col<D, R, T_I64, (R < 16 ? R : 16), 0>(buf, C, a, V, lds, P, acc);
-      else if constexpr (R == 32) lut_col<D, R, T_I64, 16, 16>(buf, C, a, V, lds, P, acc);
-      break;
-  }
-}
-
-// Every column of a pass on one tile: per segment of R rows, each column's
-// rows are loaded (all their loads in flight together, as one item) and
-// looked up; other waves hide the latency, as in the count scan.
+// Every column of a pass on one tile, in segments of R = 8 rows per lane:
+// the loads of all the segment's data columns and of their validity words
+// are issued together, unconditionally, into register slots of two vectors
+// (an int64 column takes two slots), so that a wave keeps every column of
+// its segment in flight; other waves hide the latency while it waits.  Rows
+// past the table read zeros or neighbouring values and are not counted.
 template <int D, int R>
 __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTANT LutCol* cols,
                                          const LutArgs& a, uint64_t tb, uint32_t lane,
                                          const uint32_t* lds, Hs& hs) {
-  constexpr int NSEG = kSteps / (R / 4);
-  const uint32_t nd = P->ndata;   // columns with data
+  static_assert(R == 8, "segments of two steps");
+  constexpr int S = R / 4, NSEG = kSteps / S;
   const bool full = tb + kTileRows <= P->nrows;
+  const uint64_t nrows = P->nrows;
+  const uint64_t rows = nrows - tb < (uint64_t)kTileRows ? nrows - tb : (uint64_t)kTileRows;
   const CONSTANT LutCol* cb = cols + P->col_begin;
   uint32_t acc[R][D];
   uint32_t inr;
+  v4i buf[2 * kLutSlots];
+  uint32_t vr[kLutSlots][S];
   for (int seg = 0; seg < NSEG; ++seg) {
+    const int j0 = seg * S;
+    static_for<kLutSlots>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const uint32_t code = (P->slot_col[k / 4] >> (8 * (k % 4))) & 0xFFu;
+      const bool used = code != kNoSlotCol;
+      const CONSTANT LutCol* C = cb + (code & kSlotColMask);
+      const uint32_t ty = used ? C->type : (uint32_t)T_I32;
+      const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
+      const uint32_t half = code & kSlotHigh ? 16u : 0u;
+      const char* base = used ? (const char*)C->data + tb * width + half : (const char*)a.passes;
+      // whole dwords: a raw buffer load zeroes a dword that crosses the
+      // bound, and the bytes up to the next 4-byte boundary share the last
+      // element's 16-byte-aligned block (the same memory page)
+      const uint32_t span = ((uint32_t)(rows * width) + 3u) & ~3u;
+      const uint32_t bytes = used && span > half ? span - half : 0u;
+      slot_issue<S>(buf + 2 * k, __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000),
+                    width, j0, lane);
+      // validity words of the slot's column (none for the second slot of an
+      // int64 column or a column without NULLs)
+      const bool hv = used && !half && C->valid;
+      const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
+          hv ? (void*)(C->valid + tb / 32) : (void*)a.passes, (short)0, hv ? (int)(((rows + 31) / 32) * 4) : 0,
+          0x00020000);
+#pragma unroll
+      for (int st = 0; st < S; ++st)
+        vr[k][st] = __builtin_amdgcn_raw_buffer_load_b32(vrs, (int)(4u * ((lane >> 3) + 8u * (uint32_t)(j0 + st))), 0, 0);
+    });
     lut_start<D, R>(P, cols, tb, full, seg, lane, acc, inr);
-    for (uint32_t c = 0; c < nd; ++c) {
-      const CONSTANT LutCol* C = cb + c;
-      const uint32_t V = C->valid ? lseg_valid<R>(C->valid, tb, seg * (R / 4), lane, P->nrows, full) : ~0u;
-      const uint32_t np = parts_of<R>(C);
-      for (uint32_t part = 0; part < np; ++part) {
-        LSeg x;
-        lut_issue<R>(x, P, cols, tb, full, (uint32_t)seg, c, part, lane);
-        lut_step<D, R>(x, P, cols, a, tb, full, (uint32_t)seg, c, part, lane, lds, acc, V);
+    static_for<kLutSlots>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const uint32_t code = (P->slot_col[k / 4] >> (8 * (k % 4))) & 0xFFu;
+      if (code == kNoSlotCol || (code & kSlotHigh)) return;
+      const CONSTANT LutCol* C = cb + (code & kSlotColMask);
+      uint32_t V = 0xFFu;
+      if (C->valid) {
+        V = 0;
+#pragma unroll
+        for (int st = 0; st < S; ++st) V |= ((vr[k][st] >> (4 * (lane & 7))) & 0xFu) << (4 * st);
       }
-    }
+      switch (C->type) {
+        case T_I8: lut_col<D, R, T_I8, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
+        case T_I16: lut_col<D, R, T_I16, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
+        case T_I32: lut_col<D, R, T_I32, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
+        default:
+          if constexpr (k + 1 < (int)kLutSlots) lut_col<D, R, T_I64, R, 0>(buf + 2 * k, C, a, V, lds, P, acc);
+          break;
+      }
+    });
     lut_count<D, R>(acc, P, inr, hs);
   }
 }
@@ -2061,7 +2037,7 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
 // (pass ranges are padded to kLutTileAlign), and copies a pass's LDS tables
 // from device memory when it moves to that pass.
 template <int D, int R>
-__global__ void __launch_bounds__(768) k_lbatch(LutArgs a) {
+__global__ void __launch_bounds__(lut_block_for(D)) k_lbatch(LutArgs a) {
   extern __shared__ uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
@@ -2107,7 +2083,9 @@ __global__ void __launch_bounds__(768) k_lbatch(LutArgs a) {
     }
     const uint64_t local = flat - P->tile_begin;
     if (local >= P->ntiles) continue;   // padding
-    const uint64_t tb = P->row_begin + local * kTileRows;
+    // the wave's tile start is wave-uniform: say so, so that the buffer
+    // resources built from it stay in scalar registers
+    const uint64_t tb = uni64(P->row_begin + local * kTileRows);
     lut_tile<D, R>(P, cols, a, tb, lane, lds, hs);
     if (++since == kLutFlushTiles) {
       hs_flush(hs, P, a.acc, a.acc_index, accl, nacc, lane);
@@ -2249,25 +2227,24 @@ int sel_launch_luts(const LutArgs& a, void* stream) {
 // The lookup-table kernel for passes of `dwords` accumulator dwords per row,
 // with `rows` rows per lane per segment (the larger choice, or half of it).
 namespace {
-const void* lbatch_kernel(uint32_t dwords, bool fewer_rows) {
+const void* lbatch_kernel(uint32_t dwords) {
   switch (dwords) {
-    case 1: return fewer_rows ? (const void*)k_lbatch<1, 8> : (const void*)k_lbatch<1, 16>;
-    case 2: return fewer_rows ? (const void*)k_lbatch<2, 4> : (const void*)k_lbatch<2, 8>;
-    default: return fewer_rows ? (const void*)k_lbatch<4, 4> : (const void*)k_lbatch<4, 8>;
+    case 1: return (const void*)k_lbatch<1, 8>;
+    case 2: return (const void*)k_lbatch<2, 8>;
+    default: return (const void*)k_lbatch<4, 8>;
   }
 }
 }  // namespace
 
-int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t fewer_rows, uint32_t grid, uint32_t block,
-                      uint32_t lds_bytes, void* stream) {
+int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
+                      void* stream) {
+  if (block == 0 || block > lut_block_for(dwords) || block % kWave) return (int)hipErrorInvalidValue;
   LutArgs args = a;
   void* kargs[] = {&args};
-  return (int)hipLaunchKernel(lbatch_kernel(dwords, fewer_rows != 0), dim3(grid), dim3(block), kargs, lds_bytes,
+  return (int)hipLaunchKernel(lbatch_kernel(dwords), dim3(grid), dim3(block), kargs, lds_bytes,
                               (hipStream_t)stream);
 }
 
-int sel_lbatch_occupancy(uint32_t dwords, uint32_t fewer_rows, uint32_t block, uint32_t lds_bytes,
-                         int* blocks_per_cu) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lbatch_kernel(dwords, fewer_rows != 0),
-                                                           block, lds_bytes);
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lbatch_kernel(dwords), block, lds_bytes);
 }

@@ -140,6 +140,7 @@ uint32_t dwords_for(const std::vector<uint32_t>& Ws) {
 struct Form {
   std::vector<Clause> clauses;
   std::vector<std::vector<uintptr_t>> cols;   // per clause: its columns (distinct)
+  std::map<uintptr_t, uint32_t> slots;        // per column: register slots of its data
   uint32_t ncross = 0;                        // clauses over several columns
   bool always_false = false;
   const sel_program* prog = nullptr;
@@ -177,6 +178,8 @@ bool make_form(const sel_program* p, Form& f) {
     for (const Lit& L : c) {
       const uintptr_t k = lit_col(L, c);
       if (std::find(cs.begin(), cs.end(), k) == cs.end()) cs.push_back(k);
+      if (is_value(L.ins.op)) f.slots[k] = L.ins.type == T_I64 ? 2u : 1u;
+      else f.slots.emplace(k, 0u);
     }
     if (cs.size() > 1) ++f.ncross;
     f.cols.push_back(std::move(cs));
@@ -350,6 +353,14 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
         if (std::find(key[i].begin(), key[i].end(), k) == key[i].end()) key[i].push_back(k);
     std::sort(key[i].begin(), key[i].end());
   }
+  std::map<uintptr_t, uint32_t> slots;
+  for (const Form& f : forms)
+    for (const auto& kv : f.slots) slots[kv.first] = std::max(slots[kv.first], kv.second);
+  auto slots_of = [&](const std::set<uintptr_t>& cs) {
+    uint32_t n = 0;
+    for (uintptr_t k : cs) n += slots[k];
+    return n;
+  };
   std::vector<size_t> order(forms.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
@@ -470,6 +481,23 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
         e.init[d] = init;
       }
     }
+    // register slots: int64 columns first (two each, aligned), then the
+    // narrower ones
+    e.slot_col[0] = e.slot_col[1] = ~0u;
+    {
+      uint32_t k = 0;
+      for (int wide = 1; wide >= 0; --wide)
+        for (uint32_t ci = 0; ci < order_c.size(); ++ci) {
+          const PassCol* c = order_c[ci];
+          if (c->kind == LK_VALID || (c->type == T_I64) != (wide == 1)) continue;
+          const uint32_t need = c->type == T_I64 ? 2u : 1u;
+          if (k + need > kLutSlots) return false;
+          for (uint32_t h = 0; h < need; ++h, ++k) {
+            e.slot_col[k / 4] &= ~(0xFFu << (8 * (k % 4)));
+            e.slot_col[k / 4] |= (ci | (h ? kSlotHigh : 0u)) << (8 * (k % 4));
+          }
+        }
+    }
     uint32_t lw = 0;
     for (PassCol* c : order_c) {
       LutCol lc{};
@@ -513,6 +541,8 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
       nentries += c->entries;
       gtab_words += ((c->entries * D * 4 + 255) & ~255ull) / 4;
       bounds.insert(bounds.end(), c->bounds.begin(), c->bounds.end());
+      // whole blocks of eight for the kernel's block loads
+      while (bounds.size() % 8) bounds.push_back(INT64_MAX);
       reps.insert(reps.end(), c->reps.begin(), c->reps.end());
       if (c->kind != LK_VALID) ++e.ndata;
       cols.push_back(lc);
@@ -543,7 +573,8 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
     std::vector<uint32_t> Ws;
     for (const Form* g : cur) Ws.push_back(1 + g->ncross);
     Ws.push_back(1 + f.ncross);
-    if (!cur.empty() && (P > kMaxPassProgs || dwords_for(Ws) == 0 || cs.size() > kMaxPassCols)) {
+    if (!cur.empty() && (P > kMaxPassProgs || dwords_for(Ws) == 0 || cs.size() > kMaxPassCols ||
+                         slots_of(cs) > kLutSlots)) {
       flush();
       cs.clear();
       for (const auto& c : f.cols) cs.insert(c.begin(), c.end());

@@ -243,7 +243,6 @@ struct BatchPlan {
   mutable sel::LutArgs largs{};          // as written
   uint32_t num_cus = 256;
   uint32_t lut_block = 0, lut_grid = 0;  // 0: the defaults
-  uint32_t lut_fewer_rows = 0;           // 1: half the rows per lane per segment
   std::vector<sel::BatchTable> entries;
   std::vector<sel::BatchCol> cols;
   std::vector<DevInstr> leaves;
@@ -275,8 +274,8 @@ struct BatchPlan {
   // last of them moves the finished accumulator lines out.
   int launch(const sel::BatchArgs& a, const sel::TableBuild* d_builds, uint32_t grid,
              uint32_t block, void* stream) const;
-  // Launch shape of the lookup-table kernel.
-  void lut_shape(uint32_t& grid, uint32_t& block) const;
+  // Launch shape of the lookup-table kernel for passes of `dwords` dwords.
+  void lut_shape(uint32_t dwords, uint32_t& grid, uint32_t& block) const;
   uint32_t acc_words() const {
     return (uint32_t)std::min<size_t>(progs.size(), (size_t)sel::kBatchMaxProgs);
   }

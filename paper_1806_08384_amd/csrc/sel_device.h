@@ -384,7 +384,10 @@ struct LutPass {             // 112 bytes: one pass over a table or a chunk of i
   uint32_t init[4];          // accumulator start value per dword
   uint32_t fold[4];          // per dword: b_d | G_d << 8 | pos_d << 16 (G_d = 0: unused)
   uint32_t ndata;            // columns with data (the first ones); validity-only ones follow
-  uint32_t pad[3];
+  uint32_t slot_col[2];      // byte k: the data column (index in the pass) loaded into
+                             // register slot k, kSlotHigh set on the second slot of an
+                             // int64 column; kNoSlotCol for an unused slot
+  uint32_t pad;
 };
 static_assert(sizeof(LutPass) == 112, "LutPass layout");
 
@@ -400,7 +403,14 @@ struct LutBuild {            // 40 bytes
 };
 
 constexpr uint32_t kLutTileAlign = 48;   // waves of a workgroup: 1, 2, 3, 4, 6, 8, 12 or 16
-constexpr uint32_t kLutBlock = 768;      // default workgroup: twelve waves, one per CU (its LDS)
+constexpr uint32_t kLutSlots = 8;        // register slots of two vectors per segment (8 rows per lane)
+constexpr uint32_t kNoSlotCol = 0xFF;
+constexpr uint32_t kSlotColMask = 0x1F;
+constexpr uint32_t kSlotHigh = 0x20;
+// workgroup of the lookup-table kernel, one per CU (its LDS): twelve waves
+// (three per SIMD) with one or two accumulator dwords, eight with four
+// (more registers per lane)
+constexpr uint32_t lut_block_for(uint32_t dwords) { return dwords >= 4 ? 512u : 768u; }
 constexpr uint64_t kLutMaxRows = 64ull << 20;   // longest chunk given to the lookup-table kernel
 constexpr uint32_t kLutFlushTiles = 48;  // tiles between reads of the bit-plane counters
 
@@ -447,11 +457,9 @@ int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, uin
                      void* stream);
 int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 // Table builds, then the lookup-table batch kernel over the passes with
-// `dwords` accumulator dwords per row (16 rows per lane per segment with
-// one dword, 8 with two or four; half of that with fewer_rows).
+// `dwords` accumulator dwords per row (block at most lut_block_for(dwords)).
 int sel_launch_luts(const sel::LutArgs& a, void* stream);
-int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t fewer_rows, uint32_t grid,
-                      uint32_t block, uint32_t lds_bytes, void* stream);
-int sel_lbatch_occupancy(uint32_t dwords, uint32_t fewer_rows, uint32_t block, uint32_t lds_bytes,
-                         int* blocks_per_cu);
+int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
+                      void* stream);
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 }
