@@ -61,9 +61,7 @@ sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
       distinct.push_back(tables[i]);
   }
   bp.clear();
-  // the lookup-table kernel when every table is short (see BatchPlan::add)
-  bp.allow_lut = true;
-  for (const sel_table* t : distinct) bp.allow_lut &= t->nrows <= kLutMaxRows;
+  bp.allow_lut = true;   // the lookup-table kernel for the programs it can express
   std::vector<const sel_program*> ps;
   std::vector<uint32_t> acc;
   for (const sel_table* t : distinct) {

@@ -463,13 +463,11 @@ void BatchPlan::add(const sel_table* t, uint64_t row_begin, uint64_t row_end,
                     const sel_program* const* prg_all, const uint32_t* acc_all, uint32_t n_all) {
   if (row_end <= row_begin || n_all == 0) return;
   // The lookup-table kernel takes the programs it can express when the
-  // caller allows it (every chunk of the launch at most kLutMaxRows rows:
-  // there its single lookup per column and row beats the leaf-major kernel,
-  // whose fixed costs per launch and pass dominate; over longer chunks the
-  // leaf-major kernel keeps more loads in flight per wave, and a launch that
-  // mixed both would run them one after the other).  The environment
-  // variable SEL_BATCH_KERNEL forces either kernel ("lut": every
-  // expressible program, "leaf": none).
+  // caller allows it: one lookup per column and row serves every program of
+  // a pass.  The rest (IS UNKNOWN, too many clauses or columns, a value
+  // window whose table would not stay in cache and too many bounds to rank)
+  // go to the leaf-major kernel.  The environment variable SEL_BATCH_KERNEL
+  // forces either kernel ("lut": every expressible program, "leaf": none).
   std::vector<const sel_program*> prg_v;
   std::vector<uint32_t> acc_v;
   const char* mode = std::getenv("SEL_BATCH_KERNEL");

@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nw = blockDim.x >> 6;
   const uint64_t W = (uint64_t)gridDim.x * nw;
-  extern __shared__ uint32_t sbm[];
+  extern __shared__ __align__(16) uint32_t sbm[];
   const StageView sv{(const CONSTANT BatchBitmap*)a.stage, a.nstage, sbm};
   if (a.nstage) {
     // the program's small bitmaps, each followed by a zero word
@@ -1276,7 +1276,7 @@ __device__ __forceinline__ uint32_t run_ops2(const CONSTANT uint32_t* ops, uint3
 // accumulating: a cooperative scan adds one chunk per launch.
 __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   // LDS: per-program counters, tables and staged bitmaps, each wave's slots
-  extern __shared__ uint32_t dyn[];
+  extern __shared__ __align__(16) uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t nacc = a.acc_words;   // min(nprogs, kBatchMaxProgs)
@@ -1625,6 +1625,24 @@ __device__ __forceinline__ void ent_or(const uint32_t* tab, uint32_t idx, uint32
   }
 }
 
+#define LDS_PTR(T) __attribute__((address_space(3))) T*
+
+// The entry at LDS byte address e ORed into the accumulators.
+template <int D>
+__device__ __forceinline__ void ent_or_lds(LDS_PTR(const char) e, uint32_t (&acc)[D]) {
+  if constexpr (D == 1) {
+    acc[0] |= *(LDS_PTR(const uint32_t))e;
+  } else if constexpr (D == 2) {
+    const v2u x = *(LDS_PTR(const v2u))e;
+    acc[0] |= x[0];
+    acc[1] |= x[1];
+  } else {
+    const v4u x = *(LDS_PTR(const v4u))e;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) acc[d] |= x[d];
+  }
+}
+
 // Entry idx of a device-memory table through a buffer resource: a 32-bit
 // offset per lane instead of a 64-bit address, and an offset past the
 // table reads zero.
@@ -1649,20 +1667,67 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t table_rsrc(const uint32_t* tab
   return __builtin_amdgcn_make_buffer_rsrc((void*)tab, (short)0, (int)(entries * dwords * 4u), 0x00020000);
 }
 
+// A register slot's column as its lookups need it, decoded once per tile.
+struct SlotD {
+  uint32_t info;          // kSd* flags, type in bits 0..3, kind in bits 4..5
+  uint32_t n;             // DIRECT: window size; RANK: bounds
+  int64_t lo;             // DIRECT: value of entry 1
+  uint32_t tab;           // table: LDS word offset, or kNoLds
+  uint32_t first;         // RANK: first bound
+  const uint32_t* gtab;   // table in device memory
+  const char* data;       // the slot's bytes of the tile's first row
+  const uint32_t* valid;  // validity word of the tile's first row
+  uint32_t bytes, vbytes; // readable bytes from there (0: none)
+};
+constexpr uint32_t kSdNullable = 1u << 8, kSdGuard = 1u << 10, kSdData = 1u << 11;
+
+__device__ __forceinline__ SlotD slot_decode(const CONSTANT LutPass* P, const CONSTANT LutCol* cb, int k,
+                                             uint64_t tb, uint64_t rows) {
+  SlotD d{};
+  const uint32_t code = (P->slot_col[k / 4] >> (8 * (k % 4))) & 0xFFu;
+  if (code == kNoSlotCol) {
+    d.info = T_I32;
+    d.data = (const char*)P;
+    d.valid = (const uint32_t*)P;
+  } else {
+    const CONSTANT LutCol* C = cb + (code & kSlotColMask);
+    const uint32_t ty = C->type;
+    const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
+    const uint32_t half = code & kSlotHigh ? 16u : 0u;
+    d.info = ty | (C->kind << 4) | (C->valid ? kSdNullable : 0u) | (C->guard ? kSdGuard : 0u) |
+             (half ? 0u : kSdData);
+    d.n = C->n;
+    d.lo = C->lo;
+    d.tab = C->lds_word;
+    d.first = C->first;
+    d.gtab = C->gtab;
+    d.data = (const char*)C->data + tb * width + half;
+    // whole dwords: a raw buffer load zeroes a dword that crosses the
+    // bound, and the bytes up to the next 4-byte boundary share the last
+    // element's 16-byte-aligned block (the same memory page)
+    const uint32_t span = ((uint32_t)(rows * width) + 3u) & ~3u;
+    d.bytes = span > half ? span - half : 0u;
+    const bool hv = !half && C->valid;
+    d.valid = hv ? C->valid + tb / 32 : (const uint32_t*)P;
+    d.vbytes = hv ? (uint32_t)(((rows + 31) / 32) * 4) : 0u;
+  }
+  return d;
+}
+
 // Table indices of an item's rows to entries, ORed into the accumulators of
 // segment rows OFF .. OFF + NR - 1: from LDS, or from device memory where a
 // guarded table is read only on rows some program of the pass can still
 // count (the others read the zero entry).
 template <int D, int R, int NR, int OFF>
-__device__ __forceinline__ void lookup_or(const CONSTANT LutCol* C, const uint32_t* lds, uint32_t (&idx)[NR],
+__device__ __forceinline__ void lookup_or(const SlotD& sd, const uint32_t* lds, uint32_t (&idx)[NR],
                                           uint32_t zero, const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
-  if (C->lds_word != kNoLds) {
-    const uint32_t* tab = lds + C->lds_word;
+  if (sd.tab != kNoLds) {
+    const uint32_t* tab = lds + sd.tab;
 #pragma unroll
     for (int r = 0; r < NR; ++r) ent_or<D>(tab, idx[r], acc[OFF + r]);
   } else {
-    const __amdgpu_buffer_rsrc_t tab = table_rsrc(C->gtab, zero + 1, D);
-    if (C->guard) {
+    const __amdgpu_buffer_rsrc_t tab = table_rsrc(sd.gtab, zero + 1, D);
+    if (sd.info & kSdGuard) {
       // a row some program can still count: a failure bit (word 0 of a
       // dword) still clear
       uint32_t am[D];
@@ -1684,19 +1749,41 @@ __device__ __forceinline__ void lookup_or(const CONSTANT LutCol* C, const uint32
   }
 }
 
-// One column on one item: every row's entry ORed into its accumulator.  V
-// holds the validity of the segment's R rows.
+// One column on one segment: every row's entry ORed into its accumulator.
+// V holds the validity of the segment's R rows.
 template <int D, int R, int TY, int NR, int OFF>
-__device__ __forceinline__ void lut_col(const v4i* seg, const CONSTANT LutCol* C,
-                                        const LutArgs& a, uint32_t V, const uint32_t* lds,
-                                        const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
+__device__ __forceinline__ void lut_col(const v4i* seg, const SlotD& sd, const LutArgs& a, uint32_t V,
+                                        const uint32_t* lds, const CONSTANT LutPass* P, uint32_t (&acc)[R][D]) {
   constexpr int S = NR / 4;
-  const uint32_t kind = C->kind, n = C->n;
-  const bool nullable = C->valid != nullptr;
+  const uint32_t kind = (sd.info >> 4) & 3u, n = sd.n;
+  const bool nullable = (sd.info & kSdNullable) != 0;
   uint32_t idx[NR];
   if (kind == LK_DIRECT) {
-    const int64_t lo = C->lo;
+    const int64_t lo = sd.lo;
     if constexpr (TY != T_I64) {
+      if (sd.tab != kNoLds && !nullable) {
+        // clamped value straight to the entry's LDS byte address: the
+        // table's address less (lo - 1) entries, plus the value's entries
+        constexpr int64_t tmin = TY == T_I8 ? INT8_MIN : TY == T_I16 ? INT16_MIN : INT32_MIN;
+        constexpr int64_t tmax = TY == T_I8 ? INT8_MAX : TY == T_I16 ? INT16_MAX : INT32_MAX;
+        const int32_t cl = (int32_t)(lo - 1 < tmin ? tmin : lo - 1);
+        const int32_t ch = (int32_t)(lo + (int64_t)n > tmax ? tmax : lo + (int64_t)n);
+        // byte offsets within LDS, through an LDS-space pointer (32-bit)
+        const LDS_PTR(const char) l3 = (LDS_PTR(const char))lds;
+        const uint32_t abase = sd.tab * 4u - (uint32_t)(lo - 1) * (4u * D);
+        int32_t chv = ch;   // in a vector register once: one scalar operand per VALU op
+        asm volatile("v_mov_b32 %0, %1" : "=v"(chv) : "s"(ch));
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int32_t x = lget<TY>(seg, s, i);
+            int32_t m;
+            asm("v_med3_i32 %0, %1, %2, %3" : "=v"(m) : "v"(x), "s"(cl), "v"(chv));
+            ent_or_lds<D>(l3 + (abase + (uint32_t)m * (4u * D)), acc[OFF + 4 * s + i]);
+          }
+        return;
+      }
       // clamp to [lo - 1, lo + n] (inside the type), then offset: entry 0
       // below the window, n + 1 above it
       constexpr int64_t tmin = TY == T_I8 ? INT8_MIN : TY == T_I16 ? INT16_MIN : INT32_MIN;
@@ -1728,11 +1815,11 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const CONSTANT LutCol* C
 #pragma unroll
       for (int r = 0; r < NR; ++r) idx[r] = (V >> (OFF + r)) & 1u ? idx[r] : n + 2;
     }
-    lookup_or<D, R, NR, OFF>(C, lds, idx, n + 3, P, acc);
+    lookup_or<D, R, NR, OFF>(sd, lds, idx, n + 3, P, acc);
   } else {  // LK_RANK: the number of bounds at or below the value
     // bounds in blocks of eight (the list is padded to whole blocks), one
     // scalar load per block
-    const CONSTANT int64_t* b = (const CONSTANT int64_t*)a.bounds + C->first;
+    const CONSTANT int64_t* b = (const CONSTANT int64_t*)a.bounds + sd.first;
 #pragma unroll
     for (int r = 0; r < NR; ++r) idx[r] = 0;
     for (uint32_t k0 = 0; k0 < n; k0 += 8) {
@@ -1755,7 +1842,7 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const CONSTANT LutCol* C
 #pragma unroll
       for (int r = 0; r < NR; ++r) idx[r] = (V >> (OFF + r)) & 1u ? idx[r] : n + 1;
     }
-    lookup_or<D, R, NR, OFF>(C, lds, idx, n + 2, P, acc);
+    lookup_or<D, R, NR, OFF>(sd, lds, idx, n + 2, P, acc);
   }
 }
 
@@ -1855,17 +1942,39 @@ __device__ __forceinline__ void lut_count(uint32_t (&acc)[R][D], const CONSTANT 
   }
   uint32_t T[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    uint32_t res = 0;
+  for (int r = 0; r < R; ++r) T[r] = 0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      uint32_t t = acc[r][d] ^ nm[d];
-      if (bw[d] <= 16) t &= t >> 16;
-      if (bw[d] <= 8) t &= t >> 8;
-      if (bw[d] <= 4) t &= t >> 4;
-      res |= (t & gm[d]) << ps[d];
+  for (int d = 0; d < D; ++d) {
+    // the dword's width, a uniform branch around all rows
+    if (bw[d] >= 32) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) T[r] |= ((acc[r][d] ^ nm[d]) & gm[d]) << ps[d];
+    } else if (bw[d] == 16) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t t = acc[r][d] ^ nm[d];
+        T[r] |= ((t & (t >> 16)) & gm[d]) << ps[d];
+      }
+    } else if (bw[d] == 8) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint32_t t = acc[r][d] ^ nm[d];
+        t &= t >> 16;
+        T[r] |= ((t & (t >> 8)) & gm[d]) << ps[d];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint32_t t = acc[r][d] ^ nm[d];
+        t &= t >> 16;
+        t &= t >> 8;
+        T[r] |= ((t & (t >> 4)) & gm[d]) << ps[d];
+      }
     }
-    T[r] = (inr >> r) & 1u ? res : 0u;
+  }
+  if (inr != ~0u) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) T[r] = (inr >> r) & 1u ? T[r] : 0u;
   }
   if (B == 32) {
     hs_add<R>(hs, T);
@@ -1978,30 +2087,24 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
   uint32_t inr;
   v4i buf[2 * kLutSlots];
   uint32_t vr[kLutSlots][S];
+  // decoded once per tile (what does not fit in scalar registers moves to
+  // lanes of vector registers, cheaper than reloading it per segment)
+  SlotD sd[kLutSlots];
+  static_for<kLutSlots>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    sd[k] = slot_decode(P, cb, k, tb, rows);
+  });
   for (int seg = 0; seg < NSEG; ++seg) {
     const int j0 = seg * S;
     static_for<kLutSlots>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const uint32_t code = (P->slot_col[k / 4] >> (8 * (k % 4))) & 0xFFu;
-      const bool used = code != kNoSlotCol;
-      const CONSTANT LutCol* C = cb + (code & kSlotColMask);
-      const uint32_t ty = used ? C->type : (uint32_t)T_I32;
+      const uint32_t ty = sd[k].info & 15u;
       const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
-      const uint32_t half = code & kSlotHigh ? 16u : 0u;
-      const char* base = used ? (const char*)C->data + tb * width + half : (const char*)a.passes;
-      // whole dwords: a raw buffer load zeroes a dword that crosses the
-      // bound, and the bytes up to the next 4-byte boundary share the last
-      // element's 16-byte-aligned block (the same memory page)
-      const uint32_t span = ((uint32_t)(rows * width) + 3u) & ~3u;
-      const uint32_t bytes = used && span > half ? span - half : 0u;
-      slot_issue<S>(buf + 2 * k, __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000),
+      slot_issue<S>(buf + 2 * k,
+                    __builtin_amdgcn_make_buffer_rsrc((void*)sd[k].data, (short)0, (int)sd[k].bytes, 0x00020000),
                     width, j0, lane);
-      // validity words of the slot's column (none for the second slot of an
-      // int64 column or a column without NULLs)
-      const bool hv = used && !half && C->valid;
-      const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(
-          hv ? (void*)(C->valid + tb / 32) : (void*)a.passes, (short)0, hv ? (int)(((rows + 31) / 32) * 4) : 0,
-          0x00020000);
+      const __amdgpu_buffer_rsrc_t vrs =
+          __builtin_amdgcn_make_buffer_rsrc((void*)sd[k].valid, (short)0, (int)sd[k].vbytes, 0x00020000);
 #pragma unroll
       for (int st = 0; st < S; ++st)
         vr[k][st] = __builtin_amdgcn_raw_buffer_load_b32(vrs, (int)(4u * ((lane >> 3) + 8u * (uint32_t)(j0 + st))), 0, 0);
@@ -2009,21 +2112,20 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
     lut_start<D, R>(P, cols, tb, full, seg, lane, acc, inr);
     static_for<kLutSlots>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const uint32_t code = (P->slot_col[k / 4] >> (8 * (k % 4))) & 0xFFu;
-      if (code == kNoSlotCol || (code & kSlotHigh)) return;
-      const CONSTANT LutCol* C = cb + (code & kSlotColMask);
+      const SlotD& d = sd[k];
+      if (!(d.info & kSdData)) return;
       uint32_t V = 0xFFu;
-      if (C->valid) {
+      if (d.info & kSdNullable) {
         V = 0;
 #pragma unroll
         for (int st = 0; st < S; ++st) V |= ((vr[k][st] >> (4 * (lane & 7))) & 0xFu) << (4 * st);
       }
-      switch (C->type) {
-        case T_I8: lut_col<D, R, T_I8, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
-        case T_I16: lut_col<D, R, T_I16, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
-        case T_I32: lut_col<D, R, T_I32, R, 0>(buf + 2 * k, C, a, V, lds, P, acc); break;
+      switch (d.info & 15u) {
+        case T_I8: lut_col<D, R, T_I8, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
+        case T_I16: lut_col<D, R, T_I16, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
+        case T_I32: lut_col<D, R, T_I32, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
         default:
-          if constexpr (k + 1 < (int)kLutSlots) lut_col<D, R, T_I64, R, 0>(buf + 2 * k, C, a, V, lds, P, acc);
+          if constexpr (k + 1 < (int)kLutSlots) lut_col<D, R, T_I64, R, 0>(buf + 2 * k, d, a, V, lds, P, acc);
           break;
       }
     });
@@ -2038,7 +2140,7 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
 // from device memory when it moves to that pass.
 template <int D, int R>
 __global__ void __launch_bounds__(lut_block_for(D)) k_lbatch(LutArgs a) {
-  extern __shared__ uint32_t dyn[];
+  extern __shared__ __align__(16) uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
   const uint32_t nacc = a.acc_words;

@@ -33,8 +33,10 @@ constexpr size_t kMaxClauseLits = 16;     // literals of one clause
 constexpr uint32_t kMaxPassProgs = 32;    // program bits of a pass
 constexpr uint32_t kMaxPassCols = 16;
 constexpr uint32_t kMaxRankBounds = 32;
-// device-memory tables up to 64 MB (a 16 M-value window at one dword)
-constexpr uint64_t kMaxTableBytes = 64ull << 20;
+// device-memory tables up to 2 MB (a 512 K-value window at one dword): a
+// larger one misses the L2 on most lookups, where a bitmap leaf of the
+// leaf-major kernel (one bit per value) would not
+constexpr uint64_t kMaxTableBytes = 2ull << 20;
 // LDS of the kernel's workgroup: 160 KB less the per-program counters
 constexpr uint32_t kLutLdsWords = (kLdsPerCu - 4u * (uint32_t)kBatchMaxProgs) / 4u;
 

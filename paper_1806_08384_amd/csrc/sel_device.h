@@ -411,7 +411,6 @@ constexpr uint32_t kSlotHigh = 0x20;
 // (three per SIMD) with one or two accumulator dwords, eight with four
 // (more registers per lane)
 constexpr uint32_t lut_block_for(uint32_t dwords) { return dwords >= 4 ? 512u : 768u; }
-constexpr uint64_t kLutMaxRows = 64ull << 20;   // longest chunk given to the lookup-table kernel
 constexpr uint32_t kLutFlushTiles = 48;  // tiles between reads of the bit-plane counters
 
 struct LutArgs {

@@ -275,11 +275,7 @@ bool launch_round(sel_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     std::vector<const sel_program*> gp;
     std::vector<uint32_t> gacc;
-    // the lookup-table kernel when every chunk of the round is short (see
-    // BatchPlan::add)
-    bp.allow_lut = true;
-    for (auto& kv : s->tables)
-      if (!kv.second.progs.empty()) bp.allow_lut &= kv.second.chunk_rows <= kLutMaxRows;
+    bp.allow_lut = true;   // the lookup-table kernel for the programs it can express
     for (auto& kv : s->tables) {
       TableState& ts = kv.second;
       if (ts.progs.empty()) continue;
