@@ -681,7 +681,7 @@ void BatchPlan::write(uint8_t* host, char* dev, uint32_t* gtab_dev, BatchArgs& a
 }
 
 void BatchPlan::lut_shape(uint32_t dwords, uint32_t& grid, uint32_t& block) const {
-  block = lut_block_for(dwords);
+  block = sel_lbatch_block(dwords);
   // an override applies when its waves divide the tile padding of a pass
   if (lut_block && lut_block < block && lut_block % kWave == 0 && kLutTileAlign % (lut_block / kWave) == 0)
     block = lut_block;

@@ -1545,11 +1545,11 @@ __global__ void __launch_bounds__(256) k_luts(LutArgs a) {
   }
 }
 
-// Values of one lane's rows of one column in a segment: R = 8 rows (two
-// steps of the tile's row mapping) held from vector w[0]: step s of a narrow
+// Values of one lane's rows of one column in a segment: 4 S rows (S steps
+// of the tile's row mapping) held from vector w[0]: step s of a narrow
 // column in w[s] (its leading components); of an int64 column, rows 0 and 1
-// of step s in w[s] and rows 2 and 3 in w[2 + s] (the next slot).
-template <int TY>
+// of step s in w[s] and rows 2 and 3 in w[S + s] (the next slot).
+template <int TY, int S>
 __device__ __forceinline__ auto lget(const v4i* w, int s, int i) {
   if constexpr (TY == T_I8) {
     return (int32_t)(int8_t)((uint32_t)w[s][0] >> (8 * i));
@@ -1558,7 +1558,7 @@ __device__ __forceinline__ auto lget(const v4i* w, int s, int i) {
   } else if constexpr (TY == T_I32) {
     return (int32_t)w[s][i];
   } else {
-    const v4i& q = w[2 * (i >> 1) + s];   // rows 2, 3 in the next slot
+    const v4i& q = w[S * (i >> 1) + s];   // rows 2, 3 in the next slot
     const int k = 2 * (i & 1);
     return (int64_t)(((uint64_t)(uint32_t)q[k + 1] << 32) | (uint32_t)q[k]);
   }
@@ -1777,7 +1777,7 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const SlotD& sd, const L
         for (int s = 0; s < S; ++s)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const int32_t x = lget<TY>(seg, s, i);
+            const int32_t x = lget<TY, S>(seg, s, i);
             int32_t m;
             asm("v_med3_i32 %0, %1, %2, %3" : "=v"(m) : "v"(x), "s"(cl), "v"(chv));
             ent_or_lds<D>(l3 + (abase + (uint32_t)m * (4u * D)), acc[OFF + 4 * s + i]);
@@ -1795,7 +1795,7 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const SlotD& sd, const L
       for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int32_t x = lget<TY>(seg, s, i);
+          const int32_t x = lget<TY, S>(seg, s, i);
           idx[4 * s + i] = (uint32_t)min(max(x, cl), ch) - base;
         }
     } else {
@@ -1806,7 +1806,7 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const SlotD& sd, const L
       for (int s = 0; s < S; ++s)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int64_t x = lget<TY>(seg, s, i);
+          const int64_t x = lget<TY, S>(seg, s, i);
           const int64_t m = x < cl ? cl : x > ch ? ch : x;
           idx[4 * s + i] = (uint32_t)((uint64_t)m - base);
         }
@@ -1833,8 +1833,8 @@ __device__ __forceinline__ void lut_col(const v4i* seg, const SlotD& sd, const L
         for (int s = 0; s < S; ++s)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            if constexpr (TY != T_I64) idx[4 * s + i] += lget<TY>(seg, s, i) >= (int32_t)bb[j] ? 1u : 0u;
-            else idx[4 * s + i] += lget<TY>(seg, s, i) >= bb[j] ? 1u : 0u;
+            if constexpr (TY != T_I64) idx[4 * s + i] += lget<TY, S>(seg, s, i) >= (int32_t)bb[j] ? 1u : 0u;
+            else idx[4 * s + i] += lget<TY, S>(seg, s, i) >= bb[j] ? 1u : 0u;
           }
       }
     }
@@ -2067,17 +2067,18 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
-// Every column of a pass on one tile, in segments of R = 8 rows per lane:
-// the loads of all the segment's data columns and of their validity words
-// are issued together, unconditionally, into register slots of two vectors
-// (an int64 column takes two slots), so that a wave keeps every column of
-// its segment in flight; other waves hide the latency while it waits.  Rows
-// past the table read zeros or neighbouring values and are not counted.
+// Every column of a pass on one tile, in segments of R = 4 S rows per lane
+// (S steps): the loads of all the segment's data columns and of their
+// validity words are issued together, unconditionally, into register slots
+// of S vectors (an int64 column takes two slots), so that a wave keeps
+// every column of its segment in flight; other waves hide the latency while
+// it waits.  Rows past the table read zeros or neighbouring values and are
+// not counted.
 template <int D, int R>
 __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTANT LutCol* cols,
                                          const LutArgs& a, uint64_t tb, uint32_t lane,
                                          const uint32_t* lds, Hs& hs) {
-  static_assert(R == 8, "segments of two steps");
+  static_assert(R == 4 || R == 8, "segments of one or two steps");
   constexpr int S = R / 4, NSEG = kSteps / S;
   const bool full = tb + kTileRows <= P->nrows;
   const uint64_t nrows = P->nrows;
@@ -2085,7 +2086,7 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
   const CONSTANT LutCol* cb = cols + P->col_begin;
   uint32_t acc[R][D];
   uint32_t inr;
-  v4i buf[2 * kLutSlots];
+  v4i buf[S * kLutSlots];
   uint32_t vr[kLutSlots][S];
   // decoded once per tile (what does not fit in scalar registers moves to
   // lanes of vector registers, cheaper than reloading it per segment)
@@ -2100,7 +2101,7 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
       constexpr int k = decltype(kc)::value;
       const uint32_t ty = sd[k].info & 15u;
       const uint32_t width = ty == T_I8 ? 1u : ty == T_I16 ? 2u : ty == T_I32 ? 4u : 8u;
-      slot_issue<S>(buf + 2 * k,
+      slot_issue<S>(buf + S * k,
                     __builtin_amdgcn_make_buffer_rsrc((void*)sd[k].data, (short)0, (int)sd[k].bytes, 0x00020000),
                     width, j0, lane);
       const __amdgpu_buffer_rsrc_t vrs =
@@ -2121,11 +2122,11 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
         for (int st = 0; st < S; ++st) V |= ((vr[k][st] >> (4 * (lane & 7))) & 0xFu) << (4 * st);
       }
       switch (d.info & 15u) {
-        case T_I8: lut_col<D, R, T_I8, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
-        case T_I16: lut_col<D, R, T_I16, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
-        case T_I32: lut_col<D, R, T_I32, R, 0>(buf + 2 * k, d, a, V, lds, P, acc); break;
+        case T_I8: lut_col<D, R, T_I8, R, 0>(buf + S * k, d, a, V, lds, P, acc); break;
+        case T_I16: lut_col<D, R, T_I16, R, 0>(buf + S * k, d, a, V, lds, P, acc); break;
+        case T_I32: lut_col<D, R, T_I32, R, 0>(buf + S * k, d, a, V, lds, P, acc); break;
         default:
-          if constexpr (k + 1 < (int)kLutSlots) lut_col<D, R, T_I64, R, 0>(buf + 2 * k, d, a, V, lds, P, acc);
+          if constexpr (k + 1 < (int)kLutSlots) lut_col<D, R, T_I64, R, 0>(buf + S * k, d, a, V, lds, P, acc);
           break;
       }
     });
@@ -2138,8 +2139,14 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
 // moves the finished lines out.  The workgroup takes groups of nw tiles
 // (pass ranges are padded to kLutTileAlign), and copies a pass's LDS tables
 // from device memory when it moves to that pass.
+// Workgroup of the lookup-table kernel (one per CU, whose LDS it takes):
+// twelve waves, three per SIMD; with four accumulator dwords the segments
+// hold four rows per lane instead of eight so that the registers still fit.
+template <int D>
+constexpr uint32_t lbatch_threads() { return 768u; }
+
 template <int D, int R>
-__global__ void __launch_bounds__(lut_block_for(D)) k_lbatch(LutArgs a) {
+__global__ void __launch_bounds__(lbatch_threads<D>()) k_lbatch(LutArgs a) {
   extern __shared__ __align__(16) uint32_t dyn[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t nw = blockDim.x >> 6;
@@ -2333,18 +2340,22 @@ const void* lbatch_kernel(uint32_t dwords) {
   switch (dwords) {
     case 1: return (const void*)k_lbatch<1, 8>;
     case 2: return (const void*)k_lbatch<2, 8>;
-    default: return (const void*)k_lbatch<4, 8>;
+    default: return (const void*)k_lbatch<4, 4>;   // four rows per lane: twelve waves fit
   }
 }
 }  // namespace
 
 int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
                       void* stream) {
-  if (block == 0 || block > lut_block_for(dwords) || block % kWave) return (int)hipErrorInvalidValue;
+  if (block == 0 || block > sel_lbatch_block(dwords) || block % kWave) return (int)hipErrorInvalidValue;
   LutArgs args = a;
   void* kargs[] = {&args};
   return (int)hipLaunchKernel(lbatch_kernel(dwords), dim3(grid), dim3(block), kargs, lds_bytes,
                               (hipStream_t)stream);
+}
+
+uint32_t sel_lbatch_block(uint32_t dwords) {
+  return dwords == 1 ? lbatch_threads<1>() : dwords == 2 ? lbatch_threads<2>() : lbatch_threads<4>();
 }
 
 int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {

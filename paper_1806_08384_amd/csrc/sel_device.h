@@ -407,10 +407,7 @@ constexpr uint32_t kLutSlots = 8;        // register slots of two vectors per se
 constexpr uint32_t kNoSlotCol = 0xFF;
 constexpr uint32_t kSlotColMask = 0x1F;
 constexpr uint32_t kSlotHigh = 0x20;
-// workgroup of the lookup-table kernel, one per CU (its LDS): twelve waves
-// (three per SIMD) with one or two accumulator dwords, eight with four
-// (more registers per lane)
-constexpr uint32_t lut_block_for(uint32_t dwords) { return dwords >= 4 ? 512u : 768u; }
+
 constexpr uint32_t kLutFlushTiles = 48;  // tiles between reads of the bit-plane counters
 
 struct LutArgs {
@@ -456,8 +453,10 @@ int sel_launch_batch(const sel::BatchArgs& a, uint32_t grid, uint32_t block, uin
                      void* stream);
 int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 // Table builds, then the lookup-table batch kernel over the passes with
-// `dwords` accumulator dwords per row (block at most lut_block_for(dwords)).
+// `dwords` accumulator dwords per row (block at most sel_lbatch_block(dwords),
+// the kernel's own workgroup: one per CU, whose LDS it takes).
 int sel_launch_luts(const sel::LutArgs& a, void* stream);
+uint32_t sel_lbatch_block(uint32_t dwords);
 int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
                       void* stream);
 int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
