@@ -412,6 +412,15 @@ __device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64
 }
 
 // ------------------------------------------------------------ reductions --
+// Wait until this thread's earlier memory operations, atomics included,
+// have completed.  The end-of-launch ticket hand-offs below need no more:
+// what one workgroup passes to the last one travels only through
+// device-scope atomics, which are coherent by themselves, so the cache
+// write-back and invalidation of a device-scope fence (issued by every
+// workgroup, tens of microseconds at the end of a short scan) are not
+// needed.  Plain stores (results, masks) are read after the launch.
+__device__ __forceinline__ void atomics_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // Sum over the 64 lanes: DPP within quads and 16-lane rows, then the four
 // row sums by readlane.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -437,15 +446,14 @@ __device__ void finish(DevSlot* slot, unsigned long long* out, uint32_t c0, uint
     for (uint32_t w = 0; w < (blockDim.x >> 6); ++w) { b0 += red0[w]; b1 += red1[w]; }
     if (b0) atomicAdd(&slot->acc, b0);
     if (b1) atomicAdd(&slot->acc2, b1);
-    __threadfence();
+    atomics_done();
     const unsigned int ticket = atomicAdd(&slot->ticket, 1u);
     if (ticket == gridDim.x - 1) {
-      __threadfence();
       out[0] = atomicAdd(&slot->acc, 0ull);
       if (two) out[1] = atomicAdd(&slot->acc2, 0ull);
       atomicExch(&slot->acc, 0ull);
       atomicExch(&slot->acc2, 0ull);
-      __threadfence();
+      atomics_done();
       atomicExch(&slot->ticket, 0u);
     }
   }
@@ -1389,7 +1397,7 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < nacc; p += blockDim.x)
     if (acc[p]) atomicAdd(&a.acc[(uint64_t)progs[p].acc_index * kBatchAccStride], (unsigned long long)acc[p]);
-  __threadfence();
+  atomics_done();
   __syncthreads();
   __shared__ bool last;
   if (threadIdx.x == 0) {
@@ -1398,12 +1406,11 @@ __global__ void __launch_bounds__(768) k_batch(BatchArgs a) {
   }
   __syncthreads();
   if (last) {
-    __threadfence();
     for (uint32_t k = threadIdx.x; k < a.ndone; k += blockDim.x) {
       const uint64_t line = a.done ? a.done[k] : k;
       a.out[k] = atomicExch(&a.acc[line * kBatchAccStride], 0ull);
     }
-    __threadfence();
+    atomics_done();
     __syncthreads();
     if (threadIdx.x == 0) atomicExch(&a.slot->ticket, 0u);
   }
@@ -2205,7 +2212,7 @@ __global__ void __launch_bounds__(lbatch_threads<D>()) k_lbatch(LutArgs a) {
   __syncthreads();
   for (uint32_t p = threadIdx.x; p < nacc && p < a.nprogs; p += blockDim.x)
     if (accl[p]) atomicAdd(&a.acc[(uint64_t)a.acc_index[p] * kBatchAccStride], (unsigned long long)accl[p]);
-  __threadfence();
+  atomics_done();
   __syncthreads();
   __shared__ bool last;
   if (threadIdx.x == 0) {
@@ -2214,12 +2221,11 @@ __global__ void __launch_bounds__(lbatch_threads<D>()) k_lbatch(LutArgs a) {
   }
   __syncthreads();
   if (last) {
-    __threadfence();
     for (uint32_t k = threadIdx.x; k < a.ndone; k += blockDim.x) {
       const uint64_t line = a.done ? a.done[k] : k;
       a.out[k] = atomicExch(&a.acc[line * kBatchAccStride], 0ull);
     }
-    __threadfence();
+    atomics_done();
     __syncthreads();
     if (threadIdx.x == 0) atomicExch(&a.slot->ticket, 0u);
   }
