@@ -422,24 +422,34 @@ def bench_estimate_error(ctx, small, fact_dt, log):
 
 
 def bench_autotune(ctx, dt, tree, small, log):
-    """The launch-shape tuner (workgroup size and count, per kernel, program
-    class and table size) on the step's scans and on the 64-program batch,
-    beside the default shapes measured above.  It runs last: the tuned
-    shapes stay on the context."""
+    """The tuner (per kernel, program class and table size: workgroup size
+    and count, then cached or nontemporal loads, tiles per wave step and the
+    LDS staging limit for the scans, rows per lane for the lookup-table
+    batch kernel) on the step's scans and on the 64-program batch, beside
+    the defaults measured above; each knob's pick is reported with whether
+    the library default already equals it.  It runs last: the tuned
+    configurations stay on the context."""
     import datagen
     from paper_1806_08384_amd import sel
     prog = ctx.program(dt, tree)
     out = {}
+    # the library defaults for a scan: 256-thread workgroups, 12 resident
+    # waves per CU, nontemporal loads, one tile per step, all staging
+    default_scan = {"block": 256, "grid": 3 * ctx.num_cus, "cached": 0, "tiles_per_step": 1, "stage_words": 0}
     for name, mask in (("k_scan<M_MASK>", True), ("k_scan<M_COUNT>", False)):
-        (block, grid), ms = ctx.autotune(dt, prog, with_mask=mask, reps=5)
-        out[name] = {"block": block, "grid": grid, "tuned_kernel_ms": ms}
-        log(f"autotune {name}: block {block}, grid {grid}, {ms:.3f} ms")
+        cfg, ms = ctx.autotune(dt, prog, with_mask=mask, reps=5)
+        pick = {k: getattr(cfg, k) for k in ("block", "grid", "cached", "tiles_per_step", "stage_words")}
+        out[name] = {**pick, "tuned_kernel_ms": ms,
+                     "default_is_pick": {k: default_scan[k] == v for k, v in pick.items()}}
+        log(f"autotune {name}: {pick}, {ms:.3f} ms")
     if small is not None:
         dts = list(small) + [dt]
         pairs = [(dts[t], ctx.program(dts[t], tr)) for t, tr in datagen.cfg3_programs()]
-        (block, grid), ms = ctx.autotune_batch(pairs, reps=3)
-        out["k_batch (64 programs, eager call)"] = {"block": block, "grid": grid, "tuned_call_ms": ms}
-        log(f"autotune batch: block {block}, grid {grid}, {ms:.3f} ms")
+        cfg, ms = ctx.autotune_batch(pairs, reps=3)
+        pick = {"block": cfg.block, "grid": cfg.grid, "rows_per_lane": cfg.rows_per_lane or 8}
+        out["batch (64 programs, eager call)"] = {**pick, "tuned_call_ms": ms,
+                                                  "default_is_pick": {"rows_per_lane": pick["rows_per_lane"] == 8}}
+        log(f"autotune batch: {pick}, {ms:.3f} ms")
     return out
 
 

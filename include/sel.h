@@ -536,32 +536,49 @@ void sel_server_destroy(sel_server* s);
 /* ---- launch configuration and timing ------------------------------------ */
 
 typedef struct sel_launch {
-  uint32_t block;        /* threads per workgroup: 64, 128 or 256 */
-  uint32_t grid;         /* workgroups; 0 = library default                   */
+  uint32_t block;          /* threads per workgroup: 64, 128 or 256 (scans)   */
+  uint32_t grid;           /* workgroups; 0 = library default                  */
+  uint32_t cached;         /* scans: 1 = column loads through the caches,
+                              0 = nontemporal loads (the default)             */
+  uint32_t tiles_per_step; /* scans: consecutive 2048-row tiles a wave takes
+                              per step, 1, 2 or 4 (0 = 1)                     */
+  uint32_t stage_words;    /* scans: most LDS words of the program's bitmaps
+                              and IN lists copied to LDS first (0 = all that
+                              fit 32 KB; 1 = none)                            */
+  uint32_t rows_per_lane;  /* lookup-table batch kernel: rows per lane per
+                              segment, 4 or 8 (0 = 8; four-dword passes
+                              always take 4)                                  */
 } sel_launch;
 
-/* Override (or with NULL, restore) the launch shape used by the scan kernels
- * of this context.  Errors: SEL_E_INVALID for an unsupported block size. */
+/* Override (or with NULL, restore) the launch configuration used by the
+ * scan kernels of this context.  Errors: SEL_E_INVALID for an unsupported
+ * block size, tiles_per_step or rows_per_lane. */
 sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch);
 
 /* ---- autotuning (offline: launches real kernels; not for the latency path) */
 
-/* Time every candidate launch shape (workgroups of 64/128/256 threads, 4..32
- * resident waves per CU) of the count scan (with_mask = 0) or the
- * count + mask scan (with_mask != 0) of `prog` on `table`, `reps` times each
- * (0 = 5), and record the fastest (median) for this program class (bytes
- * per row, length) and table size on the context; later calls with no fixed
- * shape use it.  *best / *best_ms (either may be NULL) receive the winner. */
+/* Time the count scan (with_mask = 0) or the count + mask scan
+ * (with_mask != 0) of `prog` on `table`, `reps` times each (0 = 5): first
+ * every launch shape (workgroups of 64/128/256 threads, 4..32 resident
+ * waves per CU), then, with the fastest shape, cached against nontemporal
+ * loads, then 1, 2 or 4 tiles per step, then the LDS staging limit (all,
+ * 2048 words, none) -- one knob at a time, each kept at its fastest
+ * (median).  The result is recorded for this program class (bytes per row,
+ * length) and table size on the context; later calls with no fixed
+ * configuration use it.  *best / *best_ms (either may be NULL) receive it. */
 sel_status sel_autotune(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
                         int with_mask, uint32_t reps, sel_launch* best, double* best_ms);
 
-/* Same for the batched count of these n pairs (see sel_count_batch), with
- * workgroups of 64 to 768 threads whose LDS fits the batch's plan. */
+/* Same for the batched count of these n pairs (see sel_count_batch): the
+ * leaf-major kernel's workgroups of 64 to 768 threads whose LDS fits the
+ * batch's plan, then the lookup-table kernel's rows per lane (4 or 8). */
 sel_status sel_autotune_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,
                               const sel_program* const* progs, uint32_t reps,
                               sel_launch* best, double* best_ms);
 
-/* Save / load the context's tuned shapes as text ("key block grid" lines;
+/* Save / load the context's tuned configurations as text ("key block grid
+ * cached tiles_per_step stage_words rows_per_lane" lines, or the older
+ * "key block grid" ones;
  * grids are rescaled if the file was written on a device with another
  * number of CUs).  sel_ctx_create loads the file named by the environment
  * variable SEL_TUNE_CACHE, if set. */

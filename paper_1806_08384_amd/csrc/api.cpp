@@ -110,24 +110,22 @@ uint64_t tune_key(int kind, uint32_t cls, uint64_t ntiles) {
   return (uint64_t)kind | ((uint64_t)cls << 4) | ((uint64_t)lg << 24);
 }
 
-// Launch shape of a scan over ntiles wave tiles: a fixed shape if the
-// caller set one, else the tuned shape of this (kernel, program class,
-// size) if the tuner recorded one, else 12 resident waves per CU (the
-// tuner's choice for the 300M-row fact-table scan: 16 or more measured
-// slower).
-void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
+// Launch configuration of a scan over ntiles wave tiles: fixed if the
+// caller set one, else the tuned one of this (kernel, program class, size)
+// if the tuner recorded one, else the defaults: 12 resident waves per CU,
+// nontemporal loads, one tile per step, every planned bitmap staged (the
+// tuner's choices for the 300M-row fact-table scans).
+void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, sel_launch& cfg, uint32_t& grid,
                 uint32_t& block) {
-  block = ctx->launch.block;
-  uint64_t g = 0;
+  cfg = kDefaultLaunch;
   if (ctx->launch_fixed) {
-    g = ctx->launch.grid;
+    cfg = ctx->launch;
   } else {
     auto it = ctx->tune.find(tune_key(mode, cls, ntiles));
-    if (it != ctx->tune.end()) {
-      block = it->second.block;
-      g = it->second.grid;
-    }
+    if (it != ctx->tune.end()) cfg = it->second;
   }
+  block = cfg.block;
+  uint64_t g = cfg.grid;
   if (g == 0) {
     int occ = 0;
     if (block == 256) {
@@ -157,9 +155,14 @@ bool check_prog(sel_ctx* ctx, const sel_table* t, const sel_program* p) {
   return true;
 }
 
-sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, ScanArgs& a, int kind, bool timed) {
+sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, ScanArgs& a, int kind, bool timed,
+                    const std::vector<uint32_t>* stage_end) {
   uint32_t grid, block;
-  scan_shape(ctx, mode, cls, a.ntiles, grid, block);
+  sel_launch cfg;
+  scan_shape(ctx, mode, cls, a.ntiles, cfg, grid, block);
+  a.cached = cfg.cached;
+  a.tiles_per_step = cfg.tiles_per_step ? cfg.tiles_per_step : 1;
+  if (stage_end) limit_stage(a, *stage_end, cfg.stage_words);
   a.slot = ctx->slot;
   TimedLaunch tl(ctx, kind, timed);
   int e = sel_launch_scan(mode, a, grid, block, ctx->stream);
@@ -246,7 +249,7 @@ sel_status pushdown_rowids_with(sel_ctx* ctx, const sel_table* table, const sel_
   a.mask = mask;
   a.tile_lanes = lanes;
   a.tile_counts = counts;
-  st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK, timed);
+  st = run_scan(ctx, M_MASK, prog->tune_class, a, SEL_K_MASK, timed, &prog->stage_end);
   if (st != SEL_OK) return st;
   // the scan of tile counts and the compaction are enqueued at once; the
   // compaction reads the published count and writes nothing if it exceeds
@@ -389,12 +392,16 @@ uint32_t sel_ctx_num_cus(const sel_ctx* ctx) { return ctx ? ctx->num_cus : 0; }
 sel_status sel_ctx_set_launch(sel_ctx* ctx, const sel_launch* launch) {
   if (!ctx) return SEL_E_INVALID;
   if (!launch) {
-    ctx->launch = sel_launch{256, 0};
+    ctx->launch = kDefaultLaunch;
     ctx->launch_fixed = false;
     return SEL_OK;
   }
   if (launch->block != 64 && launch->block != 128 && launch->block != 256)
     return set_err(ctx, SEL_E_INVALID, "block must be 64, 128 or 256");
+  if (launch->tiles_per_step > 4 || launch->tiles_per_step == 3)
+    return set_err(ctx, SEL_E_INVALID, "tiles_per_step must be 0, 1, 2 or 4");
+  if (launch->rows_per_lane != 0 && launch->rows_per_lane != 4 && launch->rows_per_lane != 8)
+    return set_err(ctx, SEL_E_INVALID, "rows_per_lane must be 0, 4 or 8");
   ctx->launch = *launch;
   ctx->launch_fixed = true;
   return SEL_OK;
@@ -505,6 +512,7 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   std::vector<BatchBitmap> stage;
   p->stage_words = plan_scan_stage(L.code, stage);
   p->nstage = (uint32_t)stage.size();
+  for (const BatchBitmap& b : stage) p->stage_end.push_back(b.lds_word + b.words + 1);
   const size_t total = code_bytes + blob_bytes + stage.size() * sizeof(BatchBitmap);
   p->dev = ctx->arena.alloc(total);
   if (!p->dev) {
@@ -577,7 +585,7 @@ sel_status sel_count_async(sel_ctx* ctx, const sel_table* table, const sel_progr
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = (unsigned long long*)d_count;
-  return run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT);
+  return run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT, true, &prog->stage_end);
 }
 
 sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* prog,
@@ -592,7 +600,7 @@ sel_status sel_count(sel_ctx* ctx, const sel_table* table, const sel_program* pr
   a.nrows = table->nrows;
   a.ntiles = ntiles_of(table->nrows);
   a.out = ctx->dout;
-  sel_status st = run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT);
+  sel_status st = run_scan(ctx, M_COUNT, prog->tune_class, a, SEL_K_COUNT, true, &prog->stage_end);
   if (st != SEL_OK) return st;
   return read_out(ctx, out_count, nullptr);
 }
@@ -673,7 +681,8 @@ sel_status sel_pushdown_keybitmap(sel_ctx* ctx, const sel_table* dim, uint32_t k
   a.key_min = key_min;
   a.nbits = nbits;
   a.bitmap = d_bitmap;
-  sel_status st = run_scan(ctx, M_KEYBITMAP, prog ? prog->tune_class : 0, a, SEL_K_KEYBITMAP);
+  sel_status st = run_scan(ctx, M_KEYBITMAP, prog ? prog->tune_class : 0, a, SEL_K_KEYBITMAP, true,
+                           prog ? &prog->stage_end : nullptr);
   if (st != SEL_OK) return st;
   uint64_t count = 0, oor = 0;
   st = read_out(ctx, &count, &oor);
@@ -830,7 +839,9 @@ sel_status sel_star_count(sel_ctx* ctx, const sel_table* fact, const sel_program
   a.nrows = fact->nrows;
   a.ntiles = ntiles_of(fact->nrows);
   a.out = ctx->dout;
-  st = run_scan(ctx, M_COUNT, tune_class_of(bpr, a.nins), a, SEL_K_STAR);
+  std::vector<uint32_t> stage_end;
+  for (const BatchBitmap& b : stage) stage_end.push_back(b.lds_word + b.words + 1);
+  st = run_scan(ctx, M_COUNT, tune_class_of(bpr, a.nins), a, SEL_K_STAR, true, &stage_end);
   if (st != SEL_OK) return st;
   return read_out(ctx, out_count, nullptr);
 }
@@ -863,6 +874,7 @@ sel_status sel_program_star(sel_ctx* ctx, const sel_table* fact, const sel_progr
   std::vector<BatchBitmap> stage;
   p->stage_words = plan_scan_stage(code, stage);
   p->nstage = (uint32_t)stage.size();
+  for (const BatchBitmap& b : stage) p->stage_end.push_back(b.lds_word + b.words + 1);
   const size_t code_bytes = code.size() * sizeof(DevInstr);
   const size_t bytes = code_bytes + stage.size() * sizeof(BatchBitmap);
   p->dev = ctx->arena.alloc(bytes);

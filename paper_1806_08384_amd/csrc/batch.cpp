@@ -90,16 +90,20 @@ void batch_shape(sel_ctx* ctx, uint32_t nprogs, const BatchPlan& bp, uint32_t& g
                  uint32_t& block) {
   block = bp.default_block();
   uint64_t g = 0;
+  uint32_t rows = 0;
   if (ctx->launch_fixed) {
     block = ctx->launch.block;
     g = ctx->launch.grid;
+    rows = ctx->launch.rows_per_lane;
   } else {
     auto it = ctx->tune.find(tune_key(TK_BATCH, batch_class(nprogs), bp.total_tiles));
     if (it != ctx->tune.end()) {
       block = it->second.block;
       g = it->second.grid;
+      rows = it->second.rows_per_lane;
     }
   }
+  bp.lut_rows = rows == 4 ? 4u : 8u;
   if (bp.lds_bytes(block) > kLdsPerCu) {
     block = 512;
     g = 0;
@@ -216,6 +220,7 @@ sel_status rebuild(sel_batch* b) {
       lgrid = lgrid * 31u + g;
       lblock = lblock * 31u + bl;
     }
+  lblock = lblock * 31u + b->plan.lut_rows;
   const uint32_t llds = b->plan.lut.empty() ? 0u : b->plan.lut.lds_bytes();
   if (b->exec && std::memcmp(&a, &b->args, sizeof a) == 0 && grid == b->grid && block == b->block &&
       lds == b->lds && d_builds == b->d_builds && nbuilds == b->nbuilds &&

@@ -688,7 +688,7 @@ void BatchPlan::lut_shape(uint32_t dwords, uint32_t& grid, uint32_t& block) cons
   uint64_t g = lut_grid;
   if (g == 0) {
     int occ = 1;
-    if (sel_lbatch_occupancy(dwords, block, lut.lds_bytes(), &occ) != 0 || occ < 1) occ = 1;
+    if (sel_lbatch_occupancy(dwords, lut_rows, block, lut.lds_bytes(), &occ) != 0 || occ < 1) occ = 1;
     g = (uint64_t)occ * num_cus;
   }
   const uint64_t need = std::max<uint64_t>(1, lut.total_tiles / (block / kWave));
@@ -716,7 +716,7 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
       la.ndone = !leaf && d == last ? a.ndone : 0u;
       uint32_t lg, lb;
       lut_shape(d, lg, lb);
-      e = sel_launch_lbatch(la, d, lg, lb, lut.lds_bytes(), stream);
+      e = sel_launch_lbatch(la, d, lut_rows, lg, lb, lut.lds_bytes(), stream);
       if (e) return e;
     }
   }

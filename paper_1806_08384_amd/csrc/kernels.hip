@@ -76,31 +76,40 @@ template <> struct Raw<T_I16> { v2i w[kSteps]; };
 template <> struct Raw<T_I32> { v4i w[kSteps]; };
 template <> struct Raw<T_I64> { v4i w[kSteps]; };
 
-template <int TY>
+// A streamed load: nontemporal (NT, the default) or through the caches as
+// usual; which one is faster is left to the tuner.
+template <bool NT, class T>
+__device__ __forceinline__ T ldg(const GLOBAL T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <int TY, bool NT = true>
 __device__ __forceinline__ void load_full(Raw<TY>& r, const void* data, uint64_t tb, uint32_t lane) {
   if constexpr (TY == T_I8) {
     const GLOBAL uint32_t* p = gptr<uint32_t>((const int8_t*)data + tb) + lane;
 #pragma unroll
-    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+    for (int j = 0; j < kSteps; ++j) r.w[j] = ldg<NT>(p + 64 * j);
   } else if constexpr (TY == T_I16) {
     const GLOBAL v2i* p = gptr<v2i>((const int16_t*)data + tb) + lane;
 #pragma unroll
-    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+    for (int j = 0; j < kSteps; ++j) r.w[j] = ldg<NT>(p + 64 * j);
   } else if constexpr (TY == T_I32) {
     const GLOBAL v4i* p = gptr<v4i>((const int32_t*)data + tb) + lane;
 #pragma unroll
-    for (int j = 0; j < kSteps; ++j) r.w[j] = __builtin_nontemporal_load(p + 64 * j);
+    for (int j = 0; j < kSteps; ++j) r.w[j] = ldg<NT>(p + 64 * j);
   }
 }
 
 // one half (steps 4h .. 4h+3) of an int64 column
+template <bool NT = true>
 __device__ __forceinline__ void load_half64(Raw<T_I64>& r, const void* data, uint64_t tb,
                                             uint32_t lane, int h) {
   const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * 4 * h;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    r.w[2 * j] = __builtin_nontemporal_load(p + 128 * j);
-    r.w[2 * j + 1] = __builtin_nontemporal_load(p + 128 * j + 1);
+    r.w[2 * j] = ldg<NT>(p + 128 * j);
+    r.w[2 * j + 1] = ldg<NT>(p + 128 * j + 1);
   }
 }
 
@@ -137,7 +146,7 @@ __device__ __forceinline__ uint64_t row_of(uint64_t tb, uint32_t lane, int b) {
 // Predicate bits of one lane's 32 rows: bit b = pred(value of row b).  The
 // word is built highest row first as P = 2P + bit, one add-with-carry per
 // row after the compare.
-template <int TY, bool FULL, class Pred>
+template <int TY, bool FULL, bool NT = true, class Pred>
 __device__ __forceinline__ uint32_t pred_bits(const void* data, uint64_t tb, uint32_t lane,
                                               uint64_t nrows, Pred pred) {
   uint32_t P = 0;
@@ -145,13 +154,13 @@ __device__ __forceinline__ uint32_t pred_bits(const void* data, uint64_t tb, uin
 #pragma unroll
     for (int h = 1; h >= 0; --h) {
       Raw<TY> r;
-      load_half64(r, data, tb, lane, h);
+      load_half64<NT>(r, data, tb, lane, h);
 #pragma unroll
       for (int b = 15; b >= 0; --b) P = (P << 1) + (uint32_t)pred(get<TY>(r, b), 16 * h + b);
     }
   } else if constexpr (FULL) {
     Raw<TY> r;
-    load_full<TY>(r, data, tb, lane);
+    load_full<TY, NT>(r, data, tb, lane);
 #pragma unroll
     for (int b = 31; b >= 0; --b) P = (P << 1) + (uint32_t)pred(get<TY>(r, b), b);
   } else {
@@ -194,7 +203,7 @@ __device__ __forceinline__ uint32_t inrange_bits(uint64_t tb, uint32_t lane, uin
 // LDS or device memory): wide loads of the column as for a range test, then
 // a branch-free lower bound that moves the eight rows of two steps one
 // search step at a time, so that their list reads are in flight together.
-template <int TY, bool FULL, class List>
+template <int TY, bool FULL, bool NT = true, class List>
 __device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, uint32_t lane,
                                                 uint64_t nrows, List list, uint32_t n, uint32_t need) {
   uint32_t P = 0;
@@ -206,20 +215,20 @@ __device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, u
       for (int js = 0; js < 2; ++js) {
         const int j = 2 * q + js;
         if constexpr (TY == T_I8) {
-          const uint32_t w = __builtin_nontemporal_load(gptr<uint32_t>((const int8_t*)data + tb) + lane + 64 * j);
+          const uint32_t w = ldg<NT>(gptr<uint32_t>((const int8_t*)data + tb) + lane + 64 * j);
 #pragma unroll
           for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int8_t)(w >> (8 * i));
         } else if constexpr (TY == T_I16) {
-          const v2i w = __builtin_nontemporal_load(gptr<v2i>((const int16_t*)data + tb) + lane + 64 * j);
+          const v2i w = ldg<NT>(gptr<v2i>((const int16_t*)data + tb) + lane + 64 * j);
 #pragma unroll
           for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int16_t)((uint32_t)w[i >> 1] >> (16 * (i & 1)));
         } else if constexpr (TY == T_I32) {
-          const v4i w = __builtin_nontemporal_load(gptr<v4i>((const int32_t*)data + tb) + lane + 64 * j);
+          const v4i w = ldg<NT>(gptr<v4i>((const int32_t*)data + tb) + lane + 64 * j);
 #pragma unroll
           for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)w[i];
         } else {
           const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * j;
-          const v4i w0 = __builtin_nontemporal_load(p), w1 = __builtin_nontemporal_load(p + 1);
+          const v4i w0 = ldg<NT>(p), w1 = ldg<NT>(p + 1);
           x[4 * js + 0] = (int64_t)(((uint64_t)(uint32_t)w0[1] << 32) | (uint32_t)w0[0]);
           x[4 * js + 1] = (int64_t)(((uint64_t)(uint32_t)w0[3] << 32) | (uint32_t)w0[2]);
           x[4 * js + 2] = (int64_t)(((uint64_t)(uint32_t)w1[1] << 32) | (uint32_t)w1[0]);
@@ -250,7 +259,7 @@ __device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, u
 }
 
 // ---------------------------------------------------------------- leaves --
-template <int TY, bool FULL>
+template <int TY, bool FULL, bool NT = true>
 __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
                                               uint64_t nrows, uint32_t need, const StageView& sv) {
   const void* data = I->data;
@@ -260,9 +269,9 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
     // the list's LDS copy if the scan staged it
     for (uint32_t k = 0; k < sv.n; ++k)
       if (sv.list[k].src == (const uint32_t*)I->aux)
-        return inlist_bits<TY, FULL>(data, tb, lane, nrows, (const int64_t*)(sv.lds + sv.list[k].lds_word),
+        return inlist_bits<TY, FULL, NT>(data, tb, lane, nrows, (const int64_t*)(sv.lds + sv.list[k].lds_word),
                                      I->n, need);
-    return inlist_bits<TY, FULL>(data, tb, lane, nrows, gptr<int64_t>(I->aux), I->n, need);
+    return inlist_bits<TY, FULL, NT>(data, tb, lane, nrows, gptr<int64_t>(I->aux), I->n, need);
   }
   if (op == D_BITMAP && sv.n) {
     uint32_t off = kNoLds, z = 0;
@@ -279,14 +288,14 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
       // int32 (the host stages only such bitmaps)
       const uint32_t* bm = sv.lds + off;
       if constexpr (TY == T_I64) {
-        return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
+        return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
           const uint64_t d = (uint64_t)x - (uint64_t)lo;
           const uint32_t k = ((need >> b) & 1u) && d < z ? (uint32_t)d : z;
           return (bm[k >> 5] >> (k & 31)) & 1u;
         });
       } else {
         const uint32_t lo32 = (uint32_t)lo;
-        return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
+        return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
           const uint32_t d = (uint32_t)x - lo32;
           const uint32_t k = ((need >> b) & 1u) && d < z ? d : z;
           return (bm[k >> 5] >> (k & 31)) & 1u;
@@ -296,12 +305,12 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
   }
   if (op == D_RANGE) {
     if constexpr (TY == T_I64) {
-      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int) {
+      return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int64_t x, int) {
         return (uint64_t)x - (uint64_t)lo <= span;
       });
     } else {
       const uint32_t lo32 = (uint32_t)lo, span32 = (uint32_t)span;
-      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int) {
+      return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int32_t x, int) {
         return (uint32_t)x - lo32 <= span32;
       });
     }
@@ -310,7 +319,7 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
     // word 0 and are masked: no branch, so all 32 lookups issue together
     const GLOBAL uint32_t* bits = gptr<uint32_t>(I->aux);
     if constexpr (TY == T_I64) {
-      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
+      return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int64_t x, int b) -> uint32_t {
         const uint64_t d = (uint64_t)x - (uint64_t)lo;
         const bool ok = d < span && ((need >> b) & 1u);
         const uint32_t k = ok ? (uint32_t)d : 0u;  // nbits <= 2^32
@@ -319,7 +328,7 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
     } else {
       // x - lo in 64 bits: a negative key must not alias a bit when nbits
       // exceeds 2^31
-      return pred_bits<TY, FULL>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
+      return pred_bits<TY, FULL, NT>(data, tb, lane, nrows, [=](int32_t x, int b) -> uint32_t {
         const uint64_t d = (uint64_t)((int64_t)x - lo);
         const bool ok = d < span && ((need >> b) & 1u);
         const uint32_t k = ok ? (uint32_t)d : 0u;
@@ -331,7 +340,7 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
   }
 }
 
-template <bool FULL>
+template <bool FULL, bool NT = true>
 __device__ __forceinline__ void eval_leaf(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
                                           uint64_t nrows, uint32_t tos_t, uint32_t tos_f,
                                           uint32_t& t, uint32_t& f, const StageView& sv) {
@@ -351,10 +360,10 @@ __device__ __forceinline__ void eval_leaf(uint32_t op, CInstr I, uint64_t tb, ui
   else if (flags & F_GUARD_OR) need = ~tos_t;
   uint32_t P;
   switch (I->type) {
-    case T_I8: P = leaf_pred<T_I8, FULL>(op, I, tb, lane, nrows, need, sv); break;
-    case T_I16: P = leaf_pred<T_I16, FULL>(op, I, tb, lane, nrows, need, sv); break;
-    case T_I32: P = leaf_pred<T_I32, FULL>(op, I, tb, lane, nrows, need, sv); break;
-    default: P = leaf_pred<T_I64, FULL>(op, I, tb, lane, nrows, need, sv); break;
+    case T_I8: P = leaf_pred<T_I8, FULL, NT>(op, I, tb, lane, nrows, need, sv); break;
+    case T_I16: P = leaf_pred<T_I16, FULL, NT>(op, I, tb, lane, nrows, need, sv); break;
+    case T_I32: P = leaf_pred<T_I32, FULL, NT>(op, I, tb, lane, nrows, need, sv); break;
+    default: P = leaf_pred<T_I64, FULL, NT>(op, I, tb, lane, nrows, need, sv); break;
   }
   t = P & V;
   f = ~P & V;
@@ -379,7 +388,7 @@ __device__ __forceinline__ void fill(const uint32_t (&st)[kMaxDepth], const uint
 }
 
 // TRUE bits of the lane's 32 rows of the tile starting at row tb.
-template <bool FULL>
+template <bool FULL, bool NT = true>
 __device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64_t tb,
                                               uint32_t lane, uint64_t nrows, const StageView& sv) {
   uint32_t st[kMaxDepth], sf[kMaxDepth];
@@ -392,7 +401,7 @@ __device__ __forceinline__ uint32_t eval_tile(CInstr prog, uint32_t nins, uint64
       uint32_t t, f;
       if (op == D_TRUE) { t = ~0u; f = 0; }
       else if (op == D_FALSE) { t = 0; f = ~0u; }
-      else eval_leaf<FULL>(op, I, tb, lane, nrows, tt, tf, t, f, sv);
+      else eval_leaf<FULL, NT>(op, I, tb, lane, nrows, tt, tf, t, f, sv);
       spill(st, sf, d - 1, tt, tf);
       tt = t; tf = f;
       ++d;
@@ -459,7 +468,7 @@ __device__ void finish(DevSlot* slot, unsigned long long* out, uint32_t c0, uint
   }
 }
 
-template <int MODE>
+template <int MODE, bool NT>
 __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_, ScanArgs a) {
   CInstr prog = (CInstr)prog_;
   const uint32_t lane = threadIdx.x & 63;
@@ -493,13 +502,17 @@ __global__ void __launch_bounds__(256) k_scan(const DevInstr* __restrict__ prog_
   int np = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) { pend[k] = 0; pidx[k] = 0; }
-  for (uint64_t tile = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)); tile < a.ntiles; tile += W) {
+  // each wave takes runs of tps consecutive tiles, W runs apart
+  const uint64_t tps = a.tiles_per_step ? a.tiles_per_step : 1;
+  const uint64_t wid = uni64((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6));
+  for (uint64_t step = wid * tps; step < a.ntiles; step += W * tps)
+  for (uint64_t tile = step; tile < step + tps && tile < a.ntiles; ++tile) {
     const uint64_t tb = tile * kTileRows;
     uint32_t T;
     if (tb + kTileRows <= a.nrows) {
-      T = eval_tile<true>(prog, a.nins, tb, lane, a.nrows, sv);
+      T = eval_tile<true, NT>(prog, a.nins, tb, lane, a.nrows, sv);
     } else {
-      T = eval_tile<false>(prog, a.nins, tb, lane, a.nrows, sv) & inrange_bits(tb, lane, a.nrows);
+      T = eval_tile<false, NT>(prog, a.nins, tb, lane, a.nrows, sv) & inrange_bits(tb, lane, a.nrows);
     }
     cnt += __builtin_popcount(T);
     if constexpr (MODE == M_MASK) {
@@ -2264,10 +2277,17 @@ int sel_noalloc_scratch(int device, void** ptr) {
 int sel_launch_scan(int mode, const ScanArgs& a, uint32_t grid, uint32_t block, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const uint32_t lds = a.nstage ? 4u * a.stage_words : 0u;
+  const bool nt = !a.cached;
   switch (mode) {
-    case M_COUNT: hipLaunchKernelGGL(k_scan<M_COUNT>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
-    case M_MASK: hipLaunchKernelGGL(k_scan<M_MASK>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
-    default: hipLaunchKernelGGL(k_scan<M_KEYBITMAP>, dim3(grid), dim3(block), lds, s, a.prog, a); break;
+    case M_COUNT:
+      if (nt) hipLaunchKernelGGL((k_scan<M_COUNT, true>), dim3(grid), dim3(block), lds, s, a.prog, a);
+      else hipLaunchKernelGGL((k_scan<M_COUNT, false>), dim3(grid), dim3(block), lds, s, a.prog, a);
+      break;
+    case M_MASK:
+      if (nt) hipLaunchKernelGGL((k_scan<M_MASK, true>), dim3(grid), dim3(block), lds, s, a.prog, a);
+      else hipLaunchKernelGGL((k_scan<M_MASK, false>), dim3(grid), dim3(block), lds, s, a.prog, a);
+      break;
+    default: hipLaunchKernelGGL((k_scan<M_KEYBITMAP, true>), dim3(grid), dim3(block), lds, s, a.prog, a); break;
   }
   return (int)hipGetLastError();
 }
@@ -2314,9 +2334,9 @@ int sel_launch_fill(uint32_t* p, uint64_t nwords, uint32_t value, void* stream) 
 int sel_scan_occupancy(int mode, uint32_t block, int* blocks_per_cu) {
   hipError_t e;
   switch (mode) {
-    case M_COUNT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_COUNT>, block, 0); break;
-    case M_MASK: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_MASK>, block, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_KEYBITMAP>, block, 0); break;
+    case M_COUNT: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_COUNT, true>, block, 0); break;
+    case M_MASK: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_MASK, true>, block, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_scan<M_KEYBITMAP, true>, block, 0); break;
   }
   return (int)e;
 }
@@ -2342,21 +2362,21 @@ int sel_launch_luts(const LutArgs& a, void* stream) {
 // The lookup-table kernel for passes of `dwords` accumulator dwords per row,
 // with `rows` rows per lane per segment (the larger choice, or half of it).
 namespace {
-const void* lbatch_kernel(uint32_t dwords) {
+const void* lbatch_kernel(uint32_t dwords, uint32_t rows) {
   switch (dwords) {
-    case 1: return (const void*)k_lbatch<1, 8>;
-    case 2: return (const void*)k_lbatch<2, 8>;
+    case 1: return rows == 4 ? (const void*)k_lbatch<1, 4> : (const void*)k_lbatch<1, 8>;
+    case 2: return rows == 4 ? (const void*)k_lbatch<2, 4> : (const void*)k_lbatch<2, 8>;
     default: return (const void*)k_lbatch<4, 4>;   // four rows per lane: twelve waves fit
   }
 }
 }  // namespace
 
-int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
-                      void* stream) {
+int sel_launch_lbatch(const LutArgs& a, uint32_t dwords, uint32_t rows, uint32_t grid, uint32_t block,
+                      uint32_t lds_bytes, void* stream) {
   if (block == 0 || block > sel_lbatch_block(dwords) || block % kWave) return (int)hipErrorInvalidValue;
   LutArgs args = a;
   void* kargs[] = {&args};
-  return (int)hipLaunchKernel(lbatch_kernel(dwords), dim3(grid), dim3(block), kargs, lds_bytes,
+  return (int)hipLaunchKernel(lbatch_kernel(dwords, rows), dim3(grid), dim3(block), kargs, lds_bytes,
                               (hipStream_t)stream);
 }
 
@@ -2364,6 +2384,7 @@ uint32_t sel_lbatch_block(uint32_t dwords) {
   return dwords == 1 ? lbatch_threads<1>() : dwords == 2 ? lbatch_threads<2>() : lbatch_threads<4>();
 }
 
-int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
-  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lbatch_kernel(dwords), block, lds_bytes);
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t rows, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+  return (int)hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, lbatch_kernel(dwords, rows), block,
+                                                           lds_bytes);
 }

@@ -106,7 +106,7 @@ struct sel_ctx {
                                            // workspace on this device
   size_t scratch_bytes = 0;
 
-  sel_launch launch{256, 0};
+  sel_launch launch{256, 0, 0, 1, 0, 0};
   bool launch_fixed = false;
   std::map<uint64_t, sel_launch> tune;     // autotuned launch shapes by class
   int occ[3] = {0, 0, 0};                  // blocks per CU per scan mode at 256 threads
@@ -135,6 +135,7 @@ struct sel_program {
   uintptr_t blob_dev = 0;           // their device address
   const sel::BatchBitmap* dstage = nullptr;   // bitmaps a scan stages in LDS
   uint32_t nstage = 0, stage_words = 0;
+  std::vector<uint32_t> stage_end;  // per staged bitmap: the LDS words up to its end
   uint32_t nins = 0;
   uint32_t tune_class = 0;          // bytes-per-row and length bucket
   int depth = 0;
@@ -179,10 +180,12 @@ inline uint32_t batch_class(uint32_t nprogs) {
   while ((1u << c) < nprogs) ++c;
   return c;
 }
-void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, uint32_t& grid,
+// The launch configuration a context uses when the caller fixed none.
+constexpr sel_launch kDefaultLaunch{256, 0, 0, 1, 0, 0};
+void scan_shape(sel_ctx* ctx, int mode, uint32_t cls, uint64_t ntiles, sel_launch& cfg, uint32_t& grid,
                 uint32_t& block);
 sel_status run_scan(sel_ctx* ctx, int mode, uint32_t cls, sel::ScanArgs& a, int kind,
-                    bool timed = true);
+                    bool timed = true, const std::vector<uint32_t>* stage_end = nullptr);
 
 // Byte layout of the row-id path's workspace for a table of ntiles tiles:
 // the packed mask words, tile counts, tile offsets, chunk sums, chunk
@@ -243,6 +246,7 @@ struct BatchPlan {
   mutable sel::LutArgs largs{};          // as written
   uint32_t num_cus = 256;
   uint32_t lut_block = 0, lut_grid = 0;  // 0: the defaults
+  mutable uint32_t lut_rows = 8;         // rows per lane per segment (four-dword passes: 4)
   std::vector<sel::BatchTable> entries;
   std::vector<sel::BatchCol> cols;
   std::vector<DevInstr> leaves;
@@ -308,6 +312,15 @@ inline void set_stage(sel::ScanArgs& a, const sel_program* p) {
   a.stage = p ? p->dstage : nullptr;
   a.nstage = p ? p->nstage : 0;
   a.stage_words = p ? p->stage_words : 0;
+}
+// Keep only the staged bitmaps that end within `limit` LDS words (a prefix:
+// they are placed in order); 0 keeps them all.
+inline void limit_stage(sel::ScanArgs& a, const std::vector<uint32_t>& stage_end, uint32_t limit) {
+  if (limit == 0) return;
+  uint32_t k = 0;
+  while (k < a.nstage && k < stage_end.size() && stage_end[k] <= limit) ++k;
+  a.nstage = k;
+  a.stage_words = k ? stage_end[k - 1] : 0;
 }
 
 sel_status plan_batch(sel_ctx* ctx, uint32_t n, const sel_table* const* tables,

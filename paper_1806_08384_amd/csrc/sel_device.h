@@ -83,6 +83,8 @@ struct ScanArgs {
   const DevInstr* prog;
   uint32_t nins;
   uint32_t nstage;             // bitmaps the workgroups copy to LDS first
+  uint32_t cached;             // 1: column loads through the caches (0: nontemporal)
+  uint32_t tiles_per_step;     // consecutive tiles a wave takes per step (0: 1)
   uint64_t nrows;
   uint64_t ntiles;
   DevSlot* slot;
@@ -457,7 +459,8 @@ int sel_batch_occupancy(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 // the kernel's own workgroup: one per CU, whose LDS it takes).
 int sel_launch_luts(const sel::LutArgs& a, void* stream);
 uint32_t sel_lbatch_block(uint32_t dwords);
-int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t grid, uint32_t block, uint32_t lds_bytes,
-                      void* stream);
-int sel_lbatch_occupancy(uint32_t dwords, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
+// `rows`: rows per lane per segment, 4 or 8 (four-dword passes take 4).
+int sel_launch_lbatch(const sel::LutArgs& a, uint32_t dwords, uint32_t rows, uint32_t grid, uint32_t block,
+                      uint32_t lds_bytes, void* stream);
+int sel_lbatch_occupancy(uint32_t dwords, uint32_t rows, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 }

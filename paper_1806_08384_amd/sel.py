@@ -10,6 +10,7 @@ there is no CPU fallback.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 import weakref
@@ -59,7 +60,16 @@ class sel_instr(ctypes.Structure):
 
 
 class sel_launch(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32)]
+    _fields_ = [("block", ctypes.c_uint32), ("grid", ctypes.c_uint32), ("cached", ctypes.c_uint32),
+                ("tiles_per_step", ctypes.c_uint32), ("stage_words", ctypes.c_uint32),
+                ("rows_per_lane", ctypes.c_uint32)]
+
+
+Launch = collections.namedtuple("Launch", "block grid cached tiles_per_step stage_words rows_per_lane")
+
+
+def _launch(l: sel_launch) -> Launch:
+    return Launch(l.block, l.grid, l.cached, l.tiles_per_step, l.stage_words, l.rows_per_lane)
 
 
 class sel_spd_relation(ctypes.Structure):
@@ -464,12 +474,12 @@ class Context:
         return Batch(self, pairs)
 
     def autotune(self, table, prog, with_mask=False, reps=5):
-        """Tune the scan's launch shape for this program class and table size;
-        returns ((block, grid), median ms)."""
+        """Tune the scan's launch configuration for this program class and
+        table size; returns (Launch, median ms)."""
         best, ms = sel_launch(), ctypes.c_double(0)
         self.check(sel_autotune(self.h, table.h, prog.h, 1 if with_mask else 0, reps,
                                 ctypes.byref(best), ctypes.byref(ms)))
-        return (best.block, best.grid), ms.value
+        return _launch(best), ms.value
 
     def autotune_batch(self, pairs, reps=3):
         n = len(pairs)
@@ -477,7 +487,7 @@ class Context:
         ps = (_vp * n)(*[p.h.value for _, p in pairs])
         best, ms = sel_launch(), ctypes.c_double(0)
         self.check(sel_autotune_batch(self.h, n, ts, ps, reps, ctypes.byref(best), ctypes.byref(ms)))
-        return (best.block, best.grid), ms.value
+        return _launch(best), ms.value
 
     def tune_save(self, path):
         self.check(sel_tune_save(self.h, str(path).encode()))
@@ -497,11 +507,12 @@ class Context:
     def server(self, **cfg):
         return Server(self, **cfg)
 
-    def set_launch(self, block=None, grid=0):
+    def set_launch(self, block=None, grid=0, cached=0, tiles_per_step=1, stage_words=0, rows_per_lane=0):
         if block is None:
             self.check(sel_ctx_set_launch(self.h, None))
         else:
-            self.check(sel_ctx_set_launch(self.h, ctypes.byref(sel_launch(block, grid))))
+            self.check(sel_ctx_set_launch(self.h, ctypes.byref(
+                sel_launch(block, grid, cached, tiles_per_step, stage_words, rows_per_lane))))
 
     def enable_timing(self, on=True):
         self.check(sel_ctx_enable_timing(self.h, 1 if on else 0))

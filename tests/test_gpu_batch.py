@@ -146,14 +146,30 @@ def test_batch_rejects_bad_input(sel, ctx, setup):
         ctx.count_batch([])
 
 
+def test_rows_per_lane_keeps_results(sel, ctx, setup):
+    """The lookup-table kernel with four or eight rows per lane per segment
+    gives the same exact counts."""
+    tables, dts, progs, pairs, want = setup
+    try:
+        for rows in (4, 8):
+            ctx.set_launch(256, 0, rows_per_lane=rows)
+            assert ctx.count_batch(pairs) == want, rows
+        with pytest.raises(sel.SelError):
+            ctx.set_launch(256, 0, rows_per_lane=5)
+    finally:
+        ctx.set_launch(None)
+
+
 def test_autotune_keeps_results(sel, ctx, setup, tmp_path):
     """Tuning changes launch shapes only: counts stay exact, and the tuned
     table survives a save/load round trip into a fresh context."""
     tables, dts, progs, pairs, want = setup
-    (block, grid), ms = ctx.autotune(*pairs[-1], with_mask=False, reps=2)
+    cfg, ms = ctx.autotune(*pairs[-1], with_mask=False, reps=2)
+    block, grid = cfg.block, cfg.grid
     assert block in (64, 128, 256) and grid > 0 and ms > 0
     ctx.autotune(*pairs[-1], with_mask=True, reps=2)
-    (bb, bg), bms = ctx.autotune_batch(pairs, reps=1)
+    bcfg, bms = ctx.autotune_batch(pairs, reps=1)
+    bb, bg = bcfg.block, bcfg.grid
     assert bb in (64, 128, 256, 512, 768) and bg > 0
     assert ctx.tune_entries >= 3
     assert ctx.count(*pairs[-1]) == want[-1]

@@ -228,6 +228,17 @@ def test_launch_shapes_agree(sel, ctx):
             cnt, ids = gpu_ids(sel, ctx, dt, prog, want)
             assert cnt == want
             np.testing.assert_array_equal(ids, want_ids)
+        # the tuner's other knobs: cached loads, runs of tiles per wave step
+        # (the last run cut at the table's end), LDS staging limited or off
+        for block, grid, cached, tps, stage in [(256, 0, 1, 1, 0), (64, 7, 0, 4, 0), (128, 33, 0, 2, 1),
+                                                (256, 3, 1, 4, 2048), (256, 0, 0, 2, 1)]:
+            ctx.set_launch(block, grid, cached=cached, tiles_per_step=tps, stage_words=stage)
+            assert ctx.count(dt, prog) == want, (block, grid, cached, tps, stage)
+            cnt, ids = gpu_ids(sel, ctx, dt, prog, want)
+            assert cnt == want
+            np.testing.assert_array_equal(ids, want_ids)
+        with pytest.raises(sel.SelError):
+            ctx.set_launch(256, 0, tiles_per_step=3)
     finally:
         ctx.set_launch(None)
 
