@@ -641,7 +641,7 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
     return res
 
 
-def bench_sweeps(ctx, dt, n, threads, log, reps=3):
+def bench_sweeps(ctx, dt, n, threads, log, in_lists, reps=3):
     """Count-kernel rate against selectivity and against the number of leaves
     on the 300M-row fact table (the analogues of the thesis' overhead versus
     selectivity and versus attribute count experiments), with the push-down
@@ -704,6 +704,21 @@ def bench_sweeps(ctx, dt, n, threads, log, reps=3):
                           "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS})
         log(f"sweep: {k} leaves, {bpr} B/row: count {kms:.3f} ms, {gbs:.0f} GB/s")
 
+    # sparse IN lists of 10, 100 and 1000 values on the int64 price column
+    # (5 % NULLs; half the values occur): sorted lists searched in the
+    # scan's LDS copy
+    in_rows = []
+    for k, values in sorted(in_lists.items()):
+        tree = ("in", 3, values)
+        prog = ctx.program(dt, tree)
+        c, kms = count_ms(dt, prog)
+        bpr = prog.bytes_per_row
+        gbs = n * bpr / kms / 1e6
+        in_rows.append({"list_values": k, "present_values": k // 2, "bytes_per_row": bpr, "selected_rows": c,
+                        "count_kernel_ms": kms, "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS})
+        log(f"sweep: int64 IN list of {k} values: {c} rows, {kms:.3f} ms, {gbs:.0f} GB/s")
+        prog.destroy()
+
     log("sweep: three uniform int32 columns at 300M rows")
     u = datagen.cfg1(n=300_000_000, threads=threads)
     du = sel.device_table(ctx, u)
@@ -715,7 +730,7 @@ def bench_sweeps(ctx, dt, n, threads, log, reps=3):
            "count_kernel_ms": kms, "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS}
     del du, prog
     torch.cuda.empty_cache()
-    return {"selectivity": sel_rows, "leaves": leaf_rows, "uniform3_300M": uni}
+    return {"selectivity": sel_rows, "leaves": leaf_rows, "in_list_int64": in_rows, "uniform3_300M": uni}
 
 
 def main():
@@ -883,12 +898,14 @@ def main():
             "per_workload": cpu_workloads(table, tree, threads, log),
         }
     table_cols = [(c.type, c.valid is not None, c.name) for c in table.columns]
+    # sparse IN lists for the sweep, drawn from the price column
+    in_lists = {k: datagen.sparse_in_values(table.col("price").data, k) for k in (10, 100, 1000)}
     del table
     if not args.no_extras:
         out["gather"] = bench_gather(ctx, dt, table_cols, log)
         out["achievable"] = bench_achievable(log)
     if not args.no_sweeps and not args.no_extras:
-        out["sweeps"] = bench_sweeps(ctx, dt, n, threads, log)
+        out["sweeps"] = bench_sweeps(ctx, dt, n, threads, log, in_lists)
     small = star = None
     if not args.no_batch:
         out["batch"], small = bench_batch(ctx, dt, threads, log)

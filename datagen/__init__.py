@@ -216,6 +216,17 @@ def cfg2(n: int = 300_000_000, seed: int = 2, threads=None) -> Table:
     return lineorder_like("cfg2", n, seed, threads)
 
 
+def sparse_in_values(col: np.ndarray, k: int, seed: int = 95, absent_lo: int = 10**7,
+                     absent_hi: int = 10**8) -> tuple:
+    """An IN list of k values too sparse for a bitmap: half drawn from the
+    first 10 M rows of `col` (so they occur), half from [absent_lo,
+    absent_hi) (above the log-normal price column's values), as a tuple."""
+    rng = np.random.default_rng(seed + k)
+    present = rng.choice(col[:10_000_000], k // 2, replace=False)
+    absent = rng.integers(absent_lo, absent_hi, k - k // 2)
+    return tuple(int(v) for v in np.concatenate([present, absent]))
+
+
 def cfg2_like_bitmap(seed: int = 6) -> np.ndarray:
     """A LIKE pattern on s4500 resolved to codes: bit c set iff
     rand(seed, 0, c) % 8 == 0."""

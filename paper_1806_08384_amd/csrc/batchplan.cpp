@@ -731,18 +731,21 @@ int BatchPlan::launch(const BatchArgs& a, const TableBuild* d_builds, uint32_t g
 uint32_t plan_scan_stage(const std::vector<DevInstr>& code, std::vector<BatchBitmap>& out) {
   out.clear();
   uint32_t words = 0;
-  // sorted IN lists first (searched in LDS: log2(n) reads per row), at
-  // even word offsets for their int64 values
+  // IN lists first, at even word offsets for their int64 values: the two
+  // cuckoo tables of a hashed list (two reads per row), else the sorted
+  // list (log2(n) reads per row)
   for (const DevInstr& I : code) {
     if (I.op != D_INLIST || I.n == 0 || out.size() == kMaxStage) continue;
+    const bool hashed = (I.flags & F_HASHED) != 0;
+    const uint32_t* src = (const uint32_t*)I.aux + (hashed ? 2 * I.n : 0);
     bool seen = false;
-    for (const BatchBitmap& b : out) seen |= b.src == (const uint32_t*)I.aux;
+    for (const BatchBitmap& b : out) seen |= b.src == src;
     if (seen) continue;
-    const uint32_t w = 2 * I.n;
+    const uint32_t w = hashed ? 4u << in_hash_bits(I.flags) : 2 * I.n;
     const uint32_t at = (words + 1) & ~1u;
     if (at + w + 1 > kScanStageWords) continue;
     BatchBitmap b{};
-    b.src = (const uint32_t*)I.aux;
+    b.src = src;
     b.words = w;
     b.last_mask = ~0u;
     b.lds_word = at;

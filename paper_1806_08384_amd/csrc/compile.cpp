@@ -66,6 +66,49 @@ const char* type_name(uint32_t ty) {
   }
 }
 
+// Two cuckoo tables of 2^b slots (b the least with 2^b >= 2 n, at least
+// 4) for the sorted distinct values v: each value in slot
+// in_hash(x, c1, b) of the first table or in_hash(x, c2, b) of the second,
+// empty slots holding v[0].  Multiplier pairs are tried in order; false if
+// insertion cycles under all of them.
+bool cuckoo_tables(const std::vector<int64_t>& v, std::vector<int64_t>& tabs, uint32_t& b, uint32_t& pair) {
+  b = 4;
+  while ((1ull << b) < 2 * v.size()) ++b;
+  const size_t m = size_t(1) << b;
+  for (pair = 0; pair < kInHashPairs; ++pair) {
+    const uint32_t c[2] = {kInHashMul[pair][0], kInHashMul[pair][1]};
+    std::vector<int64_t> t(2 * m);
+    std::vector<char> used(2 * m, 0);
+    bool ok = true;
+    for (int64_t x : v) {
+      int64_t cur = x;
+      int side = 0;
+      bool placed = false;
+      for (int kick = 0; kick < 64 && !placed; ++kick) {
+        const size_t slot = side * m + in_hash(cur, c[side], b);
+        if (!used[slot]) {
+          used[slot] = 1;
+          t[slot] = cur;
+          placed = true;
+        } else {
+          std::swap(cur, t[slot]);   // evict the occupant to its other table
+          side ^= 1;
+        }
+      }
+      if (!placed) {
+        ok = false;
+        break;
+      }
+    }
+    if (!ok) continue;
+    for (size_t k = 0; k < 2 * m; ++k)
+      if (!used[k]) t[k] = v[0];
+    tabs.swap(t);
+    return true;
+  }
+  return false;
+}
+
 struct Builder {
   const ColInfo* cols;
   uint32_t ncols;
@@ -163,6 +206,15 @@ struct Builder {
     n.ins.span = (uint64_t)mx - (uint64_t)mn;
     n.aux.resize(v.size() * 8);
     std::memcpy(n.aux.data(), v.data(), n.aux.size());
+    // short lists: two cuckoo tables after the sorted list, for the scans
+    std::vector<int64_t> tabs;
+    uint32_t b = 0, pair = 0;
+    if (v.size() <= kInHashMax && cuckoo_tables(v, tabs, b, pair)) {
+      n.ins.flags |= F_HASHED | (b << 8) | (pair << 16);
+      const size_t at = n.aux.size();
+      n.aux.resize(at + tabs.size() * 8);
+      std::memcpy(n.aux.data() + at, tabs.data(), tabs.size() * 8);
+    }
     n.col = col;
     return add(n);
   }
@@ -203,7 +255,10 @@ void emit(std::vector<Node>& nodes, int id, Lowered& out, uint32_t guard) {
   switch (n.kind) {
     case Node::LEAF: {
       DevInstr ins = n.ins;
-      ins.flags = (ins.op == D_RANGE || ins.op == D_BITMAP || ins.op == D_INLIST) ? guard : 0u;
+      // the guard of this position, beside what the leaf itself carries
+      // (a hashed IN list's table geometry)
+      ins.flags = ((ins.op == D_RANGE || ins.op == D_BITMAP || ins.op == D_INLIST) ? guard : 0u) |
+                  (n.ins.flags & ~(uint32_t)(F_GUARD_AND | F_GUARD_OR));
       if (!n.aux.empty()) {
         size_t off = (out.blob.size() + 7) & ~size_t(7);
         out.blob.resize(off + n.aux.size());
@@ -270,8 +325,8 @@ std::string listing(const Lowered& L) {
                       (long long)I.lo, (unsigned long long)I.span, I.valid ? " nullable" : "", g);
         break;
       case D_INLIST:
-        std::snprintf(buf, sizeof buf, "INLIST %s n=%u%s%s\n", type_name(I.type), I.n,
-                      I.valid ? " nullable" : "", g);
+        std::snprintf(buf, sizeof buf, "INLIST %s n=%u%s%s%s\n", type_name(I.type), I.n,
+                      (I.flags & F_HASHED) ? " hashed" : "", I.valid ? " nullable" : "", g);
         break;
       case D_NN_TRUE: std::snprintf(buf, sizeof buf, "NONNULL_TRUE\n"); break;
       case D_NN_FALSE: std::snprintf(buf, sizeof buf, "NONNULL_FALSE\n"); break;

@@ -199,6 +199,46 @@ __device__ __forceinline__ uint32_t inrange_bits(uint64_t tb, uint32_t lane, uin
   return m;
 }
 
+// Values of rows 8q .. 8q + 7 of the lane (steps 2q, 2q + 1), as int64:
+// wide loads on a full tile as for a range test, element loads (0 past the
+// table) on the partial one.
+template <int TY, bool FULL, bool NT>
+__device__ __forceinline__ void load8(const void* data, uint64_t tb, uint32_t lane, uint64_t nrows, int q,
+                                      int64_t (&x)[8]) {
+  if constexpr (FULL) {
+#pragma unroll
+    for (int js = 0; js < 2; ++js) {
+      const int j = 2 * q + js;
+      if constexpr (TY == T_I8) {
+        const uint32_t w = ldg<NT>(gptr<uint32_t>((const int8_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int8_t)(w >> (8 * i));
+      } else if constexpr (TY == T_I16) {
+        const v2i w = ldg<NT>(gptr<v2i>((const int16_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int16_t)((uint32_t)w[i >> 1] >> (16 * (i & 1)));
+      } else if constexpr (TY == T_I32) {
+        const v4i w = ldg<NT>(gptr<v4i>((const int32_t*)data + tb) + lane + 64 * j);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)w[i];
+      } else {
+        const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * j;
+        const v4i w0 = ldg<NT>(p), w1 = ldg<NT>(p + 1);
+        x[4 * js + 0] = (int64_t)(((uint64_t)(uint32_t)w0[1] << 32) | (uint32_t)w0[0]);
+        x[4 * js + 1] = (int64_t)(((uint64_t)(uint32_t)w0[3] << 32) | (uint32_t)w0[2]);
+        x[4 * js + 2] = (int64_t)(((uint64_t)(uint32_t)w1[1] << 32) | (uint32_t)w1[0]);
+        x[4 * js + 3] = (int64_t)(((uint64_t)(uint32_t)w1[3] << 32) | (uint32_t)w1[2]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint64_t row = row_of(tb, lane, 8 * q + k);
+      x[k] = row < nrows ? (int64_t)load_elem<TY>(data, row) : 0;
+    }
+  }
+}
+
 // IN-list test of a lane's 32 rows against a sorted list of n values (in
 // LDS or device memory): wide loads of the column as for a range test, then
 // a branch-free lower bound that moves the eight rows of two steps one
@@ -210,38 +250,7 @@ __device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, u
 #pragma unroll 1
   for (int q = 3; q >= 0; --q) {   // bits 8q .. 8q + 7: steps 2q, 2q + 1
     int64_t x[8];
-    if constexpr (FULL) {
-#pragma unroll
-      for (int js = 0; js < 2; ++js) {
-        const int j = 2 * q + js;
-        if constexpr (TY == T_I8) {
-          const uint32_t w = ldg<NT>(gptr<uint32_t>((const int8_t*)data + tb) + lane + 64 * j);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int8_t)(w >> (8 * i));
-        } else if constexpr (TY == T_I16) {
-          const v2i w = ldg<NT>(gptr<v2i>((const int16_t*)data + tb) + lane + 64 * j);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)(int16_t)((uint32_t)w[i >> 1] >> (16 * (i & 1)));
-        } else if constexpr (TY == T_I32) {
-          const v4i w = ldg<NT>(gptr<v4i>((const int32_t*)data + tb) + lane + 64 * j);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x[4 * js + i] = (int64_t)w[i];
-        } else {
-          const GLOBAL v4i* p = gptr<v4i>((const int64_t*)data + tb) + 2 * lane + 128 * j;
-          const v4i w0 = ldg<NT>(p), w1 = ldg<NT>(p + 1);
-          x[4 * js + 0] = (int64_t)(((uint64_t)(uint32_t)w0[1] << 32) | (uint32_t)w0[0]);
-          x[4 * js + 1] = (int64_t)(((uint64_t)(uint32_t)w0[3] << 32) | (uint32_t)w0[2]);
-          x[4 * js + 2] = (int64_t)(((uint64_t)(uint32_t)w1[1] << 32) | (uint32_t)w1[0]);
-          x[4 * js + 3] = (int64_t)(((uint64_t)(uint32_t)w1[3] << 32) | (uint32_t)w1[2]);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const uint64_t row = row_of(tb, lane, 8 * q + k);
-        x[k] = row < nrows ? (int64_t)load_elem<TY>(data, row) : 0;
-      }
-    }
+    load8<TY, FULL, NT>(data, tb, lane, nrows, q, x);
     uint32_t base[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) base[k] = 0;
@@ -258,6 +267,28 @@ __device__ __forceinline__ uint32_t inlist_bits(const void* data, uint64_t tb, u
   return P;
 }
 
+// The same test through the list's two cuckoo tables of 2^b slots each (T
+// then T + 2^b, in LDS or device memory): a value is in the list if and
+// only if it sits in its slot of either table, so two reads per row answer
+// it (empty slots hold a list value, which can only match a member).
+template <int TY, bool FULL, bool NT = true, class Tab>
+__device__ __forceinline__ uint32_t inhash_bits(const void* data, uint64_t tb, uint32_t lane, uint64_t nrows,
+                                                Tab T, uint32_t b, uint32_t c1, uint32_t c2, uint32_t need) {
+  const uint32_t m = 1u << b;
+  uint32_t P = 0;
+#pragma unroll 1
+  for (int q = 3; q >= 0; --q) {
+    int64_t x[8];
+    load8<TY, FULL, NT>(data, tb, lane, nrows, q, x);
+#pragma unroll
+    for (int k = 7; k >= 0; --k) {
+      const bool hit = T[in_hash(x[k], c1, b)] == x[k] || T[m + in_hash(x[k], c2, b)] == x[k];
+      P = (P << 1) + (uint32_t)(((need >> (8 * q + k)) & 1u) && hit);
+    }
+  }
+  return P;
+}
+
 // ---------------------------------------------------------------- leaves --
 template <int TY, bool FULL, bool NT = true>
 __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
@@ -266,6 +297,17 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
   const int64_t lo = I->lo;
   const uint64_t span = I->span;
   if (op == D_INLIST) {
+    const uint32_t f = I->flags;
+    if (f & F_HASHED) {
+      // the cuckoo tables after the sorted list: their LDS copy if staged
+      const uint32_t b = in_hash_bits(f), c1 = kInHashMul[in_hash_pair(f)][0], c2 = kInHashMul[in_hash_pair(f)][1];
+      const uint32_t* tabs = (const uint32_t*)I->aux + 2 * I->n;
+      for (uint32_t k = 0; k < sv.n; ++k)
+        if (sv.list[k].src == tabs)
+          return inhash_bits<TY, FULL, NT>(data, tb, lane, nrows, (const int64_t*)(sv.lds + sv.list[k].lds_word),
+                                           b, c1, c2, need);
+      return inhash_bits<TY, FULL, NT>(data, tb, lane, nrows, gptr<int64_t>(tabs), b, c1, c2, need);
+    }
     // the list's LDS copy if the scan staged it
     for (uint32_t k = 0; k < sv.n; ++k)
       if (sv.list[k].src == (const uint32_t*)I->aux)

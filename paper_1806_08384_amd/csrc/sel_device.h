@@ -47,8 +47,29 @@ enum DevOp : uint32_t {
 enum DevFlags : uint32_t {
   F_GUARD_AND = 1,  // leaf is the right operand of the next AND: rows whose
                     // left operand is FALSE need not be evaluated
-  F_GUARD_OR = 2    // ... of the next OR: rows whose left operand is TRUE
+  F_GUARD_OR = 2,   // ... of the next OR: rows whose left operand is TRUE
+  F_HASHED = 4      // D_INLIST: two cuckoo tables follow the sorted list;
+                    // bits 8..12 hold their log2 size, bits 16..18 the
+                    // multiplier pair
 };
+
+// IN lists of up to kInHashMax values also get two cuckoo tables of
+// 2^b >= 2n slots each: value x lives in slot in_hash(x, c1, b) of the
+// first or in_hash(x, c2, b) of the second, and empty slots hold a list
+// value.  The hash folds the two 32-bit halves, multiplies by an odd
+// constant and keeps the top b bits.
+constexpr uint32_t kInHashMax = 1024;
+constexpr uint32_t kInHashPairs = 8;
+constexpr uint32_t kInHashMul[kInHashPairs][2] = {
+    {0x9E3779B1u, 0x85EBCA77u}, {0xC2B2AE3Du, 0x27D4EB2Fu}, {0x165667B1u, 0xD3A2646Du},
+    {0xFD7046C5u, 0xB55A4F09u}, {0x2545F491u, 0x9E6C63D1u}, {0x5851F42Du, 0x4C957F2Du},
+    {0x7FEB352Du, 0x846CA68Bu}, {0xE6546B65u, 0x1B873593u}};
+constexpr uint32_t in_hash(int64_t x, uint32_t c, uint32_t b) {
+  const uint64_t u = (uint64_t)x;
+  return (((uint32_t)u ^ (uint32_t)(u >> 32)) * c) >> (32 - b);
+}
+constexpr uint32_t in_hash_bits(uint32_t flags) { return (flags >> 8) & 31u; }
+constexpr uint32_t in_hash_pair(uint32_t flags) { return (flags >> 16) & 7u; }
 
 struct DevInstr {          // 64 bytes, read with scalar loads
   uint32_t op;
@@ -105,11 +126,12 @@ struct ScanArgs {
   const BatchBitmap* stage;    // nstage entries (src, words, mask, offset)
 };
 
-// Single-program scans stage the program's small bitmaps (in program order,
-// up to this many words: 32 KB per workgroup, so that a 200 k-key dimension's
-// bitmap fits beside two smaller ones) in LDS; lookups into them skip the
-// memory system.
-constexpr uint32_t kScanStageWords = 8192;
+// Single-program scans stage the program's IN lists (or their cuckoo
+// tables) and small bitmaps (in program order, up to this many words: 48 KB
+// per workgroup, three of which fit a CU, so that two 2048-slot cuckoo
+// tables or a 200 k-key dimension's bitmap beside two smaller ones fit) in
+// LDS; lookups into them skip the memory system.
+constexpr uint32_t kScanStageWords = 12288;
 
 struct CompactArgs {
   const uint32_t* mask;        // packed nonzero result words (see ScanArgs)

@@ -13,6 +13,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <limits>
 #include <string>
@@ -60,7 +61,7 @@ uint32_t pool_offset(uint32_t pool_bytes) {
 
 int main(int argc, char** argv) {
   const long iters = argc > 1 ? std::atol(argv[1]) : 200000;
-  long accepted = 0, rejected = 0;
+  long accepted = 0, rejected = 0, hashed_lists = 0;
   std::vector<uint8_t> pool;
   for (long it = 0; it < iters; ++it) {
     // a table of 1..6 columns of random types, some nullable, some coded
@@ -146,6 +147,38 @@ int main(int argc, char** argv) {
                        (size_t)(uintptr_t)L.code[k].aux, L.blob.size());
           return 1;
         }
+      // a hashed IN list's cuckoo tables answer membership exactly as its
+      // sorted list does: on every member, its neighbours and random values
+      for (size_t k = 0; k < L.code.size(); ++k) {
+        const sel::DevInstr& I = L.code[k];
+        if (I.op != sel::D_INLIST || !(I.flags & sel::F_HASHED)) continue;
+        const uint32_t b = sel::in_hash_bits(I.flags), pr = sel::in_hash_pair(I.flags);
+        const size_t m = size_t(1) << b, off = (size_t)(uintptr_t)I.aux;
+        if (off + 8 * (I.n + 2 * m) > L.blob.size()) {
+          std::fprintf(stderr, "hashed IN list past the blob\n");
+          return 1;
+        }
+        std::vector<int64_t> v(I.n), t(2 * m);
+        std::memcpy(v.data(), L.blob.data() + off, 8 * v.size());
+        std::memcpy(t.data(), L.blob.data() + off + 8 * v.size(), 8 * t.size());
+        auto hit = [&](int64_t x) {
+          return t[sel::in_hash(x, sel::kInHashMul[pr][0], b)] == x ||
+                 t[m + sel::in_hash(x, sel::kInHashMul[pr][1], b)] == x;
+        };
+        std::vector<int64_t> probes;
+        for (int64_t x : v) {
+          probes.push_back(x);
+          probes.push_back((int64_t)((uint64_t)x + 1));
+          probes.push_back((int64_t)((uint64_t)x - 1));
+        }
+        for (int r = 0; r < 64; ++r) probes.push_back((int64_t)next());
+        for (int64_t x : probes)
+          if (hit(x) != std::binary_search(v.begin(), v.end(), x)) {
+            std::fprintf(stderr, "cuckoo tables disagree with the list on %lld\n", (long long)x);
+            return 1;
+          }
+        ++hashed_lists;
+      }
     } else {
       ++rejected;
       if (st != SEL_E_INVALID && st != SEL_E_TYPE) {
@@ -154,6 +187,7 @@ int main(int argc, char** argv) {
       }
     }
   }
-  std::printf("fuzz: %ld programs, %ld accepted, %ld rejected\n", iters, accepted, rejected);
-  return accepted > 0 && rejected > 0 ? 0 : 1;
+  std::printf("fuzz: %ld programs, %ld accepted, %ld rejected, %ld hashed IN lists checked\n", iters, accepted,
+              rejected, hashed_lists);
+  return accepted > 0 && rejected > 0 && hashed_lists > 0 ? 0 : 1;
 }

@@ -81,7 +81,9 @@ def test_lowering_in_lists():
     assert lowered(("in", 0, (7,))) == ["RANGE i32 lo=7 hi=7"]
     assert lowered(("in", 0, (3, 4, 5, 4, 3))) == ["RANGE i32 lo=3 hi=5"]
     assert lowered(("in", 0, tuple(range(0, 20, 2)))) == ["BITMAP i32 base=0 nbits=19"]
-    assert lowered(("in", 0, (-5, 10 ** 6))) == ["INLIST i32 n=2"]
+    assert lowered(("in", 0, (-5, 10 ** 6))) == ["INLIST i32 n=2 hashed"]
+    # a list longer than the hashed limit keeps only its sorted form
+    assert lowered(("in", 0, tuple(range(0, 100_000 * 1025, 100_000)))) == ["INLIST i32 n=1025"]
     assert lowered(("in", 2, (1000, 2000))) == ["FALSE"]           # no int8 value
     assert lowered(("in", 1, (2 ** 40,))) == ["NONNULL_FALSE"]
 

@@ -342,6 +342,14 @@ def test_cfg2_full_size(sel, ctx):
         bits = np.unpackbits(as_u32(vo).view(np.uint8), bitorder="little")[:cnt].astype(bool)
         np.testing.assert_array_equal(bits, wvalid)
     del out, outs, vouts
+    # the sparse int64 IN lists the benchmark sweeps (10, 100 and 1000
+    # values, half of them present)
+    for k in (10, 100, 1000):
+        tree_in = ("in", 3, datagen.sparse_in_values(t.col("price").data, k))
+        prog_in = ctx.program(dt, tree_in)
+        got_in = ctx.count(dt, prog_in)
+        say(f"cfg2 full: IN list of {k} values, count {got_in}")
+        assert got_in == orc.count(tree_in, threads=16), k
     # a date range holding about 90 % of the rows: 270M ascending ids (1.08
     # GB), the limit one below the count refuses them, the count itself
     # accepts them
