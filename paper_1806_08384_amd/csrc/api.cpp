@@ -497,6 +497,37 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   std::string e;
   int st = lower_program(ci.data(), (uint32_t)ci.size(), code, n, (const uint8_t*)pool, pool_bytes, L, e);
   if (st != SEL_OK) return set_err(ctx, (sel_status)st, e);
+  // with range tests merged, the conjuncts as written for factor counts:
+  // the same leaves' constants, found in the merged program's blob
+  Lowered U;
+  bool factors_apart = false;
+  if (L.merged) {
+    std::string e2;
+    if (lower_program(ci.data(), (uint32_t)ci.size(), code, n, (const uint8_t*)pool, pool_bytes, U, e2, false) !=
+        SEL_OK)
+      return set_err(ctx, SEL_E_INVALID, "unmerged lowering failed: " + e2);
+    factors_apart = true;
+    for (size_t k = 0; k < U.code.size() && factors_apart; ++k) {
+      if (!U.aux_is_offset[k]) continue;
+      const DevInstr& u = U.code[k];
+      const size_t nb = aux_bytes(u);
+      bool found = false;
+      for (size_t j = 0; j < L.code.size() && !found; ++j) {
+        const DevInstr& l = L.code[j];
+        if (!L.aux_is_offset[j] || l.op != u.op || l.data != u.data || l.n != u.n || l.lo != u.lo ||
+            l.span != u.span || aux_bytes(l) != nb)
+          continue;
+        const size_t lo = (size_t)(uintptr_t)l.aux, uo = (size_t)(uintptr_t)u.aux;
+        if (lo + nb <= L.blob.size() && uo + nb <= U.blob.size() &&
+            std::memcmp(L.blob.data() + lo, U.blob.data() + uo, nb) == 0) {
+          U.code[k].aux = l.aux;   // an offset into the merged program's blob
+          found = true;
+        }
+      }
+      factors_apart = found;
+    }
+    if (!factors_apart) return set_err(ctx, SEL_E_INVALID, "unmerged lowering does not match the merged one");
+  }
   DeviceGuard g(ctx->device);
   sel_program* p = new (std::nothrow) sel_program();
   if (!p) return set_err(ctx, SEL_E_NOMEM, "host allocation failed");
@@ -544,6 +575,13 @@ sel_status sel_program_compile(sel_ctx* ctx, const sel_table* table, const sel_i
   p->host_code = L.code;
   p->host_blob = L.blob;
   p->blob_dev = blob_base;
+  if (factors_apart) {
+    for (size_t k = 0; k < U.code.size(); ++k)
+      if (U.aux_is_offset[k]) U.code[k].aux = (const void*)(blob_base + (uintptr_t)U.code[k].aux);
+    p->factor_code = U.code;
+  } else {
+    p->factor_code = p->host_code;
+  }
   double bpr = 0.0;
   for (uint32_t c : L.columns) bpr += type_bytes(ci[c].type);
   bpr += (double)L.valid_columns.size() / 8.0;

@@ -395,7 +395,8 @@ sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_pro
   if (!nfactors || !count) return set_err(ctx, SEL_E_INVALID, "NULL output");
   if (!table || !prog) return set_err(ctx, SEL_E_INVALID, "NULL handle");
   if (prog->table != table) return set_err(ctx, SEL_E_INVALID, "program is bound to another table");
-  const auto ranges = and_factors(prog->host_code);
+  const std::vector<DevInstr>& fcode = prog->factor_code.empty() ? prog->host_code : prog->factor_code;
+  const auto ranges = and_factors(fcode);
   *nfactors = (uint32_t)ranges.size();
   if (ranges.size() > cap) return set_err(ctx, SEL_E_CAPACITY, "more factors than the output holds");
   if (!factor_counts) return set_err(ctx, SEL_E_INVALID, "factor_counts is NULL");
@@ -408,8 +409,7 @@ sel_status sel_factor_counts(sel_ctx* ctx, const sel_table* table, const sel_pro
     sel_program& f = fp[k];
     f.ctx = ctx;
     f.table = table;
-    f.host_code.assign(prog->host_code.begin() + ranges[k].first,
-                       prog->host_code.begin() + ranges[k].second);
+    f.host_code.assign(fcode.begin() + ranges[k].first, fcode.begin() + ranges[k].second);
     f.host_blob = prog->host_blob;
     f.blob_dev = prog->blob_dev;
     f.nins = (uint32_t)f.host_code.size();

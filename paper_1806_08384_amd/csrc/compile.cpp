@@ -22,6 +22,7 @@
 // right operand of AND (OR) is flagged so the kernel may skip its lookups
 // on rows whose left operand is already FALSE (TRUE).
 #include <algorithm>
+#include <functional>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -114,6 +115,7 @@ struct Builder {
   uint32_t ncols;
   std::vector<Node> nodes;
   std::string* err;
+  bool merged = false;
 
   int add(Node n) {
     nodes.push_back(std::move(n));
@@ -219,6 +221,101 @@ struct Builder {
     return add(n);
   }
 };
+
+// Range tests of one column under the same conjunction become one test of
+// the intersection of their ranges (an empty one: FALSE on every non-NULL
+// row).  Exact in three-valued logic: on a NULL row every such test, the
+// merged one too, is UNKNOWN.  A column is then read once per tile instead
+// of once per test.  Returns the node that replaces `id`.
+void and_operands(const std::vector<Node>& nodes, int id, std::vector<int>& ops) {
+  if (nodes[id].kind == Node::AND) {
+    and_operands(nodes, nodes[id].a, ops);
+    and_operands(nodes, nodes[id].b, ops);
+  } else {
+    ops.push_back(id);
+  }
+}
+
+int merge_and_ranges(Builder& B, int id) {
+  const Node::Kind kind = B.nodes[id].kind;
+  if (kind == Node::NOT || kind == Node::ISUNK) {
+    const int a = merge_and_ranges(B, B.nodes[id].a);
+    B.nodes[id].a = a;
+    return id;
+  }
+  if (kind == Node::OR) {
+    const int a = merge_and_ranges(B, B.nodes[id].a);
+    const int b = merge_and_ranges(B, B.nodes[id].b);
+    B.nodes[id].a = a;
+    B.nodes[id].b = b;
+    return id;
+  }
+  if (kind != Node::AND) return id;
+  std::vector<int> ops;
+  and_operands(B.nodes, id, ops);
+  for (int& o : ops) o = merge_and_ranges(B, o);
+  bool merged = false;
+  for (size_t i = 0; i < ops.size(); ++i) {
+    if (ops[i] < 0) continue;
+    const Node& first = B.nodes[ops[i]];
+    if (first.kind != Node::LEAF || first.ins.op != D_RANGE) continue;
+    int64_t lo = first.ins.lo;
+    int64_t hi = (int64_t)((uint64_t)first.ins.lo + first.ins.span);
+    bool any = false;
+    for (size_t j = i + 1; j < ops.size(); ++j) {
+      if (ops[j] < 0) continue;
+      const Node& o = B.nodes[ops[j]];
+      if (o.kind != Node::LEAF || o.ins.op != D_RANGE || o.col != first.col) continue;
+      lo = std::max(lo, o.ins.lo);
+      hi = std::min(hi, (int64_t)((uint64_t)o.ins.lo + o.ins.span));
+      ops[j] = -1;
+      any = true;
+    }
+    if (!any) continue;
+    merged = true;
+    B.merged = true;
+    const uint32_t col = B.nodes[ops[i]].col;
+    if (lo > hi) {
+      ops[i] = B.nonnull_const(col, false);
+    } else {   // a new leaf: the tree's nodes are left as they are
+      Node c = B.nodes[ops[i]];
+      c.ins.lo = lo;
+      c.ins.span = (uint64_t)hi - (uint64_t)lo;
+      ops[i] = B.add(c);
+    }
+  }
+  if (!merged) {
+    // the operands may have changed below: rebuild the chain as it was
+    // shaped only if something merged at this level
+    int k = 0;
+    std::function<int(int)> relink = [&](int n) -> int {
+      if (B.nodes[n].kind == Node::AND) {
+        const int a = relink(B.nodes[n].a);
+        const int b = relink(B.nodes[n].b);
+        B.nodes[n].a = a;
+        B.nodes[n].b = b;
+        return n;
+      }
+      return ops[k++];
+    };
+    return relink(id);
+  }
+  // the remaining operands, in their order, as a chain of ANDs
+  int acc = -1;
+  for (int o : ops) {
+    if (o < 0) continue;
+    if (acc < 0) {
+      acc = o;
+      continue;
+    }
+    Node nd;
+    nd.kind = Node::AND;
+    nd.a = acc;
+    nd.b = o;
+    acc = B.add(nd);
+  }
+  return acc;
+}
 
 int fail(std::string* err, sel_status st, const char* fmt, ...) {
   char buf[256];
@@ -344,8 +441,16 @@ std::string listing(const Lowered& L) {
   return s;
 }
 
+size_t aux_bytes(const DevInstr& I) {
+  if (I.op == D_BITMAP) return (size_t)((I.span + 31) / 32) * 4;
+  if (I.op == D_INLIST)
+    return (size_t)I.n * 8 + ((I.flags & F_HASHED) ? (size_t(16) << in_hash_bits(I.flags)) : 0);
+  return 0;
+}
+
 int lower_program(const ColInfo* cols, uint32_t ncols, const sel_instr* code, uint32_t n,
-                  const uint8_t* pool, uint32_t pool_bytes, Lowered& out, std::string& err) {
+                  const uint8_t* pool, uint32_t pool_bytes, Lowered& out, std::string& err,
+                  bool merge_ranges) {
   out = Lowered{};
   if (code == nullptr || n == 0 || n > SEL_MAX_INSTRS)
     return fail(&err, SEL_E_INVALID, "program length %u invalid (1..64)", n);
@@ -443,7 +548,8 @@ int lower_program(const ColInfo* cols, uint32_t ncols, const sel_instr* code, ui
   }
   if (stack.size() != 1)
     return fail(&err, SEL_E_INVALID, "program leaves %u values on the stack (must be 1)", (unsigned)stack.size());
-  const int root = stack[0];
+  const int root = merge_ranges ? merge_and_ranges(B, stack[0]) : stack[0];
+  out.merged = B.merged;
   out.depth = compute_need(B.nodes, root);
   if (out.depth > SEL_MAX_DEPTH)
     return fail(&err, SEL_E_INVALID, "program needs a stack of depth %d (max 8)", out.depth);

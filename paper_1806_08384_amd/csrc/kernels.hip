@@ -290,7 +290,10 @@ __device__ __forceinline__ uint32_t inhash_bits(const void* data, uint64_t tb, u
 }
 
 // ---------------------------------------------------------------- leaves --
-template <int TY, bool FULL, bool NT = true>
+// SCAN: called by the scan kernels, whose leaves carry DevFlags (a batch's
+// copies of the leaves reuse the flags word for their own guard marks, and
+// read an IN list through its sorted values only).
+template <int TY, bool FULL, bool NT = true, bool SCAN = true>
 __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb, uint32_t lane,
                                               uint64_t nrows, uint32_t need, const StageView& sv) {
   const void* data = I->data;
@@ -298,7 +301,7 @@ __device__ __forceinline__ uint32_t leaf_pred(uint32_t op, CInstr I, uint64_t tb
   const uint64_t span = I->span;
   if (op == D_INLIST) {
     const uint32_t f = I->flags;
-    if (f & F_HASHED) {
+    if (SCAN && (f & F_HASHED)) {
       // the cuckoo tables after the sorted list: their LDS copy if staged
       const uint32_t b = in_hash_bits(f), c1 = kInHashMul[in_hash_pair(f)][0], c2 = kInHashMul[in_hash_pair(f)][1];
       const uint32_t* tabs = (const uint32_t*)I->aux + 2 * I->n;
@@ -1205,10 +1208,10 @@ __device__ __forceinline__ void entry_leaves_partial(const CONSTANT BatchTable* 
       CInstr I = leaves + lb + k;
       uint32_t P;
       switch (C->type) {
-        case T_I8: P = leaf_pred<T_I8, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
-        case T_I16: P = leaf_pred<T_I16, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
-        case T_I32: P = leaf_pred<T_I32, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
-        default: P = leaf_pred<T_I64, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        case T_I8: P = leaf_pred<T_I8, false, true, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        case T_I16: P = leaf_pred<T_I16, false, true, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        case T_I32: P = leaf_pred<T_I32, false, true, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
+        default: P = leaf_pred<T_I64, false, true, false>(I->op, I, tb, lane, nrows, ~0u, StageView{}); break;
       }
       put_leaf(wl, lane, I->slot, P);
     }

@@ -131,6 +131,8 @@ struct sel_program {
   bool own_alloc = false;           // or its own hipMalloc if the arena is full
   DevInstr* dcode = nullptr;
   std::vector<DevInstr> host_code;  // with device pointers (for star programs)
+  std::vector<DevInstr> factor_code;  // the conjuncts as written (range tests of a
+                                      // column not merged), same device constants
   std::vector<uint8_t> host_blob;   // host copy of the constants (IN lists, bitmaps)
   uintptr_t blob_dev = 0;           // their device address
   const sel::BatchBitmap* dstage = nullptr;   // bitmaps a scan stages in LDS

@@ -29,10 +29,18 @@ struct Lowered {
   std::vector<uint32_t> valid_columns;  // columns whose validity is read
   int depth = 0;
   std::string text;                     // one line per instruction
+  bool merged = false;                  // range tests of a column were merged
 };
 
+// merge_ranges: range tests of one column under one conjunction become one
+// test (the code the kernels run); without it the program keeps the
+// conjuncts as written (the factors an independence estimate counts).
 int lower_program(const ColInfo* cols, uint32_t ncols, const struct sel_instr* code, uint32_t n,
-                  const uint8_t* pool, uint32_t pool_bytes, Lowered& out, std::string& err);
+                  const uint8_t* pool, uint32_t pool_bytes, Lowered& out, std::string& err,
+                  bool merge_ranges = true);
+// Bytes of a leaf's constants in the blob (bitmap words, IN list and its
+// cuckoo tables), 0 for a leaf without any.
+size_t aux_bytes(const DevInstr& I);
 std::string listing(const Lowered& L);
 
 }  // namespace sel

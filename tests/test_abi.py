@@ -88,6 +88,21 @@ def test_lowering_in_lists():
     assert lowered(("in", 1, (2 ** 40,))) == ["NONNULL_FALSE"]
 
 
+def test_lowering_merges_ranges_of_a_column():
+    """Range tests of one column under one conjunction become the test of
+    the ranges' intersection (exact in three-valued logic); tests under an
+    OR, or on other columns, stay apart."""
+    assert lowered(("and", ("between", 0, 0, 1999), ("cmp", 2, "<", 45), ("cmp", 0, ">=", 10))) == [
+        "RANGE i32 lo=10 hi=1999", "RANGE i8 lo=-128 hi=44 guard_and", "AND"]
+    assert lowered(("and", ("cmp", 1, ">", 5), ("and", ("cmp", 1, "<", 9), ("cmp", 1, "<>", 7)))) == [
+        "RANGE i32 lo=6 hi=8 nullable", "RANGE i32 lo=7 hi=7 nullable", "NOT", "AND"]
+    # disjoint ranges: FALSE on non-NULL rows, UNKNOWN on NULL ones
+    assert lowered(("and", ("cmp", 1, "<", 5), ("cmp", 1, ">", 9))) == ["NONNULL_FALSE"]
+    assert lowered(("and", ("cmp", 0, "<", 5), ("cmp", 0, ">", 9))) == ["FALSE"]
+    assert lowered(("or", ("cmp", 0, "<", 5), ("cmp", 0, ">", 9))) == [
+        "RANGE i32 lo=-2147483648 hi=4", "RANGE i32 lo=10 hi=2147483647 guard_or", "OR"]
+
+
 def test_lowering_codesets_and_nulls():
     words = np.zeros(1, dtype=np.uint32)
     # a LIKE matching no dictionary code: empty code set, NULL rows stay UNKNOWN
