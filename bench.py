@@ -43,24 +43,28 @@ def host_threads() -> int:
     return max(1, min(n, 16))
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, calibrated
-    against a plain copy) from the committed rocprofv3 summary of this
-    workload, or None when the kernel source has changed since it was taken."""
+def measured_traffic(kernels, profile="scan_fact300M_pushdown.md"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a
+    plain copy) of the named kernel, or summed over a list of kernels that
+    one launch runs, from the committed rocprofv3 summary of this workload;
+    None when the kernel source has changed since it was taken."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         src = open(os.path.join(root, "paper_1806_08384_amd", "csrc", "kernels.hip"), "rb").read()
-        text = open(os.path.join(root, "profiles", "scan_fact300M_pushdown.md")).read()
+        text = open(os.path.join(root, "profiles", profile)).read()
     except OSError:
         return None
+    names = [kernels] if isinstance(kernels, str) else list(kernels)
     for line in text.splitlines():
         if line.startswith("traffic-json: "):
             rec = json.loads(line[len("traffic-json: "):])
             if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
                 return None
-            t = rec.get("per_launch", {}).get(kernel)
-            return None if t is None else t["fetch_bytes"] + t["write_bytes"]
+            per = rec.get("per_launch", {})
+            if any(k not in per for k in names):
+                return None
+            return sum(per[k]["fetch_bytes"] + per[k]["write_bytes"] for k in names)
     return None
 
 
@@ -242,6 +246,10 @@ def bench_batch(ctx, fact_dt, threads, log):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": batch_bytes / graph_kernel_ms / 1e6 / HBM_PEAK_GBS,
+            # the graph's lookup-table launches (one per accumulator width)
+            # and table builds, from the committed profile of this batch
+            "traffic": measured_traffic(["k_lbatch<2, 8>", "k_lbatch<4, 4>", "k_luts"],
+                                        "batch_64programs_4tables.md"),
         },
     }
     b.destroy()
@@ -306,6 +314,10 @@ def bench_star(ctx, fact_rows, threads, log, cpu=False):
         "star_rows_per_s": fact_rows / (kms / 1e3),
         "star_GBps": bytes_ / (kms / 1e3) / 1e9,
         "star_frac_of_peak": bytes_ / (kms / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "star_algorithmic_bytes": bytes_,
+        # HBM bytes of one star launch from the committed profile (null if
+        # the kernels changed since)
+        "star_traffic": measured_traffic("star", "star_fact480M_probe.md"),
     }
     # the join order the exact dimension counts give (Ch.1 sec.1.1 formula)
     order, cost, inter = sel.star_plan(fact_rows, nbits, dim_counts)
@@ -864,7 +876,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_scan<1>"),
+            "traffic": measured_traffic("k_scan<1, true>"),
             "avg_kernel_ms": mask_avg_s * 1e3,
             "algorithmic_bytes_per_launch": mask_kernel_bytes,
             "mask_words_written": mask_words,
