@@ -658,13 +658,22 @@ def bench_sweeps(ctx, dt, n, threads, log, in_lists, reps=3):
     on the 300M-row fact table (the analogues of the thesis' overhead versus
     selectivity and versus attribute count experiments), with the push-down
     step (count + mask, limit, scan, ascending ids) at each selectivity; and
-    the three-column uniform table at 300M rows, a pure bandwidth probe."""
+    the three-column uniform table at 300M rows, a pure bandwidth probe.
+    Each count is timed in the configuration the tuner picks for its program
+    class (reported per row as `launch`); the push-down step keeps the
+    defaults."""
     import torch
 
     import datagen
     from paper_1806_08384_amd import sel
 
+    tuned = {}
+
     def count_ms(table, prog):
+        # the count scan in the configuration the tuner picks for this
+        # program class and table size (a deployment tunes each class once)
+        cfg, _ = ctx.autotune(table, prog, with_mask=False, reps=3)
+        tuned[id(prog)] = {k: getattr(cfg, k) for k in ("block", "grid", "cached", "tiles_per_step", "stage_words")}
         ctx.count(table, prog)
         ctx.read_timing(reset=True)
         for _ in range(reps):
@@ -692,7 +701,7 @@ def bench_sweeps(ctx, dt, n, threads, log, in_lists, reps=3):
         torch.cuda.synchronize()
         pd_ms = (time.perf_counter() - t0) / reps * 1e3
         gbs = n * bpr / kms / 1e6
-        sel_rows.append({"program": name, "selected_rows": c, "selectivity": c / n,
+        sel_rows.append({"program": name, "selected_rows": c, "selectivity": c / n, "launch": tuned[id(prog)],
                          "count_kernel_ms": kms, "count_GBps": gbs,
                          "count_frac_of_peak": gbs / HBM_PEAK_GBS,
                          "pushdown_step_ms": pd_ms, "ids_bytes": 4 * c})
@@ -711,7 +720,7 @@ def bench_sweeps(ctx, dt, n, threads, log, in_lists, reps=3):
         c, kms = count_ms(dt, prog)
         bpr = prog.bytes_per_row
         gbs = n * bpr / kms / 1e6
-        leaf_rows.append({"leaves": k, "bytes_per_row": bpr, "selected_rows": c,
+        leaf_rows.append({"leaves": k, "bytes_per_row": bpr, "selected_rows": c, "launch": tuned[id(prog)],
                           "count_kernel_ms": kms, "rows_per_s": n / kms * 1e3,
                           "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS})
         log(f"sweep: {k} leaves, {bpr} B/row: count {kms:.3f} ms, {gbs:.0f} GB/s")
@@ -727,6 +736,7 @@ def bench_sweeps(ctx, dt, n, threads, log, in_lists, reps=3):
         bpr = prog.bytes_per_row
         gbs = n * bpr / kms / 1e6
         in_rows.append({"list_values": k, "present_values": k // 2, "bytes_per_row": bpr, "selected_rows": c,
+                        "launch": tuned[id(prog)],
                         "count_kernel_ms": kms, "count_GBps": gbs, "count_frac_of_peak": gbs / HBM_PEAK_GBS})
         log(f"sweep: int64 IN list of {k} values: {c} rows, {kms:.3f} ms, {gbs:.0f} GB/s")
         prog.destroy()
