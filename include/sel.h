@@ -345,14 +345,17 @@ sel_status sel_select_pushdown(sel_ctx* ctx, uint32_t n, const sel_spd_relation*
 
 /* ---- batching (Algorithm 1 counts every candidate relation) ------------- */
 
-/* Exact counts of n (table, program) pairs in ONE persistent launch
+/* Exact counts of n (table, program) pairs in ONE batched launch sequence
  * (n in 1..1024; progs[i] must be bound to tables[i]; tables may repeat and
  * may differ in size).  Tiles of every table form one index space; a wave
  * takes a tile and evaluates every program of one pass over that tile's
  * table on it.  A table's programs are packed into as few passes as the
  * per-wave evaluation state allows, and each pass reads the columns its
  * programs use from HBM once: a table is read once per pass, not once per
- * program.  out_counts (host, n)
+ * program.  Programs in conjunctive form (every one without IS UNKNOWN
+ * whose clauses and columns fit) are counted by one lookup per column and
+ * row into per-column tables of program bits (up to 32 programs a pass);
+ * the rest by leaf-major evaluation.  out_counts (host, n)
  * receives count i for pair i; each equals what sel_count returns for it.
  * Algorithm 1 computes one count per candidate relation in its loop over
  * the relation queue; a batch computes all of them at once.
