@@ -1771,7 +1771,10 @@ __device__ __forceinline__ SlotD slot_decode(const CONSTANT LutPass* P, const CO
     // bound, and the bytes up to the next 4-byte boundary share the last
     // element's 16-byte-aligned block (the same memory page)
     const uint32_t span = ((uint32_t)(rows * width) + 3u) & ~3u;
-    d.bytes = span > half ? span - half : 0u;
+    // made scalar: the compiler turns this into a saturating subtract that
+    // only the vector unit has, and a buffer resource built from a vector
+    // register is wrapped in a readfirstlane loop at every load
+    d.bytes = uni(span > half ? span - half : 0u);
     const bool hv = !half && C->valid;
     d.valid = hv ? C->valid + tb / 32 : (const uint32_t*)P;
     d.vbytes = hv ? (uint32_t)(((rows + 31) / 32) * 4) : 0u;
