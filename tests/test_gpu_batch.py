@@ -428,3 +428,49 @@ def test_batch_conjunction_shapes(sel, ctx):
     for _ in range(2):
         assert b.run() == want
     b.destroy()
+
+
+@pytest.mark.parametrize("nb", [1, 3, 4, 5, 8, 13, 16, 17, 31])
+def test_batch_rank_bounds(sel, ctx, nb):
+    """A pass whose int64 and int32 columns are looked up by rank (value
+    ranges too wide for a direct window) with nb distinct bounds each, from
+    one bound to a whole block of eight and past it.  The values include
+    both ends of each type, every bound itself and NULLs; counts equal the
+    oracle."""
+    say(f"batch rank bounds nb={nb}")
+    rng = np.random.default_rng(43_000 + nb)
+    n = 70_001
+    i64 = np.iinfo(np.int64)
+    i32 = np.iinfo(np.int32)
+    b64 = np.sort(rng.choice(rng.integers(-10**15, 10**15, 4 * nb), nb, replace=False)).astype(np.int64)
+    b32 = np.sort(rng.choice(rng.integers(i32.min, i32.max, 4 * nb, dtype=np.int64), nb,
+                             replace=False)).astype(np.int32)
+    x64 = rng.integers(-2 * 10**15, 2 * 10**15, n).astype(np.int64)
+    x32 = rng.integers(i32.min, i32.max, n, dtype=np.int64).astype(np.int32)
+    k = np.arange(n)
+    x64[k % 7 == 0] = b64[(k[k % 7 == 0] // 7) % nb]
+    x32[k % 5 == 0] = b32[(k[k % 5 == 0] // 5) % nb]
+    x64[:6] = [i64.min, i64.max, i64.min + 1, i64.max - 1, 0, -1]
+    x32[:4] = [i32.min, i32.max, i32.min + 1, i32.max - 1]
+    t = datagen.Table("ranks", n)
+    for name, x in (("w", x64), ("v", x32)):
+        v, nn = _nulls(rng, n, 0.1)
+        t.columns.append(datagen.Column(name, "i64" if x.dtype == np.int64 else "i32", x,
+                                        valid=v, null_count=nn))
+    trees = []
+    for j in range(nb):
+        # one bound per leaf: x >= b_j, or x < b_j; the second column's
+        # leaf keeps each program two-column
+        op = ">=" if j % 2 == 0 else "<"
+        trees.append(("and", ("cmp", 0, op, int(b64[j])), ("cmp", 1, "<" if j % 3 else ">=", int(b32[j]))))
+    trees.append(("cmp", 0, ">=", int(b64[-1])))
+    trees.append(("or", ("cmp", 0, "<", int(b64[0])), ("cmp", 1, ">=", int(b32[-1]))))
+    dt = sel.device_table(ctx, t)
+    pairs = [(dt, ctx.program(dt, tree)) for tree in trees]
+    orc = oracle.Oracle(t)
+    want = [orc.count(tree) for tree in trees]
+    assert ctx.count_batch(pairs) == want
+    b = ctx.batch(pairs)
+    for _ in range(2):
+        assert b.run() == want
+    b.destroy()
