@@ -2208,10 +2208,11 @@ __device__ __forceinline__ void lut_tile(const CONSTANT LutPass* P, const CONSTA
 // (pass ranges are padded to kLutTileAlign), and copies a pass's LDS tables
 // from device memory when it moves to that pass.
 // Workgroup of the lookup-table kernel (one per CU, whose LDS it takes):
-// twelve waves, three per SIMD; with four accumulator dwords the segments
-// hold four rows per lane instead of eight so that the registers still fit.
+// twelve waves, three per SIMD (168 vector registers each); with four
+// accumulator dwords the segments hold four rows per lane instead of eight,
+// which fits 128 registers and so sixteen waves, four per SIMD.
 template <int D>
-constexpr uint32_t lbatch_threads() { return 768u; }
+constexpr uint32_t lbatch_threads() { return D == 4 ? 1024u : 768u; }
 
 template <int D, int R>
 __global__ void __launch_bounds__(lbatch_threads<D>()) k_lbatch(LutArgs a) {
@@ -2414,7 +2415,7 @@ const void* lbatch_kernel(uint32_t dwords, uint32_t rows) {
   switch (dwords) {
     case 1: return rows == 4 ? (const void*)k_lbatch<1, 4> : (const void*)k_lbatch<1, 8>;
     case 2: return rows == 4 ? (const void*)k_lbatch<2, 4> : (const void*)k_lbatch<2, 8>;
-    default: return (const void*)k_lbatch<4, 4>;   // four rows per lane: twelve waves fit
+    default: return (const void*)k_lbatch<4, 4>;   // four rows per lane: sixteen waves fit
   }
 }
 }  // namespace
