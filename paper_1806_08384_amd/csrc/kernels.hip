@@ -8,8 +8,8 @@
 //                       row of a pushed-down dimension (Ch.3 sec.3.3)
 //  k_chunk_scan,        exclusive scan of the per-tile counts (two levels)
 //  k_chunk_offsets
-//  k_compact            mask -> ascending row ids (LDS-free wave prefix by
-//                       ballot + mbcnt)
+//  k_compact            mask -> ascending row ids (wave prefix by DPP,
+//                       ballot + mbcnt; no LDS memory)
 //  k_batch              many programs over several tables in one launch,
 //                       one count per program
 //
@@ -698,6 +698,37 @@ __device__ __forceinline__ void compact_tile(uint32_t w, uint64_t base, uint64_t
     const uint32_t packed = lo | (hi << 16);
     excl[q] = wave_incl_sum(packed, lane, tot[q]) - packed;
   }
+  if (__ballot(__builtin_popcount(w) > 2u) == 0ull) {
+    // sparse tile (at most two TRUE rows per lane): each lane walks its own
+    // set bits.  Field j of the packed words becomes the rank of step j's
+    // first TRUE row of this lane: TRUE rows of earlier steps (uniform)
+    // plus those of step j in lower lanes (at most 2048 < 2^16, so the two
+    // fields of a word stay apart)
+    uint32_t first[4];
+    uint32_t run = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t t0 = tot[q] & 0xFFFFu, t1 = tot[q] >> 16;
+      first[q] = excl[q] + (run | ((run + t0) << 16));
+      run += t0 + t1;
+    }
+    uint32_t prev = ~0u;   // step of the lane's first TRUE row
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      if (w != 0u) {
+        const uint32_t b = __builtin_ctz(w);
+        const uint32_t j = b >> 2;
+        const uint32_t q = j >> 1;
+        const uint32_t word = q & 2u ? (q & 1u ? first[3] : first[2]) : (q & 1u ? first[1] : first[0]);
+        // plus one if the lane's first TRUE row is earlier in this nibble
+        const uint64_t p = base + ((word >> (16u * (j & 1u))) & 0xFFFFu) + (j == prev ? 1u : 0u);
+        if (p < cap) out[p] = (uint32_t)(tb + 256u * j + 4u * lane + (b & 3u));
+        prev = j;
+        w &= w - 1u;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < kSteps; ++j) {
     const uint32_t nib = (w >> (4 * j)) & 0xFu;
@@ -729,26 +760,30 @@ __global__ void __launch_bounds__(256) k_compact(CompactArgs a) {
   const uint64_t step = (uint64_t)gridDim.x * nw * kCompactTiles;
   for (uint64_t t0 = uni64(((uint64_t)blockIdx.x * nw + (threadIdx.x >> 6)) * kCompactTiles);
        t0 < a.ntiles; t0 += step) {
-    uint32_t w[kCompactTiles];
+    uint32_t raw[kCompactTiles];
     uint32_t off[kCompactTiles], coff[kCompactTiles];
     uint64_t nz[kCompactTiles];
 #pragma unroll
     for (int k = 0; k < kCompactTiles; ++k) {
       const uint64_t tile = t0 + k;
       const bool in = tile < a.ntiles;
-      // the lanes whose word the mask pass wrote, and each one's rank
-      // among them: its place in the tile's packed words
+      // the lanes whose word the mask pass wrote; and the tile's packed
+      // words read whole, one per lane (coalesced, and not waiting for the
+      // lane map: the words past the packed ones are not used)
       nz[k] = in ? uni64(a.tile_lanes[tile]) : 0ull;
-      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz[k] >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nz[k], 0u));
-      w[k] = (nz[k] >> lane) & 1u ? a.mask[tile * kWave + pos] : 0u;
+      raw[k] = in ? a.mask[tile * kWave + lane] : 0u;
       off[k] = in ? a.offsets[tile] : 0u;
       coff[k] = in ? a.chunk_offs[tile >> 10] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kCompactTiles; ++k) {
       if (nz[k] == 0ull) continue;  // no TRUE row in the tile
-      compact_tile(w[k], (uint64_t)uni(coff[k]) + uni(off[k]), t0 + k, lane, a.out, a.cap);
+      // a set lane's word is packed at its rank among the set lanes
+      const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz[k] >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)nz[k], 0u));
+      const uint32_t mine = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(pos << 2), (int)raw[k]);
+      const uint32_t w = (nz[k] >> lane) & 1u ? mine : 0u;
+      compact_tile(w, (uint64_t)uni(coff[k]) + uni(off[k]), t0 + k, lane, a.out, a.cap);
     }
   }
 }
