@@ -571,7 +571,7 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
     log(f"serve: {len(trace)} requests over {warm + seconds:.0f} s")
     th = threading.Thread(target=client)
     th.start()
-    lat, mismatches, by_big = [], 0, {}
+    lat, mismatches, by_big, by_pd = [], 0, {}, {}
     for i in range(len(trace)):
         while tickets[i] is None and not err:
             time.sleep(0.0002)
@@ -585,6 +585,7 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
             big = max([tables[tb].nrows for tb, _ in trace[i][1]] +
                       ([tables[trace[i][2][0]].nrows] if trace[i][2] else []))
             by_big.setdefault(big, []).append(ms)
+            by_pd.setdefault("with_pushdown" if trace[i][2] else "counts_only", []).append(ms)
     th.join()
     if err:
         raise err[0]
@@ -640,6 +641,10 @@ def bench_serve(ctx, small, fact_dt, star, threads, log, seconds, server_cfg=Non
             str(k): {"requests": len(v), "p50_ms": percentile(sorted(v), 50),
                      "p99_ms": percentile(sorted(v), 99)}
             for k, v in sorted(by_big.items())},
+        "by_pushdown": {
+            k: {"requests": len(v), "p50_ms": percentile(sorted(v), 50),
+                "p99_ms": percentile(sorted(v), 99)}
+            for k, v in sorted(by_pd.items())},
         "shared_rounds": stats["shared_rounds"],
         "max_admitted": stats["max_admitted"],
         "results_equal_alone": True,
