@@ -103,6 +103,47 @@ def test_mask_lane_patterns(sel, ctx):
         check_tree(sel, ctx, dt, orc, tree)
 
 
+def test_mask_sparse_lane_patterns(sel, ctx):
+    """Row-id materialisation of tiles where no lane holds more than two TRUE
+    rows (the compaction places them by walking each lane's set bits): one
+    row per lane at a step and position that vary with the lane, two rows of
+    one lane in the same 4-row group, two rows in different steps, and tiles
+    where one lane holds three rows (the general path) beside lanes with
+    one; the patterns alternate with empty and full tiles, on a ragged
+    table."""
+    n = 2048 * 29 + 1311
+    r = np.arange(n, dtype=np.int64)
+    lane, step, i = (r % 256) // 4, (r % 2048) // 256, r % 4
+    tmod = (r // 2048) % 4
+    l8 = lane % 8
+    t = datagen.Table("sparse_lanes", n)
+    cols = {
+        "one": (step == l8) & (i == lane % 4),
+        "same_group": (step == l8) & ((i == 1) | (i == 3)),
+        "two_steps": (i == 0) & ((step == l8) | (step == (l8 + 3) % 8)),
+        "three": ((lane == 5) & (step < 3) & (i == 0)) | ((lane != 5) & (step == 2) & (i == 1)),
+        "tmod": tmod,
+    }
+    for name, v in cols.items():
+        t.columns.append(datagen.Column(name, "i8", v.astype(np.int8)))
+    dt = sel.device_table(ctx, t)
+    orc = oracle.Oracle(t)
+    trees = [
+        ("cmp", 0, "=", 1),
+        ("cmp", 1, "=", 1),
+        ("cmp", 2, "=", 1),
+        ("cmp", 3, "=", 1),
+        ("or", ("and", ("cmp", 4, "=", 0), ("cmp", 1, "=", 1)),
+               ("and", ("cmp", 4, "=", 1), ("cmp", 3, "=", 1)),
+               ("and", ("cmp", 4, "=", 2), ("cmp", 2, "=", 1)),
+               ("and", ("cmp", 4, "=", 3), ("cmp", 0, "=", 0))),
+        ("and", ("cmp", 4, "<>", 1), ("or", ("cmp", 0, "=", 1), ("cmp", 2, "=", 1))),
+    ]
+    for tree in trees:
+        say(f"sparse lane pattern {tree}")
+        check_tree(sel, ctx, dt, orc, tree)
+
+
 def test_random_programs_small_ranges(sel, ctx):
     """Values in a small range so that comparisons split rows evenly."""
     rng = np.random.default_rng(77)
