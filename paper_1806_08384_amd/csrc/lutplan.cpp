@@ -146,7 +146,6 @@ struct Form {
   uint32_t ncross = 0;                        // clauses over several columns
   bool always_false = false;
   const sel_program* prog = nullptr;
-  uint32_t acc = 0;
 };
 
 bool make_form(const sel_program* p, Form& f) {
@@ -188,6 +187,22 @@ bool make_form(const sel_program* p, Form& f) {
   }
   return word_bits(f.ncross + 1) != 0;
 }
+
+// The program's form, made once and shared by every plan that takes the
+// program (plans are built on several threads: the caller's and a server's).
+const Form* form_of(const sel_program* p) {
+  std::call_once(p->lut_once, [p] {
+    auto f = std::make_shared<Form>();
+    if (make_form(p, *f)) p->lut_form = std::move(f);
+  });
+  return static_cast<const Form*>(p->lut_form.get());
+}
+
+// A program of one plan: its form and its place in the caller's list.
+struct FormRef {
+  const Form* f;
+  uint32_t acc;
+};
 
 void type_range(uint32_t ty, int64_t& lo, int64_t& hi) {
   switch (ty) {
@@ -336,28 +351,27 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
   std::vector<uint32_t> rejected;
   if (row_end <= row_begin || n == 0) return rejected;
   const uint64_t tiles = (row_end - row_begin + kTileRows - 1) / kTileRows;
-  std::vector<Form> forms;
+  std::vector<FormRef> forms;
   forms.reserve(n);
   for (uint32_t i = 0; i < n; ++i) {
-    Form f;
-    if (!make_form(prg[i], f)) {
+    const Form* f = form_of(prg[i]);
+    if (!f) {
       rejected.push_back(i);
       continue;
     }
-    f.acc = i;
-    forms.push_back(std::move(f));
+    forms.push_back(FormRef{f, i});
   }
   // programs that read the same columns share passes: order by column set
   std::vector<std::vector<uintptr_t>> key(forms.size());
   for (size_t i = 0; i < forms.size(); ++i) {
-    for (const auto& cs : forms[i].cols)
+    for (const auto& cs : forms[i].f->cols)
       for (uintptr_t k : cs)
         if (std::find(key[i].begin(), key[i].end(), k) == key[i].end()) key[i].push_back(k);
     std::sort(key[i].begin(), key[i].end());
   }
   std::map<uintptr_t, uint32_t> slots;
-  for (const Form& f : forms)
-    for (const auto& kv : f.slots) slots[kv.first] = std::max(slots[kv.first], kv.second);
+  for (const FormRef& r : forms)
+    for (const auto& kv : r.f->slots) slots[kv.first] = std::max(slots[kv.first], kv.second);
   auto slots_of = [&](const std::set<uintptr_t>& cs) {
     uint32_t n = 0;
     for (uintptr_t k : cs) n += slots[k];
@@ -368,13 +382,13 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
 
   // a pass's programs, then its columns, bits and tables
-  auto emit = [&](std::vector<const Form*> ps) -> bool {
+  auto emit = [&](std::vector<const FormRef*> ps) -> bool {
     // programs by word count: the pass's dwords take them in this order
     std::stable_sort(ps.begin(), ps.end(),
-                     [](const Form* x, const Form* y) { return x->ncross < y->ncross; });
+                     [](const FormRef* x, const FormRef* y) { return x->f->ncross < y->f->ncross; });
     const uint32_t P = (uint32_t)ps.size();
     std::vector<uint32_t> Ws;
-    for (const Form* f : ps) Ws.push_back(1 + f->ncross);
+    for (const FormRef* r : ps) Ws.push_back(1 + r->f->ncross);
     const std::vector<DwordGroup> groups = pack_dwords(Ws);
     const uint32_t B = bits_for(P), D = dwords_for(Ws);
     if (D == 0) return false;
@@ -400,7 +414,7 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
       return c;
     };
     for (uint32_t j = 0; j < P; ++j) {
-      const Form& f = *ps[j];
+      const Form& f = *ps[j]->f;
       uint32_t cross = 0;
       for (size_t ci = 0; ci < f.clauses.size(); ++ci) {
         const Clause& cl = f.clauses[ci];
@@ -477,8 +491,8 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
         e.fold[d] = b | (groups[d].count << 8) | (j << 16);
         uint32_t init = ~0u;
         for (uint32_t g = 0; g < groups[d].count; ++g, ++j) {
-          if (!ps[j]->always_false) init &= ~(1u << g);
-          for (uint32_t k = 1; k <= ps[j]->ncross; ++k) init &= ~(1u << (k * b + g));
+          if (!ps[j]->f->always_false) init &= ~(1u << g);
+          for (uint32_t k = 1; k <= ps[j]->f->ncross; ++k) init &= ~(1u << (k * b + g));
         }
         e.init[d] = init;
       }
@@ -551,29 +565,30 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
     }
     e.lds_words = lw;
     max_lds_words = std::max(max_lds_words, lw);
-    for (const Form* f : ps) acc_index.push_back(acc[f->acc]);
+    for (const FormRef* r : ps) acc_index.push_back(acc[r->acc]);
     passes.push_back(e);
     total_tiles += (tiles + kLutTileAlign - 1) / kLutTileAlign * kLutTileAlign;
     return true;
   };
   // greedy packing; a pass that cannot be placed sends its programs back
-  std::vector<const Form*> cur;
+  std::vector<const FormRef*> cur;
   std::set<uintptr_t> cur_cols;
   auto flush = [&]() {
     if (cur.empty()) return;
     // emit checks everything before it appends anything
     if (!emit(cur))
-      for (const Form* f : cur) rejected.push_back(f->acc);
+      for (const FormRef* r : cur) rejected.push_back(r->acc);
     cur.clear();
     cur_cols.clear();
   };
   for (size_t oi : order) {
-    const Form& f = forms[oi];
+    const FormRef& r = forms[oi];
+    const Form& f = *r.f;
     std::set<uintptr_t> cs = cur_cols;
     for (const auto& c : f.cols) cs.insert(c.begin(), c.end());
     const uint32_t P = (uint32_t)cur.size() + 1;
     std::vector<uint32_t> Ws;
-    for (const Form* g : cur) Ws.push_back(1 + g->ncross);
+    for (const FormRef* g : cur) Ws.push_back(1 + g->f->ncross);
     Ws.push_back(1 + f.ncross);
     if (!cur.empty() && (P > kMaxPassProgs || dwords_for(Ws) == 0 || cs.size() > kMaxPassCols ||
                          slots_of(cs) > kLutSlots)) {
@@ -581,7 +596,7 @@ std::vector<uint32_t> LutPlan::add(const sel_table* t, uint64_t row_begin, uint6
       cs.clear();
       for (const auto& c : f.cols) cs.insert(c.begin(), c.end());
     }
-    cur.push_back(&f);
+    cur.push_back(&r);
     cur_cols = cs;
   }
   flush();

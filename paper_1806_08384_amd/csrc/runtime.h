@@ -6,6 +6,8 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -143,6 +145,11 @@ struct sel_program {
   int depth = 0;
   double bytes_per_row = 0.0;
   std::string text;
+  // the batched count's conjunctive form of the program (for the lookup-
+  // table kernel), made on first use and kept: a program does not change
+  // after its compile.  Null when the program has none.
+  mutable std::once_flag lut_once;
+  mutable std::shared_ptr<const void> lut_form;
 };
 
 namespace selrt {
