@@ -21,7 +21,6 @@
 #include <map>
 #include <mutex>
 #include <new>
-#include <set>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -246,14 +245,20 @@ bool wait_oldest(sel_server* s) {
 
 // Bytes per row the programs read together: the element size of every
 // column one of them tests, plus 1/8 for every validity bitmap one reads.
+// (A table has few columns: the sets are short vectors searched linearly.)
 double union_bytes_per_row(const std::vector<const sel_program*>& ps) {
-  std::set<const void*> data, valid;
+  std::vector<const void*> data, valid;
+  auto first_time = [](std::vector<const void*>& seen, const void* x) {
+    if (std::find(seen.begin(), seen.end(), x) != seen.end()) return false;
+    seen.push_back(x);
+    return true;
+  };
   double b = 0;
   for (const sel_program* p : ps)
     for (const DevInstr& I : p->host_code) {
       const bool value = I.op == D_RANGE || I.op == D_BITMAP || I.op == D_INLIST;
-      if (value && I.data && data.insert(I.data).second) b += type_bytes(I.type);
-      if ((value || (I.op >= D_NN_TRUE && I.op <= D_NOTNULL)) && I.valid && valid.insert(I.valid).second)
+      if (value && I.data && first_time(data, I.data)) b += type_bytes(I.type);
+      if ((value || (I.op >= D_NN_TRUE && I.op <= D_NOTNULL)) && I.valid && first_time(valid, I.valid))
         b += 1.0 / 8.0;
     }
   return b;
